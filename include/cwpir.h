@@ -1,0 +1,160 @@
+/*
+ * cwpir.h — C ABI of the MI355X (gfx950) server path of constant-weight PIR
+ * (Mahdavi and Kerschbaum, "Constant-weight PIR: Single-round Keyword PIR via Constant-weight
+ * Equality Operators", arXiv 2202.07569).
+ *
+ * The calls follow the protocol's stages (Section 3.3, table "Stages of PIR using constant-weight
+ * codewords"): Setup (pir_setup, pir_load_key, pir_encode_db: choose parameters and put the
+ * database in plaintext form with its precomputed codewords) and Process (pir_answer,
+ * pir_answer_batch: selection vector by the plain constant-weight equality operator, Section 3.1
+ * and Algorithm 6, followed by the inner product with the database, Section 2.3 Eq. (1) and the
+ * "Inner Product" step of Section 3.3.3).  Query construction, key generation and decryption
+ * are client-side and are not in this library.
+ *
+ * Arithmetic.  FV over R_q = Z_q[x]/(x^N+1), q = q_0 ... q_{L-1} (every listed prime is a
+ * ciphertext prime), plaintext modulus t (Section 2.1.1).  All results are exact integers and are
+ * bit-identical to the textbook definitions:
+ *   Mult   c_r = round(t * X_r / q) mod q, X = centred lifts multiplied over Z[x]/(x^N+1);
+ *   Relin  per-limb digits D_i = [c2]_{q_i} in [0, q_i):  (c0 + sum_i D_i b_i, c1 + sum_i D_i a_i);
+ *   PM     plaintext coefficients in [0, t) taken as they are;
+ *   selector of element j: product of the query ciphertexts at j's ascending one positions
+ *          p_1 < ... < p_k, as the tree ((p1 p2)(p3 p4)) with an odd last factor carried up and a
+ *          relinearization after every Mult; k = 1 gives the query ciphertext itself;
+ *   answer_r = sum_j PM(sel_j, P_{j,r}) mod q  for r in [s].
+ *
+ * Layouts (all little-endian uint64 residues in [0, q_i) unless stated):
+ *   polynomial limb   N residues in coefficient order
+ *   ciphertext        [2][L][N]              (c0 limbs, then c1 limbs)
+ *   query             [m][2][L][N]           one ciphertext per codeword bit (compression c = 0)
+ *   relin key         [L digits][2][L][N]    digit i holds (b_i, a_i)
+ *   payload           uint16 [n][s][N]       coefficients in [0, 2^16) (< t = 65537)
+ *   codewords         uint32 [n][k]          strictly ascending positions in [0, m)
+ *   answer            [s][2][L][N]
+ *
+ * Ownership.  The caller owns every buffer it passes.  "dev" pointers are device memory of the
+ * context's device (allocated by the caller, e.g. through PyTorch); "host" pointers are host
+ * memory.  The library owns its internal copies (encoded database, transformed keys, work buffers)
+ * and releases them in the matching *_free call.  Asynchronous calls enqueue work on the given HIP
+ * stream (NULL = the default stream) and return before it runs: their inputs must stay alive and
+ * unmodified, and their outputs unread, until the stream has completed the work.
+ *
+ * Errors.  Every int-returning call returns PIR_OK (0) or a negative code; pir_last_error()
+ * returns a message for the calling thread's last failure.  No C++ exception crosses the ABI.
+ * A HIP error inside a call returns PIR_E_DEVICE and poisons the context: later calls on it
+ * return PIR_E_DEVICE.
+ *
+ * Concurrency.  Calls on one context are serialised by a lock; the context's work buffers are
+ * shared, so two answers in flight on different streams of the same context are ordered by the
+ * library (it waits for the previous call's stream before reusing them).
+ */
+#ifndef CWPIR_H
+#define CWPIR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PIR_OK 0
+#define PIR_E_INVALID (-1)     /* bad shape or parameter, residue >= q_i, bad codeword          */
+#define PIR_E_NOMEM (-2)       /* allocation failed or the HBM budget is exceeded               */
+#define PIR_E_DEVICE (-3)      /* HIP runtime error; the context is poisoned                    */
+#define PIR_E_BUSY (-4)        /* no free serving slot                                          */
+#define PIR_E_UNSUPPORTED (-5) /* N not in {4096, 8192, 16384}, L or k out of range             */
+
+#define PIR_MAX_L 12           /* ciphertext primes */
+#define PIR_MAX_K 4            /* Hamming weight of the codewords (tree depth <= 2) */
+
+typedef struct pir_ctx pir_ctx;
+typedef struct pir_key pir_key;
+typedef struct pir_db pir_db;
+
+typedef struct {
+    uint32_t N;                /* ring degree: 4096, 8192 or 16384                                */
+    uint32_t L;                /* number of ciphertext primes, 1..PIR_MAX_L                       */
+    const uint64_t* q;         /* host [L]: distinct primes, each = 1 mod 2N and < 2^61           */
+    uint64_t t;                /* plaintext modulus, 2 <= t < 2^32, coprime to q                  */
+    uint64_t hbm_budget_bytes; /* cap on the library's own device allocations; 0 = no cap         */
+    int32_t device;            /* HIP device ordinal                                              */
+    uint32_t chunk_elems;      /* elements per processing chunk, 1..4096; 0 = default by N        */
+    uint64_t memo_bytes;       /* cap on HBM for level-1 products shared by a whole database
+                                  (k >= 3); above it they are shared within a chunk only;
+                                  0 = default (a quarter of the budget, else 8 GiB)               */
+} pir_params;
+
+/* Setup (Section 3.3.1): validate the parameters and build the per-prime transform tables and the
+ * exact base-conversion constants on `device`.  *out receives the context.  Synchronous. */
+int pir_setup(const pir_params* params, pir_ctx** out);
+
+/* Setup: load a relinearization key rlk (host or dev [L][2][L][N], coefficient form; see
+ * "Relin" above) into the library's transformed representation.  Synchronous. */
+int pir_load_key(pir_ctx* ctx, const uint64_t* rlk, pir_key** out);
+
+/* Setup (Section 3.3.1, "Put DB in plaintext format"; codewords precomputed there as well):
+ * copy n elements of s plaintexts each, with their weight-k codewords of length m, into the
+ * library's device memory and precompute the selection-vector schedule (shared level-1 products
+ * for k >= 3).  codewords: host [n][k]; payload: host or dev uint16 [n][s][N].  Synchronous. */
+int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, uint32_t k, const uint32_t* codewords,
+                  const uint16_t* payload, pir_db** out);
+
+/* Process (Section 3.3.3: selection vector, Algorithm 6, then s inner products with the
+ * database, Eq. (1)): answer = [s][2][L][N] for the query [m][2][L][N].  query and answer are dev
+ * pointers; asynchronous on `stream` (a hipStream_t).  The query residues are not range-checked
+ * (the library never reads them on the host). */
+int pir_answer(pir_ctx* ctx, const pir_key* key, const pir_db* db, const uint64_t* query, uint64_t* answer,
+               void* stream);
+
+/* Process B queries in one call: the query ciphertexts' selection trees run side by side and
+ * queries on the same database share one scan of its payload.  keys[b], dbs[b], queries[b],
+ * answers[b] are as in pir_answer.  Every answer is bit-identical to pir_answer's.  Asynchronous. */
+int pir_answer_batch(pir_ctx* ctx, uint32_t B, const pir_key* const* keys, const pir_db* const* dbs,
+                     const uint64_t* const* queries, uint64_t* const* answers, void* stream);
+
+/* FV operations on single ciphertexts (Section 2.1.1: Multiplication, Plain multiplication), the
+ * building blocks of the path, exposed for checking.  All pointers dev; asynchronous.
+ *   pir_mult      a, b [2][L][N] -> out [3][L][N]    (textbook Mult, no relinearization)
+ *   pir_relin     in [3][L][N]   -> out [2][L][N]
+ *   pir_pm        ct [2][L][N], uint16 pt [N] -> out [2][L][N]                                */
+int pir_mult(pir_ctx* ctx, const uint64_t* a, const uint64_t* b, uint64_t* out, void* stream);
+int pir_relin(pir_ctx* ctx, const pir_key* key, const uint64_t* in, uint64_t* out, void* stream);
+int pir_pm(pir_ctx* ctx, const uint64_t* ct, const uint16_t* pt, uint64_t* out, void* stream);
+
+/* Selectors of chosen elements (Algorithm 6 for a subset of identifiers): out [count][2][L][N]
+ * holds sel_j for j = elems[0..count) (host uint64 indices < n), coefficient form.  dev query/out;
+ * synchronous (returns after the selectors are written). */
+int pir_selectors(pir_ctx* ctx, const pir_key* key, const pir_db* db, const uint64_t* query,
+                  const uint64_t* elems, uint32_t count, uint64_t* out, void* stream);
+
+/* Codeword tables (Section 3.2 and the appendix on mappings), computed on the device.
+ *   pir_map_perfect  Algorithm 3: ids (dev uint64 [n], each < C(m,k)) -> dev uint32 [n][k]
+ *   pir_map_lossy    Algorithm 8 with H_i(x) = SplitMix64-mix(seed ^ x ^ i*0x9E3779B97F4A7C15)
+ *                    mod m, i = 1, 2, ...: keywords (dev uint64 [n]) -> dev uint32 [n][k]
+ * Positions are written ascending.  Asynchronous; m <= 65535, 1 <= k <= 16. */
+int pir_map_perfect(pir_ctx* ctx, const uint64_t* ids, uint64_t n, uint32_t m, uint32_t k, uint32_t* out,
+                    void* stream);
+int pir_map_lossy(pir_ctx* ctx, const uint64_t* keywords, uint64_t n, uint32_t m, uint32_t k, uint64_t seed,
+                  uint32_t* out, void* stream);
+
+/* Introspection. */
+uint32_t pir_ctx_aux_primes(const pir_ctx* ctx, uint64_t* out_primes /* may be NULL */);
+uint64_t pir_ctx_device_bytes(const pir_ctx* ctx);       /* bytes the library holds on the device */
+uint64_t pir_db_pair_count(const pir_db* db);            /* distinct level-1 products (k >= 3)    */
+
+/* Kernel timing with HIP events on the launching stream.  When enabled, every launch is bracketed
+ * by events; pir_profile_read synchronises on them and returns, per kernel family, the summed
+ * milliseconds and launch counts (names are static strings).  Returns the number of families. */
+int pir_profile_enable(pir_ctx* ctx, int on);
+int pir_profile_read(pir_ctx* ctx, uint32_t max, const char** names, double* total_ms, uint64_t* launches,
+                     int reset);
+
+void pir_db_free(pir_db* db);
+void pir_key_free(pir_key* key);
+void pir_free(pir_ctx* ctx);
+const char* pir_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CWPIR_H */

@@ -1,0 +1,299 @@
+"""Python binding of libcwpir (include/cwpir.h): argument marshalling only.
+
+Every step of the path runs in the library's HIP kernels.  PyTorch supplies device memory and
+streams: device buffers are torch tensors on the context's device (uint64 residues, uint16
+payloads), and asynchronous calls run on torch's current stream unless one is given.  There is
+no CPU fallback: without the built library or a GPU every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from . import build as _build
+
+PIR_OK, PIR_E_INVALID, PIR_E_NOMEM, PIR_E_DEVICE, PIR_E_BUSY, PIR_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+
+EXPORTS = [
+    "pir_setup", "pir_load_key", "pir_encode_db", "pir_answer", "pir_answer_batch", "pir_mult", "pir_relin",
+    "pir_pm", "pir_selectors", "pir_map_perfect", "pir_map_lossy", "pir_ctx_aux_primes", "pir_ctx_device_bytes",
+    "pir_db_pair_count", "pir_profile_enable", "pir_profile_read", "pir_db_free", "pir_key_free", "pir_free",
+    "pir_last_error",
+]
+
+
+class PirError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"cwpir error {code}: {msg}")
+        self.code = code
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("N", ctypes.c_uint32), ("L", ctypes.c_uint32), ("q", ctypes.POINTER(ctypes.c_uint64)),
+                ("t", ctypes.c_uint64), ("hbm_budget_bytes", ctypes.c_uint64), ("device", ctypes.c_int32),
+                ("chunk_elems", ctypes.c_uint32), ("memo_bytes", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _build.LIB
+
+
+def lib():
+    """Load the built library (building it first only when nothing is built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_build.LIB):
+            _build.build()
+        L = ctypes.CDLL(_build.LIB)
+        vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+        pp = ctypes.POINTER(ctypes.c_void_p)
+        sig = {
+            "pir_setup": (i32, [ctypes.POINTER(_Params), pp]),
+            "pir_load_key": (i32, [vp, vp, pp]),
+            "pir_encode_db": (i32, [vp, u64, u32, u32, u32, vp, vp, pp]),
+            "pir_answer": (i32, [vp, vp, vp, vp, vp, vp]),
+            "pir_answer_batch": (i32, [vp, u32, pp, pp, pp, pp, vp]),
+            "pir_mult": (i32, [vp, vp, vp, vp, vp]),
+            "pir_relin": (i32, [vp, vp, vp, vp, vp]),
+            "pir_pm": (i32, [vp, vp, vp, vp, vp]),
+            "pir_selectors": (i32, [vp, vp, vp, vp, vp, u32, vp, vp]),
+            "pir_map_perfect": (i32, [vp, vp, u64, u32, u32, vp, vp]),
+            "pir_map_lossy": (i32, [vp, vp, u64, u32, u32, u64, vp, vp]),
+            "pir_ctx_aux_primes": (u32, [vp, vp]),
+            "pir_ctx_device_bytes": (u64, [vp]),
+            "pir_db_pair_count": (u64, [vp]),
+            "pir_profile_enable": (i32, [vp, i32]),
+            "pir_profile_read": (i32, [vp, u32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_uint64), i32]),
+            "pir_db_free": (None, [vp]),
+            "pir_key_free": (None, [vp]),
+            "pir_free": (None, [vp]),
+            "pir_last_error": (ctypes.c_char_p, []),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != PIR_OK:
+        raise PirError(rc, lib().pir_last_error().decode())
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    if stream is None:
+        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _dev_u64(x, device):
+    torch = _torch()
+    if isinstance(x, np.ndarray):
+        x = torch.from_numpy(np.ascontiguousarray(x, dtype=np.uint64))
+    if x.dtype != torch.uint64:
+        raise TypeError("expected uint64 residues")
+    x = x.to(device).contiguous()
+    return x
+
+
+def _ptr(t) -> ctypes.c_void_p:
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Key:
+    def __init__(self, ctx: "Context", handle):
+        self.ctx, self._h = ctx, handle
+
+    def close(self):
+        if self._h:
+            lib().pir_key_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Database:
+    def __init__(self, ctx: "Context", handle, n, s, m, k):
+        self.ctx, self._h = ctx, handle
+        self.n, self.s, self.m, self.k = n, s, m, k
+
+    @property
+    def pair_count(self) -> int:
+        return lib().pir_db_pair_count(self._h)
+
+    def close(self):
+        if self._h:
+            lib().pir_db_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Context:
+    """One FV parameter set on one device (pir_setup)."""
+
+    def __init__(self, N: int, primes, t: int = 65537, hbm_budget_bytes: int = 0, device: int = 0,
+                 chunk_elems: int = 0, memo_bytes: int = 0):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise PirError(PIR_E_DEVICE, "no GPU visible to torch")
+        self.N, self.t, self.primes = int(N), int(t), tuple(int(p) for p in primes)
+        self.L = len(self.primes)
+        self.device = torch.device("cuda", device)
+        q = (ctypes.c_uint64 * self.L)(*self.primes)
+        p = _Params(self.N, self.L, q, self.t, hbm_budget_bytes, device, chunk_elems, memo_bytes)
+        h = ctypes.c_void_p()
+        _check(lib().pir_setup(ctypes.byref(p), ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pir_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def aux_primes(self) -> tuple:
+        n = lib().pir_ctx_aux_primes(self._h, None)
+        out = (ctypes.c_uint64 * n)()
+        lib().pir_ctx_aux_primes(self._h, out)
+        return tuple(out)
+
+    @property
+    def device_bytes(self) -> int:
+        return lib().pir_ctx_device_bytes(self._h)
+
+    def empty(self, *shape, dtype=None):
+        torch = _torch()
+        return torch.empty(shape, dtype=dtype or torch.uint64, device=self.device)
+
+    # ---- Setup ----
+    def load_key(self, rlk) -> Key:
+        rlk = _dev_u64(rlk, self.device)
+        assert tuple(rlk.shape) == (self.L, 2, self.L, self.N)
+        h = ctypes.c_void_p()
+        _check(lib().pir_load_key(self._h, _ptr(rlk), ctypes.byref(h)))
+        return Key(self, h)
+
+    def encode_db(self, codewords: np.ndarray, payload, m: int) -> Database:
+        torch = _torch()
+        cw = np.ascontiguousarray(codewords, dtype=np.uint32)
+        n, k = cw.shape
+        if isinstance(payload, np.ndarray):
+            payload = torch.from_numpy(np.ascontiguousarray(payload, dtype=np.uint16))
+        payload = payload.contiguous()
+        assert payload.dtype == torch.uint16 and payload.shape[0] == n and payload.shape[2] == self.N
+        s = payload.shape[1]
+        h = ctypes.c_void_p()
+        _check(lib().pir_encode_db(self._h, n, s, m, k, cw.ctypes.data_as(ctypes.c_void_p),
+                                   ctypes.c_void_p(payload.data_ptr()) if n else None, ctypes.byref(h)))
+        return Database(self, h, n, s, m, k)
+
+    # ---- Process ----
+    def answer(self, key: Key, db: Database, query, out=None, stream=None):
+        query = _dev_u64(query, self.device)
+        assert tuple(query.shape) == (db.m, 2, self.L, self.N)
+        if out is None:
+            out = self.empty(db.s, 2, self.L, self.N)
+        _check(lib().pir_answer(self._h, key._h, db._h, _ptr(query), _ptr(out), _stream(stream)))
+        return out
+
+    def answer_batch(self, keys, dbs, queries, outs=None, stream=None):
+        B = len(queries)
+        queries = [_dev_u64(q, self.device) for q in queries]
+        if outs is None:
+            outs = [self.empty(db.s, 2, self.L, self.N) for db in dbs]
+        arr = lambda xs: (ctypes.c_void_p * B)(*xs)  # noqa: E731
+        _check(lib().pir_answer_batch(self._h, B, arr([k._h.value for k in keys]), arr([d._h.value for d in dbs]),
+                                      arr([q.data_ptr() for q in queries]), arr([o.data_ptr() for o in outs]),
+                                      _stream(stream)))
+        return outs
+
+    def selectors(self, key: Key, db: Database, query, elems, out=None, stream=None):
+        query = _dev_u64(query, self.device)
+        el = np.ascontiguousarray(elems, dtype=np.uint64)
+        if out is None:
+            out = self.empty(len(el), 2, self.L, self.N)
+        _check(lib().pir_selectors(self._h, key._h, db._h, _ptr(query), el.ctypes.data_as(ctypes.c_void_p), len(el),
+                                   _ptr(out), _stream(stream)))
+        return out
+
+    def mult(self, a, b, stream=None):
+        a, b = _dev_u64(a, self.device), _dev_u64(b, self.device)
+        out = self.empty(3, self.L, self.N)
+        _check(lib().pir_mult(self._h, _ptr(a), _ptr(b), _ptr(out), _stream(stream)))
+        return out
+
+    def relin(self, key: Key, c3, stream=None):
+        c3 = _dev_u64(c3, self.device)
+        out = self.empty(2, self.L, self.N)
+        _check(lib().pir_relin(self._h, key._h, _ptr(c3), _ptr(out), _stream(stream)))
+        return out
+
+    def pm(self, ct, pt, stream=None):
+        torch = _torch()
+        ct = _dev_u64(ct, self.device)
+        if isinstance(pt, np.ndarray):
+            pt = torch.from_numpy(np.ascontiguousarray(pt, dtype=np.uint16))
+        pt = pt.to(self.device).contiguous()
+        out = self.empty(2, self.L, self.N)
+        _check(lib().pir_pm(self._h, _ptr(ct), _ptr(pt), _ptr(out), _stream(stream)))
+        return out
+
+    # ---- codeword tables ----
+    def map_perfect(self, ids, m: int, k: int, stream=None):
+        torch = _torch()
+        ids = _dev_u64(np.asarray(ids, dtype=np.uint64), self.device)
+        out = torch.empty((ids.shape[0], k), dtype=torch.uint32, device=self.device)
+        _check(lib().pir_map_perfect(self._h, _ptr(ids), ids.shape[0], m, k, _ptr(out), _stream(stream)))
+        return out
+
+    def map_lossy(self, keywords, m: int, k: int, seed: int, stream=None):
+        torch = _torch()
+        kw = _dev_u64(np.asarray(keywords, dtype=np.uint64), self.device)
+        out = torch.empty((kw.shape[0], k), dtype=torch.uint32, device=self.device)
+        _check(lib().pir_map_lossy(self._h, _ptr(kw), kw.shape[0], m, k, seed, _ptr(out), _stream(stream)))
+        return out
+
+    # ---- profiling ----
+    def profile(self, on: bool = True):
+        _check(lib().pir_profile_enable(self._h, 1 if on else 0))
+
+    def profile_read(self, reset: bool = True) -> dict:
+        cap = 64
+        names = (ctypes.c_char_p * cap)()
+        ms = (ctypes.c_double * cap)()
+        cnt = (ctypes.c_uint64 * cap)()
+        n = lib().pir_profile_read(self._h, cap, names, ms, cnt, 1 if reset else 0)
+        if n < 0:
+            _check(n)
+        return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(min(n, cap))}

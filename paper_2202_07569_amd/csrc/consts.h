@@ -1,0 +1,53 @@
+// Constant tables of one parameter set, laid out identically for the host builder and the kernels.
+//
+// Primes are indexed Q first (the ciphertext primes q_0..q_{L-1}) and then B (the auxiliary primes
+// b_0..b_{LB-1}, chosen by the library).  Q*B must hold every exact tensor product X of two centred
+// ciphertext polynomials (|X| < N q^2 / 2) and B must hold every rounded result round(t X / q)
+// (|y| < t N q / 2 + 1), so B > 4 t N q is required.
+#pragma once
+#include <stdint.h>
+
+namespace cw {
+
+constexpr int MAX_L = 12;            // ciphertext primes
+constexpr int MAX_LB = 13;           // auxiliary primes
+constexpr int MAX_LL = MAX_L + MAX_LB;
+constexpr int MAX_CONV = MAX_LB;     // >= max(MAX_L, MAX_LB)
+constexpr int MAX_W = 14;            // 64-bit words of a basis product, plus two spare words
+
+// Exact centred conversion from basis P = {p_i} to basis R = {r_j}.  For x with residues x_i:
+//   y_i = [x_i (P/p_i)^{-1}]_{p_i} (the caller may fold a factor into this constant),
+//   v   = round(sum_i y_i / p_i)   (fraction sum in 0.64 fixed point, exact fallback near 1/2),
+//   [x]_centred mod r_j = sum_i y_i [(P/p_i) mod r_j] - v [P mod r_j].
+struct ConvTable {
+    uint32_t nin, nout, W, pad;
+    uint64_t pin[MAX_CONV];
+    uint64_t om_hi[MAX_CONV], om_lo[MAX_CONV];   // floor(2^128 / p_i) = om_hi 2^64 + om_lo
+    uint64_t pout[MAX_CONV];
+    uint64_t M[MAX_CONV][MAX_CONV];              // (P/p_i) mod r_j
+    uint64_t Mq[MAX_CONV][MAX_CONV];             // Shoup companions
+    uint64_t Pm[MAX_CONV], Pmq[MAX_CONV];        // P mod r_j
+    uint64_t Pw[MAX_W];                          // P, little-endian words
+    uint64_t Phat[MAX_CONV][MAX_W];              // P / p_i
+};
+
+struct CtxConst {
+    uint32_t N, logN, L, LB, LL, pad;
+    uint64_t t;
+    uint64_t p[MAX_LL];
+    uint64_t bar_mu[MAX_LL];                     // floor(2^(2s) / p), s = bit length of p
+    uint32_t bar_s[MAX_LL];
+    uint64_t r1[MAX_LL];                         // floor(2^64 / p)
+    uint64_t ninv[MAX_LL], ninvq[MAX_LL];        // N^{-1} mod p
+    uint64_t qinv[MAX_L], qinvq[MAX_L];          // [(q/q_i)^{-1}]_{q_i}
+    uint64_t tqinv[MAX_L], tqinvq[MAX_L];        // [t (q/q_i)^{-1}]_{q_i}
+    uint64_t kb1[MAX_LB], kb1q[MAX_LB];          // [t q^{-1} (B/b_j)^{-1}]_{b_j}
+    uint64_t kb2[MAX_LB], kb2q[MAX_LB];          // [q^{-1} (B/b_j)^{-1}]_{b_j}
+    ConvTable qb;                                // q -> B
+    ConvTable bq;                                // B -> q
+};
+
+// Operand reference of a tree node: a query ciphertext (leaf) or a level-1 product (node).
+constexpr uint32_t REF_NODE = 0x80000000u;
+
+}  // namespace cw

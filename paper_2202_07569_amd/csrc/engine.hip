@@ -1,0 +1,855 @@
+// Host engine and C ABI (include/cwpir.h) of the constant-weight PIR server path on gfx950.
+//
+// One answer (Section 3.3.3) runs as:
+//   1. query residency: every query ciphertext is extended exactly from Q to Q u B and
+//      transformed (once per query);
+//   2. per group of elements: the distinct level-1 products of the group (k >= 3) are computed
+//      once — Mult + Relin, then extended and transformed again — and kept in HBM;
+//   3. per chunk of E elements: the root Mult + Relin of each element's tree gives its selector
+//      (transformed over Q); the chunk's payload rows are lifted and transformed once and
+//      multiplied into the accumulators of every query scanning this database;
+//   4. the accumulators are transformed back into the answer ciphertexts.
+// Everything is enqueued on the caller's stream; work buffers are owned by the context.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <set>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/cwpir.h"
+#include "host_params.h"
+#include "kernels.h"
+
+using cw::CtxConst;
+using cw::Launch;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string& msg) {
+    g_err = msg;
+    return code;
+}
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+struct ProfRec {
+    const char* name;
+    hipEvent_t a, b;
+};
+
+struct pir_ctx {
+    int device = 0;
+    uint32_t N = 0, logN = 0, L = 0, LB = 0, LL = 0;
+    uint64_t t = 0;
+    std::vector<uint64_t> primes;  // Q then B
+    CtxConst K;
+    CtxConst* dK = nullptr;
+    uint64_t* dtw = nullptr;
+    uint64_t budget = 0, held = 0;
+    bool poisoned = false;
+    std::recursive_mutex mu;
+    uint64_t* dfix = nullptr;
+    uint32_t* dfixcnt = nullptr;
+    size_t fix_cap = 0;
+    uint32_t chunk = 0;  // elements per chunk
+    uint64_t memo_cap = 0;
+    std::map<std::string, DevBuf> ws;
+    hipEvent_t done = nullptr;
+    bool prof = false;
+    std::vector<ProfRec> recs;
+    std::map<std::string, std::pair<double, uint64_t>> prof_acc;
+    std::map<std::pair<uint32_t, uint32_t>, uint64_t*> binom;  // (m, k) -> device table
+};
+
+struct pir_key {
+    pir_ctx* ctx = nullptr;
+    uint64_t* d = nullptr;  // [L][2][L][N] transformed, then [L][2][L][N] Shoup companions
+    size_t bytes = 0;
+};
+
+struct Group {
+    uint64_t e0 = 0, ne = 0;   // element range
+    uint32_t p0 = 0, np = 0;   // pair range in the pair table
+};
+
+struct pir_db {
+    pir_ctx* ctx = nullptr;
+    uint64_t n = 0;
+    uint32_t s = 0, m = 0, k = 0;
+    uint16_t* dpay = nullptr;
+    std::vector<uint32_t> cw;    // host codewords [n][k]
+    std::vector<Group> groups;
+    uint32_t* dpairs = nullptr;  // [pairs][2] leaf positions
+    uint32_t* drefs = nullptr;   // [n][2] root operands
+    uint32_t max_pairs = 0;
+    uint64_t total_pairs = 0;
+    size_t pay_bytes = 0, pairs_bytes = 0, refs_bytes = 0;
+};
+
+// ------------------------------------------------------------------------------------------------
+// helpers
+// ------------------------------------------------------------------------------------------------
+#define CW_HIP(ctx, expr)                                                                                \
+    do {                                                                                                 \
+        hipError_t e_ = (expr);                                                                          \
+        if (e_ != hipSuccess) {                                                                          \
+            (ctx)->poisoned = true;                                                                      \
+            return fail(PIR_E_DEVICE, std::string(#expr) + " failed: " + hipGetErrorString(e_));         \
+        }                                                                                                \
+    } while (0)
+
+#define CW_TRY(expr)                \
+    do {                            \
+        int rc_ = (expr);           \
+        if (rc_ != PIR_OK) return rc_; \
+    } while (0)
+
+static int dev_alloc(pir_ctx* ctx, void** p, size_t bytes) {
+    *p = nullptr;
+    if (!bytes) return PIR_OK;
+    if (ctx->budget && ctx->held + bytes > ctx->budget)
+        return fail(PIR_E_NOMEM, "HBM budget exceeded (" + std::to_string(ctx->held + bytes) + " > " +
+                                     std::to_string(ctx->budget) + " bytes)");
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        *p = nullptr;
+        return fail(PIR_E_NOMEM, std::string("hipMalloc failed: ") + hipGetErrorString(e));
+    }
+    ctx->held += bytes;
+    return PIR_OK;
+}
+
+static void dev_free(pir_ctx* ctx, void* p, size_t bytes) {
+    if (!p) return;
+    (void)hipFree(p);
+    ctx->held -= bytes;
+}
+
+// Work buffer `name` of at least `bytes`; growing waits for all queued work first.
+static int ws_get(pir_ctx* ctx, const std::string& name, size_t bytes, void** out) {
+    DevBuf& b = ctx->ws[name];
+    if (b.bytes >= bytes && b.p) {
+        *out = b.p;
+        return PIR_OK;
+    }
+    if (b.p) {
+        CW_HIP(ctx, hipDeviceSynchronize());
+        dev_free(ctx, b.p, b.bytes);
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    CW_TRY(dev_alloc(ctx, &b.p, bytes));
+    b.bytes = bytes;
+    *out = b.p;
+    return PIR_OK;
+}
+
+template <typename T>
+static int ws_get_t(pir_ctx* ctx, const std::string& name, size_t count, T** out) {
+    void* p = nullptr;
+    CW_TRY(ws_get(ctx, name, count * sizeof(T), &p));
+    *out = (T*)p;
+    return PIR_OK;
+}
+
+static Launch make_launch(pir_ctx* ctx, hipStream_t st) {
+    Launch lc;
+    lc.stream = st;
+    lc.K = ctx->dK;
+    lc.tw = ctx->dtw;
+    lc.N = ctx->N;
+    lc.logN = ctx->logN;
+    lc.L = ctx->L;
+    lc.LB = ctx->LB;
+    lc.LL = ctx->LL;
+    lc.fix = ctx->dfix;
+    lc.fixcnt = ctx->dfixcnt;
+    return lc;
+}
+
+// Profiling bracket: events on the launching stream around one kernel family's launch(es).
+struct Prof {
+    pir_ctx* ctx;
+    const char* name;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    Prof(pir_ctx* c, const char* n, hipStream_t s) : ctx(c), name(n), st(s) {
+        if (ctx->prof && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, st);
+    }
+    ~Prof() {
+        if (!a) return;
+        hipEvent_t b = nullptr;
+        if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, st) == hipSuccess) ctx->recs.push_back({name, a, b});
+    }
+};
+
+static int check_launch(pir_ctx* ctx) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        ctx->poisoned = true;
+        return fail(PIR_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+    }
+    return PIR_OK;
+}
+
+// Order this call after the context's previous asynchronous call (possibly on another stream).
+static int begin_async(pir_ctx* ctx, hipStream_t st) {
+    CW_HIP(ctx, hipSetDevice(ctx->device));
+    CW_HIP(ctx, hipStreamWaitEvent(st, ctx->done, 0));
+    return PIR_OK;
+}
+static int end_async(pir_ctx* ctx, hipStream_t st) {
+    CW_TRY(check_launch(ctx));
+    CW_HIP(ctx, hipEventRecord(ctx->done, st));
+    return PIR_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
+// setup
+// ------------------------------------------------------------------------------------------------
+extern "C" int pir_setup(const pir_params* params, pir_ctx** out) {
+    if (!params || !out || !params->q) return fail(PIR_E_INVALID, "null argument");
+    *out = nullptr;
+    std::vector<uint64_t> q(params->q, params->q + params->L);
+    if (params->L == 0 || params->L > PIR_MAX_L) return fail(PIR_E_UNSUPPORTED, "L out of range");
+    if (params->N != 4096 && params->N != 8192 && params->N != 16384)
+        return fail(PIR_E_UNSUPPORTED, "N must be 4096, 8192 or 16384");
+    std::string why = cw::host::validate(params->N, q, params->t);
+    if (!why.empty()) return fail(PIR_E_INVALID, why);
+    std::vector<uint64_t> B = cw::host::aux_primes(params->N, q, params->t);
+    if (B.size() > (size_t)cw::MAX_LB) return fail(PIR_E_UNSUPPORTED, "auxiliary basis too large");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(PIR_E_DEVICE, "no HIP device");
+    if (params->device < 0 || params->device >= ndev) return fail(PIR_E_INVALID, "bad device ordinal");
+
+    auto cleanup_early = [](int rc, pir_ctx* c) {
+        delete c;
+        return rc;
+    };
+    pir_ctx* ctx = new pir_ctx();
+    ctx->device = params->device;
+    ctx->N = params->N;
+    ctx->logN = params->N == 4096 ? 12 : params->N == 8192 ? 13 : 14;
+    ctx->L = params->L;
+    ctx->LB = (uint32_t)B.size();
+    ctx->LL = ctx->L + ctx->LB;
+    ctx->t = params->t;
+    ctx->budget = params->hbm_budget_bytes;
+    ctx->primes = q;
+    ctx->primes.insert(ctx->primes.end(), B.begin(), B.end());
+    cw::host::build_const(ctx->K, ctx->N, q, B, ctx->t);
+    if (params->chunk_elems > 4096) return cleanup_early(fail(PIR_E_INVALID, "chunk_elems must be <= 4096"), ctx);
+    ctx->chunk = params->chunk_elems ? params->chunk_elems : (ctx->N >= 16384 ? 64 : 128);
+    ctx->memo_cap = params->memo_bytes ? params->memo_bytes : (ctx->budget ? ctx->budget / 4 : (8ull << 30));
+    auto cleanup = [&](int rc) {
+        pir_free(ctx);
+        return rc;
+    };
+    if (hipSetDevice(ctx->device) != hipSuccess) return cleanup(fail(PIR_E_DEVICE, "hipSetDevice failed"));
+    if (cw::kernels_init() != hipSuccess) return cleanup(fail(PIR_E_DEVICE, "kernel attribute setup failed"));
+    std::vector<uint64_t> tw;
+    cw::host::build_twiddles(tw, ctx->primes, ctx->N);
+    int rc;
+    if ((rc = dev_alloc(ctx, (void**)&ctx->dK, sizeof(CtxConst))) != PIR_OK) return cleanup(rc);
+    if ((rc = dev_alloc(ctx, (void**)&ctx->dtw, tw.size() * 8)) != PIR_OK) return cleanup(rc);
+    ctx->fix_cap = (size_t)3 * ctx->chunk * ctx->N;
+    if ((rc = dev_alloc(ctx, (void**)&ctx->dfix, ctx->fix_cap * 8)) != PIR_OK) return cleanup(rc);
+    if ((rc = dev_alloc(ctx, (void**)&ctx->dfixcnt, 256)) != PIR_OK) return cleanup(rc);
+    if (hipMemcpy(ctx->dK, &ctx->K, sizeof(CtxConst), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(ctx->dtw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(ctx->dfixcnt, 0, 256) != hipSuccess || hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) != hipSuccess ||
+        hipDeviceSynchronize() != hipSuccess)
+        return cleanup(fail(PIR_E_DEVICE, "device initialisation failed"));
+    *out = ctx;
+    return PIR_OK;
+}
+
+extern "C" void pir_free(pir_ctx* ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& r : ctx->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto& kv : ctx->ws) dev_free(ctx, kv.second.p, kv.second.bytes);
+    for (auto& kv : ctx->binom) (void)hipFree(kv.second);
+    dev_free(ctx, ctx->dK, sizeof(CtxConst));
+    dev_free(ctx, ctx->dtw, (size_t)ctx->LL * 4 * ctx->N * 8);
+    dev_free(ctx, ctx->dfix, ctx->fix_cap * 8);
+    dev_free(ctx, ctx->dfixcnt, 256);
+    if (ctx->done) (void)hipEventDestroy(ctx->done);
+    delete ctx;
+}
+
+extern "C" uint32_t pir_ctx_aux_primes(const pir_ctx* ctx, uint64_t* out) {
+    if (!ctx) return 0;
+    if (out)
+        for (uint32_t j = 0; j < ctx->LB; ++j) out[j] = ctx->primes[ctx->L + j];
+    return ctx->LB;
+}
+
+extern "C" uint64_t pir_ctx_device_bytes(const pir_ctx* ctx) { return ctx ? ctx->held : 0; }
+
+extern "C" const char* pir_last_error(void) { return g_err.c_str(); }
+
+#define CW_ENTER(ctx)                                                               \
+    if (!(ctx)) return fail(PIR_E_INVALID, "null context");                         \
+    std::lock_guard<std::recursive_mutex> lock_((ctx)->mu);                         \
+    if ((ctx)->poisoned) return fail(PIR_E_DEVICE, "context poisoned by an earlier device error");
+
+// ------------------------------------------------------------------------------------------------
+// keys
+// ------------------------------------------------------------------------------------------------
+extern "C" int pir_load_key(pir_ctx* ctx, const uint64_t* rlk, pir_key** out) {
+    CW_ENTER(ctx);
+    if (!rlk || !out) return fail(PIR_E_INVALID, "null argument");
+    *out = nullptr;
+    CW_HIP(ctx, hipSetDevice(ctx->device));
+    const uint32_t N = ctx->N, L = ctx->L;
+    const size_t rows = (size_t)L * 2 * L, half = rows * N;
+    std::vector<uint64_t> host(half);
+    CW_HIP(ctx, hipMemcpy(host.data(), rlk, half * 8, hipMemcpyDefault));
+    for (size_t r = 0; r < rows; ++r) {
+        const uint64_t p = ctx->primes[r % L];
+        for (uint32_t c = 0; c < N; ++c)
+            if (host[r * N + c] >= p) return fail(PIR_E_INVALID, "relinearization key residue >= q_j");
+    }
+    pir_key* key = new pir_key();
+    key->ctx = ctx;
+    key->bytes = 2 * half * 8;
+    int rc = dev_alloc(ctx, (void**)&key->d, key->bytes);
+    if (rc != PIR_OK) {
+        delete key;
+        return rc;
+    }
+    hipStream_t st = nullptr;
+    Launch lc = make_launch(ctx, st);
+    if (hipMemcpy(key->d, host.data(), half * 8, hipMemcpyHostToDevice) != hipSuccess) {
+        pir_key_free(key);
+        ctx->poisoned = true;
+        return fail(PIR_E_DEVICE, "key upload failed");
+    }
+    cw::launch_ntt(lc, false, key->d, key->d, rows, L, 0);
+    cw::launch_shoup_companions(lc, key->d, key->d + half, rows, L);
+    if (hipDeviceSynchronize() != hipSuccess || hipGetLastError() != hipSuccess) {
+        pir_key_free(key);
+        ctx->poisoned = true;
+        return fail(PIR_E_DEVICE, "key transform failed");
+    }
+    *out = key;
+    return PIR_OK;
+}
+
+extern "C" void pir_key_free(pir_key* key) {
+    if (!key) return;
+    std::lock_guard<std::recursive_mutex> lock(key->ctx->mu);
+    (void)hipSetDevice(key->ctx->device);
+    (void)hipDeviceSynchronize();
+    dev_free(key->ctx, key->d, key->bytes);
+    delete key;
+}
+
+// ------------------------------------------------------------------------------------------------
+// database
+// ------------------------------------------------------------------------------------------------
+// Tree of element j (leaves = ascending positions): k=1 leaf; k=2 (p1 p2); k=3 ((p1 p2) p3);
+// k=4 ((p1 p2)(p3 p4)).  Level-1 products depend only on their two positions, so equal pairs
+// are computed once per group.
+struct PlanBuild {
+    std::vector<uint32_t> pairs;  // [np][2]
+    std::vector<uint32_t> refs;   // [ne][2]
+};
+
+static void plan_elements(const uint32_t* cw, uint64_t e0, uint64_t ne, uint32_t k, PlanBuild& pb) {
+    std::unordered_map<uint64_t, uint32_t> ids;
+    auto pair_id = [&](uint32_t a, uint32_t b) {
+        uint64_t key = ((uint64_t)a << 32) | b;
+        auto it = ids.find(key);
+        if (it != ids.end()) return it->second;
+        uint32_t id = (uint32_t)(pb.pairs.size() / 2);
+        pb.pairs.push_back(a);
+        pb.pairs.push_back(b);
+        ids.emplace(key, id);
+        return id;
+    };
+    for (uint64_t e = e0; e < e0 + ne; ++e) {
+        const uint32_t* p = cw + e * k;
+        uint32_t ra = 0, rb = 0;
+        if (k == 1) {
+            ra = p[0];
+        } else if (k == 2) {
+            ra = p[0];
+            rb = p[1];
+        } else if (k == 3) {
+            ra = pair_id(p[0], p[1]) | cw::REF_NODE;
+            rb = p[2];
+        } else {
+            ra = pair_id(p[0], p[1]) | cw::REF_NODE;
+            rb = pair_id(p[2], p[3]) | cw::REF_NODE;
+        }
+        pb.refs.push_back(ra);
+        pb.refs.push_back(rb);
+    }
+}
+
+static size_t node_bytes(const pir_ctx* ctx) { return (size_t)2 * ctx->LL * ctx->N * 8; }
+
+extern "C" int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, uint32_t k, const uint32_t* codewords,
+                             const uint16_t* payload, pir_db** out) {
+    CW_ENTER(ctx);
+    if (!out) return fail(PIR_E_INVALID, "null argument");
+    *out = nullptr;
+    if (k < 1 || k > PIR_MAX_K) return fail(PIR_E_UNSUPPORTED, "k must be in [1, 4]");
+    if (s < 1 || m < k || m >= 0x7fffffffu) return fail(PIR_E_INVALID, "bad s or m");
+    if (n && (!codewords || !payload)) return fail(PIR_E_INVALID, "null argument");
+    if (n > (1ull << 40)) return fail(PIR_E_INVALID, "n too large");
+    for (uint64_t e = 0; e < n; ++e) {
+        const uint32_t* p = codewords + e * k;
+        for (uint32_t a = 0; a < k; ++a) {
+            if (p[a] >= m) return fail(PIR_E_INVALID, "codeword position >= m at element " + std::to_string(e));
+            if (a && p[a] <= p[a - 1])
+                return fail(PIR_E_INVALID, "codeword positions not strictly ascending at element " + std::to_string(e));
+        }
+    }
+    CW_HIP(ctx, hipSetDevice(ctx->device));
+    pir_db* db = new pir_db();
+    db->ctx = ctx;
+    db->n = n;
+    db->s = s;
+    db->m = m;
+    db->k = k;
+    db->cw.assign(codewords, codewords + n * k);
+    // schedule: one group sharing all level-1 products when they fit the memo budget, else one
+    // group per chunk of elements
+    const uint32_t E = ctx->chunk;
+    PlanBuild all;
+    plan_elements(db->cw.data(), 0, n, k, all);
+    const uint64_t memo_cap = ctx->memo_cap;
+    const uint64_t np_all = all.pairs.size() / 2;
+    PlanBuild pb;
+    if (k < 3 || np_all * node_bytes(ctx) <= memo_cap) {
+        Group g;
+        g.e0 = 0;
+        g.ne = n;
+        g.p0 = 0;
+        g.np = (uint32_t)np_all;
+        db->groups.push_back(g);
+        pb = std::move(all);
+    } else {
+        for (uint64_t e0 = 0; e0 < n; e0 += E) {
+            Group g;
+            g.e0 = e0;
+            g.ne = std::min<uint64_t>(E, n - e0);
+            g.p0 = (uint32_t)(pb.pairs.size() / 2);
+            PlanBuild local;
+            plan_elements(db->cw.data(), e0, g.ne, k, local);
+            g.np = (uint32_t)(local.pairs.size() / 2);
+            pb.pairs.insert(pb.pairs.end(), local.pairs.begin(), local.pairs.end());
+            pb.refs.insert(pb.refs.end(), local.refs.begin(), local.refs.end());
+            db->groups.push_back(g);
+        }
+    }
+    for (auto& g : db->groups) db->max_pairs = std::max(db->max_pairs, g.np);
+    db->total_pairs = pb.pairs.size() / 2;
+    const size_t pay_bytes = (size_t)n * s * ctx->N * 2;
+    int rc = dev_alloc(ctx, (void**)&db->dpay, pay_bytes);
+    if (rc == PIR_OK) db->pay_bytes = pay_bytes;
+    if (rc == PIR_OK) rc = dev_alloc(ctx, (void**)&db->dpairs, std::max<size_t>(8, pb.pairs.size() * 4));
+    if (rc == PIR_OK) db->pairs_bytes = std::max<size_t>(8, pb.pairs.size() * 4);
+    if (rc == PIR_OK) rc = dev_alloc(ctx, (void**)&db->drefs, std::max<size_t>(8, pb.refs.size() * 4));
+    if (rc == PIR_OK) db->refs_bytes = std::max<size_t>(8, pb.refs.size() * 4);
+    if (rc != PIR_OK) {
+        pir_db_free(db);
+        return rc;
+    }
+    if ((pay_bytes && hipMemcpy(db->dpay, payload, pay_bytes, hipMemcpyDefault) != hipSuccess) ||
+        (!pb.pairs.empty() && hipMemcpy(db->dpairs, pb.pairs.data(), pb.pairs.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+        (!pb.refs.empty() && hipMemcpy(db->drefs, pb.refs.data(), pb.refs.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+        hipDeviceSynchronize() != hipSuccess) {
+        pir_db_free(db);
+        ctx->poisoned = true;
+        return fail(PIR_E_DEVICE, "database upload failed");
+    }
+    *out = db;
+    return PIR_OK;
+}
+
+extern "C" void pir_db_free(pir_db* db) {
+    if (!db) return;
+    pir_ctx* ctx = db->ctx;
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    dev_free(ctx, db->dpay, db->pay_bytes);
+    dev_free(ctx, db->dpairs, db->pairs_bytes);
+    dev_free(ctx, db->drefs, db->refs_bytes);
+    delete db;
+}
+
+extern "C" uint64_t pir_db_pair_count(const pir_db* db) { return db ? db->total_pairs : 0; }
+
+// ------------------------------------------------------------------------------------------------
+// the path
+// ------------------------------------------------------------------------------------------------
+struct Bufs {
+    uint64_t* X = nullptr;   // [E][3][LL][N]
+    uint64_t* R = nullptr;   // [E][L+2][L][N]
+    uint64_t* Ph = nullptr;  // [E][s][L][N]
+};
+
+static int get_bufs(pir_ctx* ctx, uint32_t E, uint32_t s, Bufs& b) {
+    const size_t N = ctx->N, L = ctx->L, LL = ctx->LL;
+    CW_TRY(ws_get_t(ctx, "X", (size_t)E * 3 * LL * N, &b.X));
+    CW_TRY(ws_get_t(ctx, "R", (size_t)E * (L + 2) * L * N, &b.R));
+    if (s) CW_TRY(ws_get_t(ctx, "Ph", (size_t)E * s * L * N, &b.Ph));
+    return PIR_OK;
+}
+
+// Query residency: extend [m][2][L][N] to Q u B and transform.
+static int make_leaves(pir_ctx* ctx, const Launch& lc, const uint64_t* query, uint32_t m, uint64_t* QX) {
+    const size_t N = ctx->N, L = ctx->L, LL = ctx->LL;
+    const size_t G = (size_t)2 * m, gmax = std::max<size_t>(1, ctx->fix_cap / N);
+    {
+        Prof pr(ctx, "extend", lc.stream);
+        for (size_t g0 = 0; g0 < G; g0 += gmax) {
+            size_t g = std::min(gmax, G - g0);
+            cw::launch_extend(lc, query + g0 * L * N, QX + g0 * LL * N, g);
+        }
+    }
+    Prof pr(ctx, "ntt_fwd", lc.stream);
+    cw::launch_ntt(lc, false, QX, QX, G * LL, (uint32_t)LL, 0);
+    return check_launch(ctx);
+}
+
+// Mult + Relin of `cnt` operand pairs (refs into leaves/nodes); result transformed over Q in sel.
+static void mult_relin(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint32_t* refs, const uint64_t* leaves,
+                       const uint64_t* nodes, const pir_key* key, uint64_t* sel, uint32_t cnt) {
+    const uint32_t L = ctx->L, LL = ctx->LL;
+    {
+        Prof pr(ctx, "tensor", lc.stream);
+        cw::launch_tensor(lc, refs, leaves, nodes, b.X, cnt);
+    }
+    {
+        Prof pr(ctx, "ntt_inv", lc.stream);
+        cw::launch_ntt(lc, true, b.X, b.X, (size_t)cnt * 3 * LL, LL, 0);
+    }
+    {
+        Prof pr(ctx, "scale", lc.stream);
+        cw::launch_scale(lc, b.X, b.R, cnt, cw::SCALE_STAGING);
+    }
+    {
+        Prof pr(ctx, "ntt_fwd", lc.stream);
+        cw::launch_ntt(lc, false, b.R, b.R, (size_t)cnt * (L + 2) * L, L, 0);
+    }
+    Prof pr(ctx, "relin_mac", lc.stream);
+    cw::launch_relin_mac(lc, b.R, key->d, sel, cnt);
+}
+
+// Level-1 products of pairs[0..np) into nodes (extended, transformed), in chunks of E.
+static void make_nodes(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint32_t* pairs, uint32_t np,
+                       const uint64_t* leaves, const pir_key* key, uint64_t* tmp_sel, uint64_t* nodes, uint32_t E) {
+    const size_t N = ctx->N, L = ctx->L, LL = ctx->LL;
+    for (uint32_t p0 = 0; p0 < np; p0 += E) {
+        const uint32_t cnt = std::min(E, np - p0);
+        mult_relin(ctx, lc, b, pairs + 2 * (size_t)p0, leaves, nullptr, key, tmp_sel, cnt);
+        {
+            Prof pr(ctx, "ntt_inv", lc.stream);
+            cw::launch_ntt(lc, true, tmp_sel, tmp_sel, (size_t)cnt * 2 * L, L, 0);
+        }
+        uint64_t* dst = nodes + (size_t)p0 * 2 * LL * N;
+        {
+            Prof pr(ctx, "extend", lc.stream);
+            cw::launch_extend(lc, tmp_sel, dst, (size_t)2 * cnt);
+        }
+        Prof pr(ctx, "ntt_fwd", lc.stream);
+        cw::launch_ntt(lc, false, dst, dst, (size_t)cnt * 2 * LL, LL, 0);
+    }
+}
+
+static void roots(pir_ctx* ctx, const Launch& lc, const Bufs& b, uint32_t k, const uint32_t* refs,
+                  const uint64_t* leaves, const uint64_t* nodes, const pir_key* key, uint64_t* sel, uint32_t cnt) {
+    if (k == 1) {
+        Prof pr(ctx, "gather", lc.stream);
+        cw::launch_gather_leaf(lc, refs, leaves, sel, cnt);
+        return;
+    }
+    mult_relin(ctx, lc, b, refs, leaves, nodes, key, sel, cnt);
+}
+
+// B queries against one database.
+static int answer_same_db(pir_ctx* ctx, hipStream_t st, const pir_db* db, uint32_t B, const pir_key* const* keys,
+                          const uint64_t* const* queries, uint64_t* const* answers) {
+    const size_t N = ctx->N, L = ctx->L, LL = ctx->LL;
+    const uint32_t E = ctx->chunk, s = db->s, m = db->m, k = db->k;
+    Launch lc = make_launch(ctx, st);
+    Bufs b;
+    CW_TRY(get_bufs(ctx, E, s, b));
+    uint64_t *QX, *nodes, *sel;
+    const size_t qx_one = (size_t)m * 2 * LL * N, node_one = (size_t)std::max<uint32_t>(db->max_pairs, 1) * 2 * LL * N;
+    const size_t sel_one = (size_t)E * 2 * L * N;
+    CW_TRY(ws_get_t(ctx, "QX", qx_one * B, &QX));
+    if (k >= 3) CW_TRY(ws_get_t(ctx, "nodes", node_one * B, &nodes));
+    else nodes = nullptr;
+    CW_TRY(ws_get_t(ctx, "sel", sel_one * B, &sel));
+    const size_t acc_n = (size_t)s * 2 * L * N;
+    for (uint32_t q = 0; q < B; ++q) {
+        CW_TRY(make_leaves(ctx, lc, queries[q], m, QX + q * qx_one));
+        Prof pr(ctx, "fill", st);
+        cw::launch_fill(st, answers[q], acc_n, 0);
+    }
+    for (const Group& g : db->groups) {
+        if (g.np)
+            for (uint32_t q = 0; q < B; ++q)
+                make_nodes(ctx, lc, b, db->dpairs + 2 * (size_t)g.p0, g.np, QX + q * qx_one, keys[q], sel + q * sel_one,
+                           nodes + q * node_one, E);
+        for (uint64_t c0 = 0; c0 < g.ne; c0 += E) {
+            const uint32_t cnt = (uint32_t)std::min<uint64_t>(E, g.ne - c0);
+            const uint32_t* refs = db->drefs + 2 * (g.e0 + c0);
+            for (uint32_t q = 0; q < B; ++q)
+                roots(ctx, lc, b, k, refs, QX + q * qx_one, nodes ? nodes + q * node_one : nullptr, keys[q],
+                      sel + q * sel_one, cnt);
+            {
+                Prof pr(ctx, "payload_ntt", st);
+                cw::launch_ntt_payload(lc, db->dpay + (g.e0 + c0) * s * N, b.Ph, (size_t)cnt * s);
+            }
+            Prof pr(ctx, "accumulate", st);
+            for (uint32_t q0 = 0; q0 < B; q0 += cw::MAX_BATCH) {
+                cw::QueryPtrs qp;
+                const uint32_t nq = std::min<uint32_t>(cw::MAX_BATCH, B - q0);
+                for (uint32_t q = 0; q < nq; ++q) {
+                    qp.sel[q] = sel + (q0 + q) * sel_one;
+                    qp.acc[q] = answers[q0 + q];
+                }
+                cw::launch_accumulate(lc, qp, b.Ph, nq, cnt, s);
+            }
+        }
+        CW_TRY(check_launch(ctx));
+    }
+    for (uint32_t q = 0; q < B; ++q) {
+        Prof pr(ctx, "ntt_inv", st);
+        cw::launch_ntt(lc, true, answers[q], answers[q], (size_t)s * 2 * L, L, 0);
+    }
+    return check_launch(ctx);
+}
+
+extern "C" int pir_answer_batch(pir_ctx* ctx, uint32_t B, const pir_key* const* keys, const pir_db* const* dbs,
+                                const uint64_t* const* queries, uint64_t* const* answers, void* stream) {
+    CW_ENTER(ctx);
+    if (B == 0) return PIR_OK;
+    if (!keys || !dbs || !queries || !answers) return fail(PIR_E_INVALID, "null argument");
+    for (uint32_t q = 0; q < B; ++q) {
+        if (!keys[q] || !dbs[q] || !queries[q] || !answers[q]) return fail(PIR_E_INVALID, "null argument");
+        if (keys[q]->ctx != ctx || dbs[q]->ctx != ctx) return fail(PIR_E_INVALID, "handle from another context");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    CW_TRY(begin_async(ctx, st));
+    // queries on the same database share its payload scan; databases run in first-seen order
+    std::vector<const pir_db*> order;
+    for (uint32_t q = 0; q < B; ++q)
+        if (std::find(order.begin(), order.end(), dbs[q]) == order.end()) order.push_back(dbs[q]);
+    for (const pir_db* db : order) {
+        std::vector<const pir_key*> ks;
+        std::vector<const uint64_t*> qs;
+        std::vector<uint64_t*> as;
+        for (uint32_t q = 0; q < B; ++q)
+            if (dbs[q] == db) {
+                ks.push_back(keys[q]);
+                qs.push_back(queries[q]);
+                as.push_back(answers[q]);
+            }
+        CW_TRY(answer_same_db(ctx, st, db, (uint32_t)ks.size(), ks.data(), qs.data(), as.data()));
+    }
+    return end_async(ctx, st);
+}
+
+extern "C" int pir_answer(pir_ctx* ctx, const pir_key* key, const pir_db* db, const uint64_t* query, uint64_t* answer,
+                          void* stream) {
+    return pir_answer_batch(ctx, 1, &key, &db, &query, &answer, stream);
+}
+
+extern "C" int pir_selectors(pir_ctx* ctx, const pir_key* key, const pir_db* db, const uint64_t* query,
+                             const uint64_t* elems, uint32_t count, uint64_t* out, void* stream) {
+    CW_ENTER(ctx);
+    if (!key || !db || !query || (count && (!elems || !out))) return fail(PIR_E_INVALID, "null argument");
+    for (uint32_t i = 0; i < count; ++i)
+        if (elems[i] >= db->n) return fail(PIR_E_INVALID, "element index out of range");
+    if (!count) return PIR_OK;
+    hipStream_t st = (hipStream_t)stream;
+    CW_TRY(begin_async(ctx, st));
+    const size_t N = ctx->N, L = ctx->L, LL = ctx->LL;
+    const uint32_t E = ctx->chunk, k = db->k;
+    Launch lc = make_launch(ctx, st);
+    Bufs b;
+    CW_TRY(get_bufs(ctx, E, 0, b));
+    uint64_t *QX, *sel, *nodes = nullptr;
+    CW_TRY(ws_get_t(ctx, "QX", (size_t)db->m * 2 * LL * N, &QX));
+    CW_TRY(ws_get_t(ctx, "sel", (size_t)E * 2 * L * N, &sel));
+    CW_TRY(make_leaves(ctx, lc, query, db->m, QX));
+    for (uint32_t c0 = 0; c0 < count; c0 += E) {
+        const uint32_t cnt = std::min(E, count - c0);
+        std::vector<uint32_t> cw((size_t)cnt * k);
+        for (uint32_t i = 0; i < cnt; ++i)
+            std::memcpy(&cw[(size_t)i * k], &db->cw[elems[c0 + i] * k], k * 4);
+        PlanBuild pb;
+        plan_elements(cw.data(), 0, cnt, k, pb);
+        uint32_t *dpairs, *drefs;
+        CW_TRY(ws_get_t(ctx, "sel_pairs", std::max<size_t>(2, pb.pairs.size()), &dpairs));
+        CW_TRY(ws_get_t(ctx, "sel_refs", pb.refs.size(), &drefs));
+        if (!pb.pairs.empty())
+            CW_HIP(ctx, hipMemcpyAsync(dpairs, pb.pairs.data(), pb.pairs.size() * 4, hipMemcpyHostToDevice, st));
+        CW_HIP(ctx, hipMemcpyAsync(drefs, pb.refs.data(), pb.refs.size() * 4, hipMemcpyHostToDevice, st));
+        const uint32_t np = (uint32_t)(pb.pairs.size() / 2);
+        if (np) {
+            CW_TRY(ws_get_t(ctx, "sel_nodes", (size_t)np * 2 * LL * N, &nodes));
+            make_nodes(ctx, lc, b, dpairs, np, QX, key, sel, nodes, E);
+        }
+        roots(ctx, lc, b, k, drefs, QX, nodes, key, sel, cnt);
+        cw::launch_ntt(lc, true, sel, out + (size_t)c0 * 2 * L * N, (size_t)cnt * 2 * L, L, 0);
+        CW_HIP(ctx, hipStreamSynchronize(st));  // the plan lives in pageable host memory
+    }
+    return end_async(ctx, st);
+}
+
+// ------------------------------------------------------------------------------------------------
+// single FV operations
+// ------------------------------------------------------------------------------------------------
+extern "C" int pir_mult(pir_ctx* ctx, const uint64_t* a, const uint64_t* b_, uint64_t* out, void* stream) {
+    CW_ENTER(ctx);
+    if (!a || !b_ || !out) return fail(PIR_E_INVALID, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    CW_TRY(begin_async(ctx, st));
+    const size_t N = ctx->N, L = ctx->L, LL = ctx->LL;
+    Launch lc = make_launch(ctx, st);
+    Bufs b;
+    CW_TRY(get_bufs(ctx, 1, 0, b));
+    uint64_t* QX;
+    uint32_t* refs;
+    CW_TRY(ws_get_t(ctx, "op_leaves", (size_t)2 * 2 * LL * N, &QX));
+    CW_TRY(ws_get_t(ctx, "op_refs", 2, &refs));
+    static const uint32_t h_refs[2] = {0, 1};
+    CW_HIP(ctx, hipMemcpyAsync(refs, h_refs, 8, hipMemcpyHostToDevice, st));
+    cw::launch_extend(lc, a, QX, 2);
+    cw::launch_extend(lc, b_, QX + 2 * LL * N, 2);
+    cw::launch_ntt(lc, false, QX, QX, 4 * LL, LL, 0);
+    cw::launch_tensor(lc, refs, QX, nullptr, b.X, 1);
+    cw::launch_ntt(lc, true, b.X, b.X, 3 * LL, LL, 0);
+    cw::launch_scale(lc, b.X, out, 1, cw::SCALE_PLAIN);
+    (void)L;
+    return end_async(ctx, st);
+}
+
+extern "C" int pir_relin(pir_ctx* ctx, const pir_key* key, const uint64_t* in, uint64_t* out, void* stream) {
+    CW_ENTER(ctx);
+    if (!key || !in || !out) return fail(PIR_E_INVALID, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    CW_TRY(begin_async(ctx, st));
+    const uint32_t L = ctx->L;
+    Launch lc = make_launch(ctx, st);
+    Bufs b;
+    CW_TRY(get_bufs(ctx, 1, 0, b));
+    cw::launch_relin_stage(lc, in, b.R, 1);
+    cw::launch_ntt(lc, false, b.R, b.R, (size_t)(L + 2) * L, L, 0);
+    cw::launch_relin_mac(lc, b.R, key->d, out, 1);
+    cw::launch_ntt(lc, true, out, out, (size_t)2 * L, L, 0);
+    return end_async(ctx, st);
+}
+
+extern "C" int pir_pm(pir_ctx* ctx, const uint64_t* ct, const uint16_t* pt, uint64_t* out, void* stream) {
+    CW_ENTER(ctx);
+    if (!ct || !pt || !out) return fail(PIR_E_INVALID, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    CW_TRY(begin_async(ctx, st));
+    const size_t N = ctx->N, L = ctx->L;
+    Launch lc = make_launch(ctx, st);
+    uint64_t *tct, *tpt;
+    CW_TRY(ws_get_t(ctx, "op_ct", 2 * L * N, &tct));
+    CW_TRY(ws_get_t(ctx, "op_pt", L * N, &tpt));
+    cw::launch_ntt(lc, false, ct, tct, 2 * L, (uint32_t)L, 0);
+    cw::launch_ntt_payload(lc, pt, tpt, 1);
+    cw::launch_pointwise_pt(lc, tct, tpt, tct);
+    cw::launch_ntt(lc, true, tct, out, 2 * L, (uint32_t)L, 0);
+    return end_async(ctx, st);
+}
+
+// ------------------------------------------------------------------------------------------------
+// codeword tables
+// ------------------------------------------------------------------------------------------------
+extern "C" int pir_map_perfect(pir_ctx* ctx, const uint64_t* ids, uint64_t n, uint32_t m, uint32_t k, uint32_t* out,
+                               void* stream) {
+    CW_ENTER(ctx);
+    if (n && (!ids || !out)) return fail(PIR_E_INVALID, "null argument");
+    if (k < 1 || k > 16 || m < k || m > 65535) return fail(PIR_E_INVALID, "need 1 <= k <= 16, k <= m <= 65535");
+    hipStream_t st = (hipStream_t)stream;
+    CW_TRY(begin_async(ctx, st));
+    auto key = std::make_pair(m, k);
+    uint64_t* tab = nullptr;
+    auto it = ctx->binom.find(key);
+    if (it == ctx->binom.end()) {
+        std::vector<uint64_t> T = cw::host::binom_table(m, k);
+        CW_HIP(ctx, hipMalloc((void**)&tab, T.size() * 8));
+        CW_HIP(ctx, hipMemcpy(tab, T.data(), T.size() * 8, hipMemcpyHostToDevice));
+        ctx->binom[key] = tab;
+    } else {
+        tab = it->second;
+    }
+    cw::launch_map_perfect(st, ids, n, m, k, tab, out);
+    return end_async(ctx, st);
+}
+
+extern "C" int pir_map_lossy(pir_ctx* ctx, const uint64_t* keywords, uint64_t n, uint32_t m, uint32_t k, uint64_t seed,
+                             uint32_t* out, void* stream) {
+    CW_ENTER(ctx);
+    if (n && (!keywords || !out)) return fail(PIR_E_INVALID, "null argument");
+    if (k < 1 || k > 16 || m < k || m > 65535) return fail(PIR_E_INVALID, "need 1 <= k <= 16, k <= m <= 65535");
+    hipStream_t st = (hipStream_t)stream;
+    CW_TRY(begin_async(ctx, st));
+    cw::launch_map_lossy(st, keywords, n, m, k, seed, out);
+    return end_async(ctx, st);
+}
+
+// ------------------------------------------------------------------------------------------------
+// profiling
+// ------------------------------------------------------------------------------------------------
+extern "C" int pir_profile_enable(pir_ctx* ctx, int on) {
+    CW_ENTER(ctx);
+    ctx->prof = on != 0;
+    return PIR_OK;
+}
+
+extern "C" int pir_profile_read(pir_ctx* ctx, uint32_t max, const char** names, double* total_ms, uint64_t* launches,
+                                int reset) {
+    CW_ENTER(ctx);
+    for (auto& r : ctx->recs) {
+        float ms = 0.f;
+        if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+            auto& acc = ctx->prof_acc[r.name];
+            acc.first += ms;
+            acc.second += 1;
+        }
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    ctx->recs.clear();
+    uint32_t i = 0;
+    static std::set<std::string> keep;  // node-based: returned pointers stay valid
+    for (auto& kv : ctx->prof_acc) {
+        if (i < max) {
+            if (names) names[i] = keep.insert(kv.first).first->c_str();
+            if (total_ms) total_ms[i] = kv.second.first;
+            if (launches) launches[i] = kv.second.second;
+        }
+        ++i;
+    }
+    if (reset) ctx->prof_acc.clear();
+    return (int)i;
+}

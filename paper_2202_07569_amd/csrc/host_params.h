@@ -1,0 +1,31 @@
+// Host-side parameter construction (see host_params.cpp).
+#pragma once
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "consts.h"
+
+namespace cw {
+namespace host {
+
+uint64_t mulmod(uint64_t a, uint64_t b, uint64_t p);
+uint64_t powmod(uint64_t a, uint64_t e, uint64_t p);
+uint64_t invmod(uint64_t a, uint64_t p);
+uint64_t shoup(uint64_t w, uint64_t p);
+bool is_prime(uint64_t n);
+uint64_t find_psi(uint64_t p, uint32_t N);
+
+// "" when (N, q, t) is supported, else the reason.
+std::string validate(uint32_t N, const std::vector<uint64_t>& q, uint64_t t);
+// Largest primes = 1 mod 2N below 2^61, not in q, until their product exceeds 4 t N q.
+std::vector<uint64_t> aux_primes(uint32_t N, const std::vector<uint64_t>& q, uint64_t t);
+void build_const(CtxConst& K, uint32_t N, const std::vector<uint64_t>& q, const std::vector<uint64_t>& B,
+                 uint64_t t);
+// [prime][4][N]: psi^bitrev(i), its Shoup companion, psi^-bitrev(i), its Shoup companion.
+void build_twiddles(std::vector<uint64_t>& tw, const std::vector<uint64_t>& primes, uint32_t N);
+std::vector<uint64_t> binom_table(uint32_t m, uint32_t k);
+
+}  // namespace host
+}  // namespace cw

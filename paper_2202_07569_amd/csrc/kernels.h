@@ -1,0 +1,50 @@
+// Launch wrappers of the gfx950 kernels (kernels.hip).  Every wrapper enqueues on lc.stream.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "consts.h"
+
+namespace cw {
+
+constexpr int NTT_THREADS = 512;
+constexpr int SCALE_STAGING = 0;
+constexpr int SCALE_PLAIN = 1;
+constexpr int MAX_BATCH = 32;  // queries per accumulate launch
+
+struct QueryPtrs {  // passed by value as a kernel argument
+    const uint64_t* sel[MAX_BATCH];
+    uint64_t* acc[MAX_BATCH];
+};
+
+struct Launch {
+    hipStream_t stream;
+    const CtxConst* K;    // device copy of the constants
+    const uint64_t* tw;   // device twiddles [LL][4][N]
+    uint32_t N, logN, L, LB, LL;
+    uint64_t* fix;        // fixup list for ambiguous conversions (capacity >= coefficients per launch)
+    uint32_t* fixcnt;     // its counter; zero between launches
+};
+
+hipError_t kernels_init();
+void launch_ntt(const Launch& lc, bool inverse, const uint64_t* in, uint64_t* out, size_t rows, uint32_t nl,
+                uint32_t pbase);
+void launch_ntt_payload(const Launch& lc, const uint16_t* pay, uint64_t* out, size_t rows_u16);
+void launch_extend(const Launch& lc, const uint64_t* in, uint64_t* out, size_t G);
+void launch_tensor(const Launch& lc, const uint32_t* refs, const uint64_t* leaves, const uint64_t* nodes, uint64_t* X,
+                   uint32_t E);
+void launch_scale(const Launch& lc, const uint64_t* X, uint64_t* out, uint32_t E, int mode);
+void launch_relin_stage(const Launch& lc, const uint64_t* in, uint64_t* out, uint32_t E);
+void launch_relin_mac(const Launch& lc, const uint64_t* R, const uint64_t* rlk, uint64_t* sel, uint32_t E);
+void launch_shoup_companions(const Launch& lc, const uint64_t* v, uint64_t* comp, size_t rows, uint32_t nl);
+void launch_gather_leaf(const Launch& lc, const uint32_t* refs, const uint64_t* leaves, uint64_t* sel, uint32_t E);
+void launch_accumulate(const Launch& lc, const QueryPtrs& qp, const uint64_t* Ph, uint32_t nq, uint32_t E,
+                       uint32_t s);
+void launch_pointwise_pt(const Launch& lc, const uint64_t* ct, const uint64_t* pt, uint64_t* out);
+void launch_fill(hipStream_t st, uint64_t* p, size_t n, uint64_t v);
+void launch_map_perfect(hipStream_t st, const uint64_t* ids, size_t n, uint32_t m, uint32_t k, const uint64_t* binom,
+                        uint32_t* out);
+void launch_map_lossy(hipStream_t st, const uint64_t* kw, size_t n, uint32_t m, uint32_t k, uint64_t seed,
+                      uint32_t* out);
+
+}  // namespace cw

@@ -1,0 +1,69 @@
+"""Host-side checks of the HIP library that need no GPU: it loads, exports every declared entry
+point, and rejects unsupported parameters before touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import datagen
+from paper_2202_07569_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    names = []
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", fn)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"^\s*(?:[\w\*]+\s+)+\**(pir_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = binding.lib()
+    declared = _declared()
+    assert len(declared) >= 20
+    for name in declared:
+        assert hasattr(lib, name), name
+    assert sorted(binding.EXPORTS) == declared
+
+
+def _setup(N, primes, t=65537, chunk=0):
+    q = (ctypes.c_uint64 * len(primes))(*primes)
+    p = binding._Params(N, len(primes), q, t, 0, 0, chunk, 0)
+    h = ctypes.c_void_p()
+    rc = binding.lib().pir_setup(ctypes.byref(p), ctypes.byref(h))
+    return rc, binding.lib().pir_last_error().decode()
+
+
+@pytest.mark.parametrize("N,primes,t,code,text", [
+    (2048, datagen.Q_N4096, 65537, binding.PIR_E_UNSUPPORTED, "N must be"),
+    (4096, (), 65537, binding.PIR_E_UNSUPPORTED, "L out of range"),
+    (4096, datagen.Q_N4096[:2] + (datagen.Q_N4096[0],), 65537, binding.PIR_E_INVALID, "distinct"),
+    (4096, (0xffffee001 + 8192,), 65537, binding.PIR_E_INVALID, "not prime"),
+    (8192, datagen.Q_N4096, 65537, binding.PIR_E_INVALID, "1 mod 2N"),
+    (4096, ((1 << 61) + 1,), 65537, binding.PIR_E_INVALID, "(2^30, 2^61)"),
+    (4096, datagen.Q_N4096, 1, binding.PIR_E_INVALID, "t must be"),
+])
+def test_setup_rejects_bad_parameters(N, primes, t, code, text):
+    rc, msg = _setup(N, primes, t)
+    assert rc == code and text in msg
+
+
+def test_setup_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    rc, msg = _setup(4096, datagen.Q_N4096)
+    assert rc == binding.PIR_E_DEVICE and "device" in msg
+
+
+def test_context_refuses_to_run_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(binding.PirError):
+        binding.Context(4096, datagen.Q_N4096)
