@@ -31,10 +31,11 @@ sys.path.insert(0, ROOT)
 import datagen  # noqa: E402
 
 MI355X_HBM_GBPS = 8000.0
-# Integer ALU roof: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz full-rate lane ops; 32-bit multiplies
-# (v_mul_lo_u32 / v_mul_hi_u32 / v_mad_u64_u32) issue at a quarter of that rate.
-MI355X_INT_MUL_PER_S = 256 * 4 * 16 * 2.4e9 / 4
-MULS_PER_BUTTERFLY = 10  # 64-bit Shoup butterfly: hi64(a w') 4, lo64(a w) 3, lo64(q p) 3
+# Integer ALU roof: 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz = 78.6 T lane-ops/s for
+# full-rate 32-bit operations; the 32-bit multipliers (v_mul_lo_u32, v_mul_hi_u32,
+# v_mad_u64_u32) run at half that rate, 39.3 T/s (measured 31-33 T/s with an ALU-only probe).
+MI355X_INT_MUL_PER_S = 256 * 4 * 32 * 2.4e9 / 2
+MULS_PER_BUTTERFLY = 10  # 64-bit Shoup butterfly: hi64(a w') 5 mads, lo64(a w) and lo64(q p) 4 muls + 1 mul_hi
 
 
 def log(msg):
@@ -130,32 +131,10 @@ def main():
     value = B * n * args.steps / t_b
     log(f"batched {ms_step:.1f} ms/step -> {value:.0f} elements/s")
 
-    roof = None
-    if prof:
-        name, (tot_ms, launches) = max(prof.items(), key=lambda kv: kv[1][0])
-        # algorithmic work of one launch of the dominant family
-        bfly_row = cfg.N // 2 * int(math.log2(cfg.N))
-        L, LB = cfg.L, len(ctx.aux_primes)
-        LL = L + LB
-        E = 128 if cfg.N <= 8192 else 64
-        rows_by_family = {}
-        avg_ms = tot_ms / launches
-        if name.startswith("ntt"):
-            # rows per launch differ by call site; use the family's total rows per step
-            rows_step = _ntt_rows_per_step(cfg, n, LL, L, db.pair_count, B, name)
-            bfly = rows_step * bfly_row / (launches / args.steps)
-            achieved = bfly / (avg_ms * 1e-3)
-            peak = MI355X_INT_MUL_PER_S / MULS_PER_BUTTERFLY
-            roof = {"kernel": name, "bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                    "unit": "Tbutterfly/s", "frac": achieved / peak, "traffic": None,
-                    "avg_launch_ms": avg_ms, "launches_per_step": launches / args.steps}
-        else:
-            roof = {"kernel": name, "avg_launch_ms": avg_ms, "launches_per_step": launches / args.steps}
-        roof["families_ms_per_step"] = {k: v[0] / args.steps for k, v in sorted(prof.items())}
-        del rows_by_family, E
+    roof = roofline(prof, args.steps, cfg.N) if prof else None
 
     cpu = None
-    sample = args.cpu_sample if args.cpu_sample >= 0 else (16 if cfg.N <= 8192 else 4)
+    sample = args.cpu_sample if args.cpu_sample >= 0 else (256 if cfg.N <= 8192 else 32)
     if sample:
         cpu = cpu_baseline(cfg, rlk, queries[0], codewords[:sample], payload[:sample])
 
@@ -177,20 +156,29 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-def _ntt_rows_per_step(cfg, n, LL, L, pairs, B, family):
-    """Limb-polynomial transforms of one batched step, per family (forward or inverse)."""
-    k, m, s = cfg.k, cfg.m, cfg.s
-    roots = n if k >= 2 else 0
-    mults = roots + (pairs if k >= 3 else 0)
-    if family == "ntt_fwd":
-        rows = 2 * m * LL                       # query residency
-        rows += mults * (L + 2) * L             # relinearization digits, c0, c1
-        rows += (pairs if k >= 3 else 0) * 2 * LL  # level-1 products back to Q u B
-        return rows * B
-    rows = mults * 3 * LL                       # tensor products
-    rows += (pairs if k >= 3 else 0) * 2 * L    # level-1 products to coefficient form
-    rows += s * 2 * L                           # answers
-    return rows * B
+NTT_FAMILIES = ("ntt_fwd", "ntt_inv", "ntt_inv_tensor", "ntt_digits", "payload_ntt")
+
+
+def roofline(prof, steps, N):
+    """Roofline entry of the kernel family with the largest share of the timed region.
+
+    Transforms are bound by the 32-bit integer multipliers: one lazy Shoup butterfly on 64-bit
+    words takes MULS_PER_BUTTERFLY multiplies, so the peak is MI355X_INT_MUL_PER_S /
+    MULS_PER_BUTTERFLY butterflies per second; achieved = algorithmic butterflies of one launch
+    (rows x N/2 x log2 N) / the launch's average duration from HIP events on its stream.
+    """
+    name, (tot_ms, launches, work) = max(prof.items(), key=lambda kv: kv[1][0])
+    avg_ms = tot_ms / launches
+    fam = {k: {"ms_per_step": v[0] / steps, "launches_per_step": v[1] / steps,
+               "work_per_s": (v[2] / (v[0] * 1e-3)) if v[0] else None} for k, v in sorted(prof.items())}
+    out = {"kernel": name, "avg_launch_ms": avg_ms, "launches_per_step": launches / steps, "families": fam}
+    if name in NTT_FAMILIES:
+        per_launch = work / launches
+        achieved = per_launch / (avg_ms * 1e-3)
+        peak = MI355X_INT_MUL_PER_S / MULS_PER_BUTTERFLY
+        out.update({"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "Tbutterfly/s",
+                    "frac": achieved / peak, "traffic": None, "butterflies_per_launch": per_launch})
+    return out
 
 
 def cpu_baseline(cfg, rlk, query, codewords, payload):

@@ -141,12 +141,15 @@ uint32_t pir_ctx_aux_primes(const pir_ctx* ctx, uint64_t* out_primes /* may be N
 uint64_t pir_ctx_device_bytes(const pir_ctx* ctx);       /* bytes the library holds on the device */
 uint64_t pir_db_pair_count(const pir_db* db);            /* distinct level-1 products (k >= 3)    */
 
-/* Kernel timing with HIP events on the launching stream.  When enabled, every launch is bracketed
- * by events; pir_profile_read synchronises on them and returns, per kernel family, the summed
- * milliseconds and launch counts (names are static strings).  Returns the number of families. */
+/* Kernel timing with HIP events on the launching stream.  When enabled, every kernel family's
+ * launch is bracketed by events; pir_profile_read synchronises on them and returns, per family,
+ * the summed milliseconds, the number of bracketed launches and the algorithmic work done
+ * (butterflies for transforms, coefficients for the element-wise kernels).  Names stay valid
+ * until the library is unloaded.  Any output pointer may be NULL.  Returns the number of
+ * families (or a negative error code). */
 int pir_profile_enable(pir_ctx* ctx, int on);
 int pir_profile_read(pir_ctx* ctx, uint32_t max, const char** names, double* total_ms, uint64_t* launches,
-                     int reset);
+                     double* work, int reset);
 
 void pir_db_free(pir_db* db);
 void pir_key_free(pir_key* key);

@@ -69,7 +69,7 @@ def lib():
             "pir_db_pair_count": (u64, [vp]),
             "pir_profile_enable": (i32, [vp, i32]),
             "pir_profile_read": (i32, [vp, u32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
-                                       ctypes.POINTER(ctypes.c_uint64), i32]),
+                                       ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double), i32]),
             "pir_db_free": (None, [vp]),
             "pir_key_free": (None, [vp]),
             "pir_free": (None, [vp]),
@@ -289,11 +289,13 @@ class Context:
         _check(lib().pir_profile_enable(self._h, 1 if on else 0))
 
     def profile_read(self, reset: bool = True) -> dict:
+        """{family: (total_ms, launches, work)} since the last reset."""
         cap = 64
         names = (ctypes.c_char_p * cap)()
         ms = (ctypes.c_double * cap)()
         cnt = (ctypes.c_uint64 * cap)()
-        n = lib().pir_profile_read(self._h, cap, names, ms, cnt, 1 if reset else 0)
+        work = (ctypes.c_double * cap)()
+        n = lib().pir_profile_read(self._h, cap, names, ms, cnt, work, 1 if reset else 0)
         if n < 0:
             _check(n)
-        return {names[i].decode(): (ms[i], int(cnt[i])) for i in range(min(n, cap))}
+        return {names[i].decode(): (ms[i], int(cnt[i]), work[i]) for i in range(min(n, cap))}

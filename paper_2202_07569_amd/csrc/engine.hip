@@ -43,6 +43,7 @@ struct DevBuf {
 struct ProfRec {
     const char* name;
     hipEvent_t a, b;
+    double work;
 };
 
 struct pir_ctx {
@@ -60,12 +61,17 @@ struct pir_ctx {
     uint32_t* dfixcnt = nullptr;
     size_t fix_cap = 0;
     uint32_t chunk = 0;  // elements per chunk
+    uint32_t cus = 0;    // compute units
     uint64_t memo_cap = 0;
     std::map<std::string, DevBuf> ws;
     hipEvent_t done = nullptr;
     bool prof = false;
     std::vector<ProfRec> recs;
-    std::map<std::string, std::pair<double, uint64_t>> prof_acc;
+    struct ProfAcc {
+        double ms = 0, work = 0;
+        uint64_t launches = 0;
+    };
+    std::map<std::string, ProfAcc> prof_acc;
     std::map<std::pair<uint32_t, uint32_t>, uint64_t*> binom;  // (m, k) -> device table
 };
 
@@ -171,26 +177,32 @@ static Launch make_launch(pir_ctx* ctx, hipStream_t st) {
     lc.L = ctx->L;
     lc.LB = ctx->LB;
     lc.LL = ctx->LL;
+    lc.cus = ctx->cus;
     lc.fix = ctx->dfix;
     lc.fixcnt = ctx->dfixcnt;
     return lc;
 }
 
-// Profiling bracket: events on the launching stream around one kernel family's launch(es).
+// Profiling bracket: events on the launching stream around one kernel family's launch(es), with
+// the algorithmic work they do (butterflies for transforms, coefficients for the others).
 struct Prof {
     pir_ctx* ctx;
     const char* name;
     hipStream_t st;
+    double work;
     hipEvent_t a = nullptr;
-    Prof(pir_ctx* c, const char* n, hipStream_t s) : ctx(c), name(n), st(s) {
+    Prof(pir_ctx* c, const char* n, hipStream_t s, double w = 0) : ctx(c), name(n), st(s), work(w) {
         if (ctx->prof && hipEventCreate(&a) == hipSuccess) (void)hipEventRecord(a, st);
     }
     ~Prof() {
         if (!a) return;
         hipEvent_t b = nullptr;
-        if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, st) == hipSuccess) ctx->recs.push_back({name, a, b});
+        if (hipEventCreate(&b) == hipSuccess && hipEventRecord(b, st) == hipSuccess)
+            ctx->recs.push_back({name, a, b, work});
     }
 };
+
+static double bfly(const pir_ctx* ctx, size_t rows) { return (double)rows * (ctx->N / 2) * ctx->logN; }
 
 static int check_launch(pir_ctx* ctx) {
     hipError_t e = hipGetLastError();
@@ -256,6 +268,12 @@ extern "C" int pir_setup(const pir_params* params, pir_ctx** out) {
     };
     if (hipSetDevice(ctx->device) != hipSuccess) return cleanup(fail(PIR_E_DEVICE, "hipSetDevice failed"));
     if (cw::kernels_init() != hipSuccess) return cleanup(fail(PIR_E_DEVICE, "kernel attribute setup failed"));
+    {
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, ctx->device) != hipSuccess)
+            return cleanup(fail(PIR_E_DEVICE, "hipGetDeviceProperties failed"));
+        ctx->cus = (uint32_t)std::max(1, prop.multiProcessorCount);
+    }
     std::vector<uint64_t> tw;
     cw::host::build_twiddles(tw, ctx->primes, ctx->N);
     int rc;
@@ -502,14 +520,16 @@ extern "C" uint64_t pir_db_pair_count(const pir_db* db) { return db ? db->total_
 // the path
 // ------------------------------------------------------------------------------------------------
 struct Bufs {
-    uint64_t* X = nullptr;   // [E][3][LL][N]
-    uint64_t* R = nullptr;   // [E][L+2][L][N]
-    uint64_t* Ph = nullptr;  // [E][s][L][N]
+    uint64_t* X = nullptr;   // [E][3][LL][N]  tensor product over Q u B
+    uint64_t* C = nullptr;   // [E][3][L][N]   after scale-and-round, coefficient form
+    uint64_t* R = nullptr;   // [E][L+2][L][N] transformed relinearization staging
+    uint64_t* Ph = nullptr;  // [E][s][L][N]   transformed payload rows
 };
 
 static int get_bufs(pir_ctx* ctx, uint32_t E, uint32_t s, Bufs& b) {
     const size_t N = ctx->N, L = ctx->L, LL = ctx->LL;
     CW_TRY(ws_get_t(ctx, "X", (size_t)E * 3 * LL * N, &b.X));
+    CW_TRY(ws_get_t(ctx, "C", (size_t)E * 3 * L * N, &b.C));
     CW_TRY(ws_get_t(ctx, "R", (size_t)E * (L + 2) * L * N, &b.R));
     if (s) CW_TRY(ws_get_t(ctx, "Ph", (size_t)E * s * L * N, &b.Ph));
     return PIR_OK;
@@ -520,13 +540,13 @@ static int make_leaves(pir_ctx* ctx, const Launch& lc, const uint64_t* query, ui
     const size_t N = ctx->N, L = ctx->L, LL = ctx->LL;
     const size_t G = (size_t)2 * m, gmax = std::max<size_t>(1, ctx->fix_cap / N);
     {
-        Prof pr(ctx, "extend", lc.stream);
+        Prof pr(ctx, "extend", lc.stream, (double)G * N);
         for (size_t g0 = 0; g0 < G; g0 += gmax) {
             size_t g = std::min(gmax, G - g0);
             cw::launch_extend(lc, query + g0 * L * N, QX + g0 * LL * N, g);
         }
     }
-    Prof pr(ctx, "ntt_fwd", lc.stream);
+    Prof pr(ctx, "ntt_fwd", lc.stream, bfly(ctx, G * LL));
     cw::launch_ntt(lc, false, QX, QX, G * LL, (uint32_t)LL, 0);
     return check_launch(ctx);
 }
@@ -534,24 +554,20 @@ static int make_leaves(pir_ctx* ctx, const Launch& lc, const uint64_t* query, ui
 // Mult + Relin of `cnt` operand pairs (refs into leaves/nodes); result transformed over Q in sel.
 static void mult_relin(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint32_t* refs, const uint64_t* leaves,
                        const uint64_t* nodes, const pir_key* key, uint64_t* sel, uint32_t cnt) {
-    const uint32_t L = ctx->L, LL = ctx->LL;
+    const uint32_t LL = ctx->LL;
     {
-        Prof pr(ctx, "tensor", lc.stream);
-        cw::launch_tensor(lc, refs, leaves, nodes, b.X, cnt);
+        Prof pr(ctx, "ntt_inv_tensor", lc.stream, bfly(ctx, (size_t)cnt * 3 * LL));
+        cw::launch_ntt_inv_tensor(lc, refs, leaves, nodes, b.X, cnt);
     }
     {
-        Prof pr(ctx, "ntt_inv", lc.stream);
-        cw::launch_ntt(lc, true, b.X, b.X, (size_t)cnt * 3 * LL, LL, 0);
+        Prof pr(ctx, "scale", lc.stream, (double)cnt * 3 * ctx->N);
+        cw::launch_scale(lc, b.X, b.C, cnt);
     }
     {
-        Prof pr(ctx, "scale", lc.stream);
-        cw::launch_scale(lc, b.X, b.R, cnt, cw::SCALE_STAGING);
+        Prof pr(ctx, "ntt_digits", lc.stream, bfly(ctx, (size_t)cnt * (ctx->L + 2) * ctx->L));
+        cw::launch_ntt_digits(lc, b.C, b.R, cnt);
     }
-    {
-        Prof pr(ctx, "ntt_fwd", lc.stream);
-        cw::launch_ntt(lc, false, b.R, b.R, (size_t)cnt * (L + 2) * L, L, 0);
-    }
-    Prof pr(ctx, "relin_mac", lc.stream);
+    Prof pr(ctx, "relin_mac", lc.stream, (double)cnt * ctx->L * ctx->N);
     cw::launch_relin_mac(lc, b.R, key->d, sel, cnt);
 }
 
@@ -563,15 +579,15 @@ static void make_nodes(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint
         const uint32_t cnt = std::min(E, np - p0);
         mult_relin(ctx, lc, b, pairs + 2 * (size_t)p0, leaves, nullptr, key, tmp_sel, cnt);
         {
-            Prof pr(ctx, "ntt_inv", lc.stream);
+            Prof pr(ctx, "ntt_inv", lc.stream, bfly(ctx, (size_t)cnt * 2 * L));
             cw::launch_ntt(lc, true, tmp_sel, tmp_sel, (size_t)cnt * 2 * L, L, 0);
         }
         uint64_t* dst = nodes + (size_t)p0 * 2 * LL * N;
         {
-            Prof pr(ctx, "extend", lc.stream);
+            Prof pr(ctx, "extend", lc.stream, (double)2 * cnt * N);
             cw::launch_extend(lc, tmp_sel, dst, (size_t)2 * cnt);
         }
-        Prof pr(ctx, "ntt_fwd", lc.stream);
+        Prof pr(ctx, "ntt_fwd", lc.stream, bfly(ctx, (size_t)cnt * 2 * LL));
         cw::launch_ntt(lc, false, dst, dst, (size_t)cnt * 2 * LL, LL, 0);
     }
 }
@@ -619,10 +635,10 @@ static int answer_same_db(pir_ctx* ctx, hipStream_t st, const pir_db* db, uint32
                 roots(ctx, lc, b, k, refs, QX + q * qx_one, nodes ? nodes + q * node_one : nullptr, keys[q],
                       sel + q * sel_one, cnt);
             {
-                Prof pr(ctx, "payload_ntt", st);
+                Prof pr(ctx, "payload_ntt", st, bfly(ctx, (size_t)cnt * s * L));
                 cw::launch_ntt_payload(lc, db->dpay + (g.e0 + c0) * s * N, b.Ph, (size_t)cnt * s);
             }
-            Prof pr(ctx, "accumulate", st);
+            Prof pr(ctx, "accumulate", st, (double)B * cnt * s * 2 * L * N);
             for (uint32_t q0 = 0; q0 < B; q0 += cw::MAX_BATCH) {
                 cw::QueryPtrs qp;
                 const uint32_t nq = std::min<uint32_t>(cw::MAX_BATCH, B - q0);
@@ -636,7 +652,7 @@ static int answer_same_db(pir_ctx* ctx, hipStream_t st, const pir_db* db, uint32
         CW_TRY(check_launch(ctx));
     }
     for (uint32_t q = 0; q < B; ++q) {
-        Prof pr(ctx, "ntt_inv", st);
+        Prof pr(ctx, "ntt_inv", st, bfly(ctx, (size_t)s * 2 * L));
         cw::launch_ntt(lc, true, answers[q], answers[q], (size_t)s * 2 * L, L, 0);
     }
     return check_launch(ctx);
@@ -741,9 +757,8 @@ extern "C" int pir_mult(pir_ctx* ctx, const uint64_t* a, const uint64_t* b_, uin
     cw::launch_extend(lc, a, QX, 2);
     cw::launch_extend(lc, b_, QX + 2 * LL * N, 2);
     cw::launch_ntt(lc, false, QX, QX, 4 * LL, LL, 0);
-    cw::launch_tensor(lc, refs, QX, nullptr, b.X, 1);
-    cw::launch_ntt(lc, true, b.X, b.X, 3 * LL, LL, 0);
-    cw::launch_scale(lc, b.X, out, 1, cw::SCALE_PLAIN);
+    cw::launch_ntt_inv_tensor(lc, refs, QX, nullptr, b.X, 1);
+    cw::launch_scale(lc, b.X, out, 1);
     (void)L;
     return end_async(ctx, st);
 }
@@ -757,8 +772,7 @@ extern "C" int pir_relin(pir_ctx* ctx, const pir_key* key, const uint64_t* in, u
     Launch lc = make_launch(ctx, st);
     Bufs b;
     CW_TRY(get_bufs(ctx, 1, 0, b));
-    cw::launch_relin_stage(lc, in, b.R, 1);
-    cw::launch_ntt(lc, false, b.R, b.R, (size_t)(L + 2) * L, L, 0);
+    cw::launch_ntt_digits(lc, in, b.R, 1);
     cw::launch_relin_mac(lc, b.R, key->d, out, 1);
     cw::launch_ntt(lc, true, out, out, (size_t)2 * L, L, 0);
     return end_async(ctx, st);
@@ -827,14 +841,15 @@ extern "C" int pir_profile_enable(pir_ctx* ctx, int on) {
 }
 
 extern "C" int pir_profile_read(pir_ctx* ctx, uint32_t max, const char** names, double* total_ms, uint64_t* launches,
-                                int reset) {
+                                double* work, int reset) {
     CW_ENTER(ctx);
     for (auto& r : ctx->recs) {
         float ms = 0.f;
         if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
             auto& acc = ctx->prof_acc[r.name];
-            acc.first += ms;
-            acc.second += 1;
+            acc.ms += ms;
+            acc.work += r.work;
+            acc.launches += 1;
         }
         (void)hipEventDestroy(r.a);
         (void)hipEventDestroy(r.b);
@@ -845,8 +860,9 @@ extern "C" int pir_profile_read(pir_ctx* ctx, uint32_t max, const char** names, 
     for (auto& kv : ctx->prof_acc) {
         if (i < max) {
             if (names) names[i] = keep.insert(kv.first).first->c_str();
-            if (total_ms) total_ms[i] = kv.second.first;
-            if (launches) launches[i] = kv.second.second;
+            if (total_ms) total_ms[i] = kv.second.ms;
+            if (launches) launches[i] = kv.second.launches;
+            if (work) work[i] = kv.second.work;
         }
         ++i;
     }

@@ -7,9 +7,6 @@
 
 namespace cw {
 
-constexpr int NTT_THREADS = 512;
-constexpr int SCALE_STAGING = 0;
-constexpr int SCALE_PLAIN = 1;
 constexpr int MAX_BATCH = 32;  // queries per accumulate launch
 
 struct QueryPtrs {  // passed by value as a kernel argument
@@ -22,6 +19,7 @@ struct Launch {
     const CtxConst* K;    // device copy of the constants
     const uint64_t* tw;   // device twiddles [LL][4][N]
     uint32_t N, logN, L, LB, LL;
+    uint32_t cus;         // compute units of the device
     uint64_t* fix;        // fixup list for ambiguous conversions (capacity >= coefficients per launch)
     uint32_t* fixcnt;     // its counter; zero between launches
 };
@@ -30,11 +28,14 @@ hipError_t kernels_init();
 void launch_ntt(const Launch& lc, bool inverse, const uint64_t* in, uint64_t* out, size_t rows, uint32_t nl,
                 uint32_t pbase);
 void launch_ntt_payload(const Launch& lc, const uint16_t* pay, uint64_t* out, size_t rows_u16);
+// Transformed relinearization staging [E][L+2][L][N] straight from a coefficient-form [E][3][L][N].
+void launch_ntt_digits(const Launch& lc, const uint64_t* c3, uint64_t* out, uint32_t E);
 void launch_extend(const Launch& lc, const uint64_t* in, uint64_t* out, size_t G);
-void launch_tensor(const Launch& lc, const uint32_t* refs, const uint64_t* leaves, const uint64_t* nodes, uint64_t* X,
-                   uint32_t E);
-void launch_scale(const Launch& lc, const uint64_t* X, uint64_t* out, uint32_t E, int mode);
-void launch_relin_stage(const Launch& lc, const uint64_t* in, uint64_t* out, uint32_t E);
+// Tensor product (a0 b0, a0 b1 + a1 b0, a1 b1) of E operand pairs over Q u B, formed while loading
+// and inverse-transformed: X [E][3][LL][N] in coefficient form.
+void launch_ntt_inv_tensor(const Launch& lc, const uint32_t* refs, const uint64_t* leaves, const uint64_t* nodes,
+                           uint64_t* X, uint32_t E);
+void launch_scale(const Launch& lc, const uint64_t* X, uint64_t* out, uint32_t E);
 void launch_relin_mac(const Launch& lc, const uint64_t* R, const uint64_t* rlk, uint64_t* sel, uint32_t E);
 void launch_shoup_companions(const Launch& lc, const uint64_t* v, uint64_t* comp, size_t rows, uint32_t nl);
 void launch_gather_leaf(const Launch& lc, const uint32_t* refs, const uint64_t* leaves, uint64_t* sel, uint32_t E);

@@ -3,12 +3,15 @@
 // Data layout in HBM (u64 residues, limb-major inside a polynomial, N coefficients per limb):
 //   extended ciphertext  [2][LL][N]   over Q then B, transformed (NTT domain)
 //   tensor product       [E][3][LL][N]
-//   relin staging        [E][L+2][L][N]  rows 0..L-1: digit i reduced mod q_j; rows L, L+1: c0, c1
+//   product after scale  [E][3][L][N]  coefficient form over Q
+//   relin staging        [E][L+2][L][N]  transformed; rows 0..L-1: digit i mod q_j; rows L, L+1: c0, c1
 //   selector             [E][2][L][N]  transformed over Q
 //   payload transform    [E][s][L][N]
 //   accumulator/answer   [s][2][L][N]
 // A "limb-poly" is one row of N residues; its prime is prime_base + (row index mod nl).
 #include <hip/hip_runtime.h>
+
+#include <algorithm>
 
 #include "arith.h"
 #include "kernels.h"
@@ -20,152 +23,399 @@ constexpr int EW_THREADS = 256;
 static inline unsigned blocks_for(size_t n, int t = EW_THREADS) { return (unsigned)((n + t - 1) / t); }
 
 // ---------------------------------------------------------------------------------------------
-// Negacyclic NTT, one workgroup per limb-poly, the whole limb resident in LDS.
-// Forward: Cooley-Tukey with the psi powers merged into the twiddles (psi^bitrev), natural order in,
-// bit-reversed order out.  Inverse: Gentleman-Sande with psi^-bitrev, bit-reversed in, natural out,
-// scaled by N^-1.  Pointwise products of two forward transforms are negacyclic products.
+// Negacyclic NTT: one workgroup per limb-poly, register-resident radix-2^r passes.
+//
+// Forward: Cooley-Tukey butterflies with the psi powers merged into the twiddles (table index
+// m + i holds psi^bitrev(m + i)), stage s pairing the indices that differ in bit LOGN-1-s.  Inverse:
+// Gentleman-Sande butterflies with psi^-bitrev, the stages in reverse order, then N^-1.  Lazy
+// reduction (D. Harvey 2014): forward values stay in [0, 4p), inverse values in [0, 2p), with the
+// final reduction to [0, p) at the store (p < 2^61, so 4p < 2^63).
+//
+// The LOGN stages are cut into three passes of r_p stages.  In pass p a thread holds EPT = 2^R
+// elements: the 2^r_p combinations of the pass's index bits times 2^(R - r_p) "extra" bits, so
+// every butterfly of the pass is between two of its registers.  Between passes the values go
+// through LDS.  The first forward pass reads natural order (coalesced); the last forward pass
+// writes element u of thread t to position u*T + t (coalesced).  That permuted order is the
+// library's transformed layout: every transformed array comes from this kernel, products in that
+// domain are pointwise, and the inverse reads the same layout back.
 // ---------------------------------------------------------------------------------------------
+// A transform shape: 2^R elements per thread (T = N / 2^R threads) and NP passes of r(p) stages.
+template <int LOGN_, int R_, int NP_, int R0, int R1 = 0, int R2 = 0, int R3 = 0, int R4 = 0>
+struct Shape {
+    static constexpr int LOGN = LOGN_, R = R_, NP = NP_;
+    static constexpr int N = 1 << LOGN, EPT = 1 << R, T = 1 << (LOGN - R);
+    static constexpr int LDS_WORDS = N + N / 16;
+    __host__ __device__ static constexpr int r(int p) {
+        return p == 0 ? R0 : p == 1 ? R1 : p == 2 ? R2 : p == 3 ? R3 : R4;
+    }
+    __host__ __device__ static constexpr int S0(int p) {
+        int s = 0;
+        for (int q = 0; q < p; ++q) s += r(q);
+        return s;
+    }
+    static_assert(R0 == R, "the first pass reads whole coalesced rows");
+    static_assert(R0 + R1 + R2 + R3 + R4 == LOGN, "passes must cover every stage");
+};
+
+// Shapes used by the library (chosen by measurement on MI355X).
 template <int LOGN>
-__device__ __forceinline__ void ntt_fwd_lds(uint64_t* sm, const uint64_t* __restrict__ psi,
-                                            const uint64_t* __restrict__ psiq, uint64_t p) {
-    constexpr int N = 1 << LOGN;
-#pragma unroll 1
-    for (int lt = LOGN - 1, m = 1; lt >= 0; --lt, m <<= 1) {
-        const int t = 1 << lt;
-        for (int b = threadIdx.x; b < N / 2; b += NTT_THREADS) {
-            const int i = b >> lt, j = b & (t - 1);
-            const int j1 = (i << (lt + 1)) + j;
-            const uint64_t w = psi[m + i], wq = psiq[m + i];
-            const uint64_t U = sm[j1];
-            const uint64_t V = mul_shoup(sm[j1 + t], w, wq, p);
-            sm[j1] = add_mod(U, V, p);
-            sm[j1 + t] = sub_mod(U, V, p);
-        }
-        __syncthreads();
+struct DefaultShape;
+template <>
+struct DefaultShape<12> {
+    using type = Shape<12, 4, 3, 4, 4, 4>;
+};
+template <>
+struct DefaultShape<13> {
+    using type = Shape<13, 4, 4, 4, 3, 3, 3>;
+};
+template <>
+struct DefaultShape<14> {
+    using type = Shape<14, 4, 4, 4, 4, 3, 3>;
+};
+
+template <class Sh, int P>
+struct PassGeo {
+    static constexpr int R = Sh::R;
+    static constexpr int rp = Sh::r(P);
+    static constexpr int S0 = Sh::S0(P);                // stages before this pass
+    static constexpr int plo = Sh::LOGN - S0 - rp;      // lowest pass bit
+    static constexpr int x = R - rp;                    // extra bits
+    static_assert(plo == 0 || plo >= x, "extra bits must sit below a middle pass");
+};
+
+// Natural index of element u of thread tid in pass P.
+template <class Sh, int P>
+__device__ __forceinline__ uint32_t elem_index(uint32_t tid, uint32_t u) {
+    using G = PassGeo<Sh, P>;
+    constexpr int x = G::x, rp = G::rp, plo = G::plo;
+    if constexpr (plo == 0) {  // last pass: the extra bits sit just above the pass bits
+        return (u >> x) | ((u & ((1u << x) - 1u)) << rp) | (tid << G::R);
+    } else {  // extra bits lowest, then tid low part, pass bits, tid high part
+        const uint32_t ev = u & ((1u << x) - 1u), pv = u >> x;
+        const uint32_t tl = tid & ((1u << (plo - x)) - 1u), th = tid >> (plo - x);
+        return ev | (tl << x) | (pv << plo) | (th << (plo + rp));
     }
 }
 
-template <int LOGN>
-__device__ __forceinline__ void ntt_inv_lds(uint64_t* sm, const uint64_t* __restrict__ psi,
-                                            const uint64_t* __restrict__ psiq, uint64_t p) {
-    constexpr int N = 1 << LOGN;
-#pragma unroll 1
-    for (int lt = 0, m = N / 2; lt < LOGN; ++lt, m >>= 1) {
-        const int t = 1 << lt;
-        for (int b = threadIdx.x; b < N / 2; b += NTT_THREADS) {
-            const int i = b >> lt, j = b & (t - 1);
-            const int j1 = (i << (lt + 1)) + j;
-            const uint64_t w = psi[m + i], wq = psiq[m + i];
-            const uint64_t U = sm[j1], V = sm[j1 + t];
-            sm[j1] = add_mod(U, V, p);
-            sm[j1 + t] = mul_shoup(sub_mod(U, V, p), w, wq, p);
+__device__ __forceinline__ uint32_t lds_pad(uint32_t idx) { return idx + (idx >> 4); }
+
+template <class Sh, int P>
+__device__ __forceinline__ void fwd_pass(uint64_t* a, uint32_t tid, const uint64_t* __restrict__ psi,
+                                         const uint64_t* __restrict__ psiq, uint64_t p) {
+    using G = PassGeo<Sh, P>;
+    const uint64_t p2 = 2 * p;
+#pragma unroll
+    for (int sp = 0; sp < G::rp; ++sp) {
+        const int s = G::S0 + sp;
+        const int pb = G::x + G::rp - 1 - sp;
+#pragma unroll
+        for (int u0 = 0; u0 < Sh::EPT; ++u0) {
+            if (u0 & (1 << pb)) continue;
+            const int u1 = u0 | (1 << pb);
+            const uint32_t ti = (1u << s) + (elem_index<Sh, P>(tid, (uint32_t)u0) >> (Sh::LOGN - s));
+            const uint64_t w = psi[ti], wq = psiq[ti];
+            uint64_t X = a[u0];
+            X = X >= p2 ? X - p2 : X;
+            const uint64_t T = mul_shoup_lazy(a[u1], w, wq, p);
+            a[u0] = X + T;
+            a[u1] = X - T + p2;
         }
-        __syncthreads();
     }
 }
 
-template <int LOGN>
-__global__ __launch_bounds__(NTT_THREADS) void k_ntt_fwd(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
-                                                         const uint64_t* in, uint64_t* out, uint32_t nl,
-                                                         uint32_t pbase) {
-    constexpr int N = 1 << LOGN;
-    extern __shared__ uint64_t sm[];
-    const size_t g = blockIdx.x;
-    const uint32_t pi = pbase + (uint32_t)(g % nl);
-    const uint64_t p = K->p[pi];
-    const uint64_t* psi = tw + (size_t)pi * 4 * N;
-    const uint64_t* src = in + g * N;
-    for (int i = threadIdx.x; i < N; i += NTT_THREADS) sm[i] = src[i];
-    __syncthreads();
-    ntt_fwd_lds<LOGN>(sm, psi, psi + N, p);
-    uint64_t* dst = out + g * N;
-    for (int i = threadIdx.x; i < N; i += NTT_THREADS) dst[i] = sm[i];
+template <class Sh, int P>
+__device__ __forceinline__ void inv_pass(uint64_t* a, uint32_t tid, const uint64_t* __restrict__ psi,
+                                         const uint64_t* __restrict__ psiq, uint64_t p) {
+    using G = PassGeo<Sh, P>;
+    const uint64_t p2 = 2 * p;
+#pragma unroll
+    for (int sp = G::rp - 1; sp >= 0; --sp) {
+        const int s = G::S0 + sp;
+        const int pb = G::x + G::rp - 1 - sp;
+#pragma unroll
+        for (int u0 = 0; u0 < Sh::EPT; ++u0) {
+            if (u0 & (1 << pb)) continue;
+            const int u1 = u0 | (1 << pb);
+            const uint32_t ti = (1u << s) + (elem_index<Sh, P>(tid, (uint32_t)u0) >> (Sh::LOGN - s));
+            const uint64_t w = psi[ti], wq = psiq[ti];
+            const uint64_t X = a[u0], Y = a[u1];
+            const uint64_t Sm = X + Y;
+            a[u0] = Sm >= p2 ? Sm - p2 : Sm;
+            a[u1] = mul_shoup_lazy(X - Y + p2, w, wq, p);
+        }
+    }
 }
 
-template <int LOGN>
-__global__ __launch_bounds__(NTT_THREADS) void k_ntt_inv(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
-                                                         const uint64_t* in, uint64_t* out, uint32_t nl,
-                                                         uint32_t pbase) {
-    constexpr int N = 1 << LOGN;
-    extern __shared__ uint64_t sm[];
-    const size_t g = blockIdx.x;
-    const uint32_t pi = pbase + (uint32_t)(g % nl);
-    const uint64_t p = K->p[pi];
-    const uint64_t* psi = tw + (size_t)pi * 4 * N + 2 * N;
-    const uint64_t* src = in + g * N;
-    for (int i = threadIdx.x; i < N; i += NTT_THREADS) sm[i] = src[i];
+// registers of pass PA -> LDS -> registers of pass PB
+template <class Sh, int PA, int PB>
+__device__ __forceinline__ void exchange(uint64_t* a, uint64_t* sm, uint32_t tid) {
+#pragma unroll
+    for (int u = 0; u < Sh::EPT; ++u) sm[lds_pad(elem_index<Sh, PA>(tid, u))] = a[u];
     __syncthreads();
-    ntt_inv_lds<LOGN>(sm, psi, psi + N, p);
+#pragma unroll
+    for (int u = 0; u < Sh::EPT; ++u) a[u] = sm[lds_pad(elem_index<Sh, PB>(tid, u))];
+    __syncthreads();
+}
+
+template <class Sh, int P>
+__device__ __forceinline__ void fwd_passes(uint64_t* a, uint64_t* sm, uint32_t tid, const uint64_t* psi,
+                                           const uint64_t* psiq, uint64_t p) {
+    fwd_pass<Sh, P>(a, tid, psi, psiq, p);
+    if constexpr (P + 1 < Sh::NP) {
+        exchange<Sh, P, P + 1>(a, sm, tid);
+        fwd_passes<Sh, P + 1>(a, sm, tid, psi, psiq, p);
+    }
+}
+
+template <class Sh, int P>
+__device__ __forceinline__ void inv_passes(uint64_t* a, uint64_t* sm, uint32_t tid, const uint64_t* psi,
+                                           const uint64_t* psiq, uint64_t p) {
+    inv_pass<Sh, P>(a, tid, psi, psiq, p);
+    if constexpr (P > 0) {
+        exchange<Sh, P, P - 1>(a, sm, tid);
+        inv_passes<Sh, P - 1>(a, sm, tid, psi, psiq, p);
+    }
+}
+
+// ---------------------------------------------------------------------------------------------
+// Row drivers: one workgroup per row.  A row policy supplies prime(g), load(g, tid, a) (the EPT
+// inputs of thread tid in the first pass's pattern: natural order for the forward transform, the
+// transformed layout for the inverse) and store(g, tid, u, v) for one reduced output.
+// ---------------------------------------------------------------------------------------------
+template <class Sh, class Row>
+__device__ __forceinline__ void ntt_fwd_row(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
+                                            const Row& row) {
+    __shared__ uint64_t sm[Sh::LDS_WORDS];
+    const uint32_t tid = threadIdx.x;
+    const size_t g = blockIdx.x;
+    uint64_t a[Sh::EPT];
+    row.load(g, tid, a);
+    const uint32_t pi = row.prime(g);
+    const uint64_t p = K->p[pi];
+    const uint64_t* psi = tw + (size_t)pi * 4 * Sh::N;
+    fwd_passes<Sh, 0>(a, sm, tid, psi, psi + Sh::N, p);
+    const uint64_t p2 = 2 * p;
+#pragma unroll
+    for (int u = 0; u < Sh::EPT; ++u) {
+        uint64_t v = a[u];
+        v = v >= p2 ? v - p2 : v;
+        row.store(g, tid, u, v >= p ? v - p : v);
+    }
+}
+
+template <class Sh, class Row>
+__device__ __forceinline__ void ntt_inv_row(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
+                                            const Row& row) {
+    __shared__ uint64_t sm[Sh::LDS_WORDS];
+    const uint32_t tid = threadIdx.x;
+    const size_t g = blockIdx.x;
+    uint64_t a[Sh::EPT];
+    row.load(g, tid, a);
+    const uint32_t pi = row.prime(g);
+    const uint64_t p = K->p[pi];
+    const uint64_t* psi = tw + (size_t)pi * 4 * Sh::N + 2 * Sh::N;
+    inv_passes<Sh, Sh::NP - 1>(a, sm, tid, psi, psi + Sh::N, p);
     const uint64_t ni = K->ninv[pi], niq = K->ninvq[pi];
-    uint64_t* dst = out + g * N;
-    for (int i = threadIdx.x; i < N; i += NTT_THREADS) dst[i] = mul_shoup(sm[i], ni, niq, p);
+#pragma unroll
+    for (int u = 0; u < Sh::EPT; ++u) {
+        const uint64_t v = mul_shoup_lazy(a[u], ni, niq, p);
+        row.store(g, tid, u, v >= p ? v - p : v);
+    }
 }
 
-// Payload rows: block g = (e s + r) L + j lifts uint16 row (e, r) (values < 2^16 < q_j, so the
-// residue is the value itself) and transforms it modulo q_j.
-template <int LOGN>
-__global__ __launch_bounds__(NTT_THREADS) void k_ntt_payload(const CtxConst* __restrict__ K,
-                                                             const uint64_t* __restrict__ tw,
-                                                             const uint16_t* __restrict__ pay,
-                                                             uint64_t* __restrict__ out) {
-    constexpr int N = 1 << LOGN;
-    extern __shared__ uint64_t sm[];
-    const uint32_t L = K->L;
-    const size_t g = blockIdx.x;
-    const uint32_t pi = (uint32_t)(g % L);
-    const uint64_t p = K->p[pi];
-    const uint64_t* psi = tw + (size_t)pi * 4 * N;
-    const uint16_t* src = pay + (g / L) * N;
-    for (int i = threadIdx.x; i < N; i += NTT_THREADS) sm[i] = src[i];
-    __syncthreads();
-    ntt_fwd_lds<LOGN>(sm, psi, psi + N, p);
-    uint64_t* dst = out + g * N;
-    for (int i = threadIdx.x; i < N; i += NTT_THREADS) dst[i] = sm[i];
+// Forward outputs go to the transformed layout (u*T + tid); inverse outputs to natural order.
+template <class Sh>
+__device__ __forceinline__ size_t transformed_pos(size_t g, uint32_t tid, int u) {
+    return g * Sh::N + (size_t)u * Sh::T + tid;
 }
+template <class Sh>
+__device__ __forceinline__ size_t natural_pos(size_t g, uint32_t tid, int u) {
+    return g * Sh::N + elem_index<Sh, 0>(tid, u);
+}
+
+// Plain rows of a [rows][N] array, prime = pbase + row mod nl.
+template <class Sh>
+struct RowsFwdU64 {
+    const uint64_t* in;
+    uint64_t* out;
+    uint32_t nl, pbase;
+    __device__ uint32_t prime(size_t g) const { return pbase + (uint32_t)(g % nl); }
+    __device__ void load(size_t g, uint32_t tid, uint64_t* a) const {
+#pragma unroll
+        for (int u = 0; u < Sh::EPT; ++u) a[u] = in[natural_pos<Sh>(g, tid, u)];
+    }
+    __device__ void store(size_t g, uint32_t tid, int u, uint64_t v) const { out[transformed_pos<Sh>(g, tid, u)] = v; }
+};
+
+template <class Sh>
+struct RowsInvU64 {
+    const uint64_t* in;
+    uint64_t* out;
+    uint32_t nl, pbase;
+    __device__ uint32_t prime(size_t g) const { return pbase + (uint32_t)(g % nl); }
+    __device__ void load(size_t g, uint32_t tid, uint64_t* a) const {
+#pragma unroll
+        for (int u = 0; u < Sh::EPT; ++u) a[u] = in[transformed_pos<Sh>(g, tid, u)];
+    }
+    __device__ void store(size_t g, uint32_t tid, int u, uint64_t v) const { out[natural_pos<Sh>(g, tid, u)] = v; }
+};
+
+// Payload rows: row g = (e s + r) L + j lifts uint16 row (e, r) (values < 2^16 < q_j, so the
+// residue is the value itself) and transforms it modulo q_j.
+template <class Sh>
+struct RowsPayload {
+    const uint16_t* pay;
+    uint64_t* out;
+    uint32_t L;
+    __device__ uint32_t prime(size_t g) const { return (uint32_t)(g % L); }
+    __device__ void load(size_t g, uint32_t tid, uint64_t* a) const {
+        const uint16_t* src = pay + (g / L) * Sh::N;
+#pragma unroll
+        for (int u = 0; u < Sh::EPT; ++u) a[u] = src[elem_index<Sh, 0>(tid, u)];
+    }
+    __device__ void store(size_t g, uint32_t tid, int u, uint64_t v) const { out[transformed_pos<Sh>(g, tid, u)] = v; }
+};
+
+// Relinearization staging rows: row (e, i, j) of [E][L+2][L][N] is digit i (row 2L+i of the
+// coefficient-form product [E][3][L][N]) reduced mod q_j for i < L, and c0 / c1 limb j for
+// i = L, L+1; the reduction is done while loading.
+template <class Sh>
+struct RowsDigits {
+    const uint64_t* c3;
+    uint64_t* out;
+    const CtxConst* K;
+    uint32_t L;
+    __device__ uint32_t prime(size_t g) const { return (uint32_t)(g % L); }
+    __device__ void load(size_t g, uint32_t tid, uint64_t* a) const {
+        const uint32_t j = (uint32_t)(g % L);
+        const size_t ei = g / L;
+        const uint32_t i = (uint32_t)(ei % (L + 2));
+        const size_t e = ei / (L + 2);
+        const uint64_t* base = c3 + e * 3 * L * Sh::N;
+        const uint64_t* src = i < L ? base + ((size_t)2 * L + i) * Sh::N : base + ((size_t)(i - L) * L + j) * Sh::N;
+        if (i < L && i != j) {
+            const uint64_t p = K->p[j], r1 = K->r1[j];
+#pragma unroll
+            for (int u = 0; u < Sh::EPT; ++u) a[u] = reduce64(src[elem_index<Sh, 0>(tid, u)], p, r1);
+        } else {
+#pragma unroll
+            for (int u = 0; u < Sh::EPT; ++u) a[u] = src[elem_index<Sh, 0>(tid, u)];
+        }
+    }
+    __device__ void store(size_t g, uint32_t tid, int u, uint64_t v) const { out[transformed_pos<Sh>(g, tid, u)] = v; }
+};
+
+// Tensor product rows fused into the inverse transform: row g = (e 3 + r) LL + l of X is
+// (a0 b0, a0 b1 + a1 b0, a1 b1)[r] in limb l of element e's operands, formed while loading.
+template <class Sh>
+struct RowsTensor {
+    const uint32_t* refs;
+    const uint64_t* leaves;
+    const uint64_t* nodes;
+    uint64_t* out;
+    const CtxConst* K;
+    uint32_t LL;
+    __device__ uint32_t prime(size_t g) const { return (uint32_t)(g % LL); }
+    __device__ void load(size_t g, uint32_t tid, uint64_t* a) const {
+        constexpr int N = Sh::N, T = Sh::T;
+        const uint32_t l = (uint32_t)(g % LL);
+        const size_t er = g / LL;
+        const uint32_t r = (uint32_t)(er % 3);
+        const size_t e = er / 3;
+        const size_t ct = (size_t)2 * LL * N;
+        const uint32_t ra = refs[2 * e], rb = refs[2 * e + 1];
+        const uint64_t* A = (ra & REF_NODE) ? nodes + (size_t)(ra & ~REF_NODE) * ct : leaves + (size_t)ra * ct;
+        const uint64_t* B = (rb & REF_NODE) ? nodes + (size_t)(rb & ~REF_NODE) * ct : leaves + (size_t)rb * ct;
+        const uint64_t p = K->p[l], mu = K->bar_mu[l];
+        const uint32_t s = K->bar_s[l];
+        const size_t o0 = (size_t)l * N + tid, o1 = (size_t)(LL + l) * N + tid;
+        if (r == 0) {
+#pragma unroll
+            for (int u = 0; u < Sh::EPT; ++u) a[u] = mul_barrett(A[o0 + u * T], B[o0 + u * T], p, mu, s);
+        } else if (r == 2) {
+#pragma unroll
+            for (int u = 0; u < Sh::EPT; ++u) a[u] = mul_barrett(A[o1 + u * T], B[o1 + u * T], p, mu, s);
+        } else {
+#pragma unroll
+            for (int u = 0; u < Sh::EPT; ++u)
+                a[u] = add_mod(mul_barrett(A[o0 + u * T], B[o1 + u * T], p, mu, s),
+                               mul_barrett(A[o1 + u * T], B[o0 + u * T], p, mu, s), p);
+        }
+    }
+    __device__ void store(size_t g, uint32_t tid, int u, uint64_t v) const { out[natural_pos<Sh>(g, tid, u)] = v; }
+};
+
+template <class Sh>
+__global__ __launch_bounds__(Sh::T) void k_ntt_fwd(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
+                                                   const uint64_t* in, uint64_t* out, uint32_t nl, uint32_t pbase) {
+    ntt_fwd_row<Sh>(K, tw, RowsFwdU64<Sh>{in, out, nl, pbase});
+}
+template <class Sh>
+__global__ __launch_bounds__(Sh::T) void k_ntt_inv(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
+                                                   const uint64_t* in, uint64_t* out, uint32_t nl, uint32_t pbase) {
+    ntt_inv_row<Sh>(K, tw, RowsInvU64<Sh>{in, out, nl, pbase});
+}
+template <class Sh>
+__global__ __launch_bounds__(Sh::T) void k_ntt_payload(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
+                                                       const uint16_t* __restrict__ pay, uint64_t* __restrict__ out) {
+    ntt_fwd_row<Sh>(K, tw, RowsPayload<Sh>{pay, out, K->L});
+}
+template <class Sh>
+__global__ __launch_bounds__(Sh::T) void k_ntt_digits(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
+                                                      const uint64_t* __restrict__ c3, uint64_t* __restrict__ out) {
+    ntt_fwd_row<Sh>(K, tw, RowsDigits<Sh>{c3, out, K, K->L});
+}
+template <class Sh>
+__global__ __launch_bounds__(Sh::T) void k_ntt_inv_tensor(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
+                                                          const uint32_t* __restrict__ refs,
+                                                          const uint64_t* __restrict__ leaves,
+                                                          const uint64_t* __restrict__ nodes, uint64_t* __restrict__ X) {
+    ntt_inv_row<Sh>(K, tw, RowsTensor<Sh>{refs, leaves, nodes, X, K, K->LL});
+}
+
+#define CW_BY_N(LOGNV, CALL)                                 \
+    switch (LOGNV) {                                         \
+        case 12: { using Sh = DefaultShape<12>::type; CALL; } break; \
+        case 13: { using Sh = DefaultShape<13>::type; CALL; } break; \
+        case 14: { using Sh = DefaultShape<14>::type; CALL; } break; \
+    }
 
 void launch_ntt(const Launch& lc, bool inverse, const uint64_t* in, uint64_t* out, size_t rows, uint32_t nl,
                 uint32_t pbase) {
     if (!rows) return;
-    const size_t lds = (size_t)lc.N * 8;
-    dim3 grid((unsigned)rows), block(NTT_THREADS);
-#define CW_NTT_CASE(LG)                                                                                          \
-    case LG:                                                                                                     \
-        if (inverse)                                                                                             \
-            hipLaunchKernelGGL(k_ntt_inv<LG>, grid, block, lds, lc.stream, lc.K, lc.tw, in, out, nl, pbase);   \
-        else                                                                                                     \
-            hipLaunchKernelGGL(k_ntt_fwd<LG>, grid, block, lds, lc.stream, lc.K, lc.tw, in, out, nl, pbase);   \
-        break;
-    switch (lc.logN) {
-        CW_NTT_CASE(12)
-        CW_NTT_CASE(13)
-        CW_NTT_CASE(14)
-    }
-#undef CW_NTT_CASE
+    if (inverse)
+        CW_BY_N(lc.logN, hipLaunchKernelGGL(k_ntt_inv<Sh>, dim3((unsigned)rows), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,
+                                            in, out, nl, pbase))
+    else
+        CW_BY_N(lc.logN, hipLaunchKernelGGL(k_ntt_fwd<Sh>, dim3((unsigned)rows), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,
+                                            in, out, nl, pbase))
 }
 
-// Let the transform kernels use the whole limb in dynamic LDS (128 KiB at N = 16384).
-hipError_t kernels_init() {
-    hipError_t e = hipSuccess;
-#define CW_ATTR(K, LG)                                                                                  \
-    if (e == hipSuccess)                                                                                \
-        e = hipFuncSetAttribute((const void*)K<LG>, hipFuncAttributeMaxDynamicSharedMemorySize, 8 << LG);
-    CW_ATTR(k_ntt_fwd, 12) CW_ATTR(k_ntt_fwd, 13) CW_ATTR(k_ntt_fwd, 14)
-    CW_ATTR(k_ntt_inv, 12) CW_ATTR(k_ntt_inv, 13) CW_ATTR(k_ntt_inv, 14)
-    CW_ATTR(k_ntt_payload, 12) CW_ATTR(k_ntt_payload, 13) CW_ATTR(k_ntt_payload, 14)
-#undef CW_ATTR
-    return e;
+void launch_ntt_digits(const Launch& lc, const uint64_t* c3, uint64_t* out, uint32_t E) {
+    if (!E) return;
+    const size_t rows = (size_t)E * (lc.L + 2) * lc.L;
+    CW_BY_N(lc.logN, hipLaunchKernelGGL(k_ntt_digits<Sh>, dim3((unsigned)rows), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,
+                                        c3, out))
+}
+
+void launch_ntt_inv_tensor(const Launch& lc, const uint32_t* refs, const uint64_t* leaves, const uint64_t* nodes,
+                           uint64_t* X, uint32_t E) {
+    if (!E) return;
+    const size_t rows = (size_t)E * 3 * lc.LL;
+    CW_BY_N(lc.logN, hipLaunchKernelGGL(k_ntt_inv_tensor<Sh>, dim3((unsigned)rows), dim3(Sh::T), 0, lc.stream, lc.K,
+                                        lc.tw, refs, leaves, nodes, X))
 }
 
 void launch_ntt_payload(const Launch& lc, const uint16_t* pay, uint64_t* out, size_t rows_u16) {
     if (!rows_u16) return;
-    const size_t lds = (size_t)lc.N * 8;
-    dim3 grid((unsigned)(rows_u16 * lc.L)), block(NTT_THREADS);
-    switch (lc.logN) {
-        case 12: hipLaunchKernelGGL(k_ntt_payload<12>, grid, block, lds, lc.stream, lc.K, lc.tw, pay, out); break;
-        case 13: hipLaunchKernelGGL(k_ntt_payload<13>, grid, block, lds, lc.stream, lc.K, lc.tw, pay, out); break;
-        case 14: hipLaunchKernelGGL(k_ntt_payload<14>, grid, block, lds, lc.stream, lc.K, lc.tw, pay, out); break;
-    }
+    const size_t rows = rows_u16 * lc.L;
+    CW_BY_N(lc.logN, hipLaunchKernelGGL(k_ntt_payload<Sh>, dim3((unsigned)rows), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,
+                                        pay, out))
 }
+
+// Static LDS of the transform kernels stays below the 160 KiB per workgroup of gfx950; nothing to
+// raise at run time.
+hipError_t kernels_init() { return hipSuccess; }
 
 // ---------------------------------------------------------------------------------------------
 // Exact centred extension Q -> Q u B of coefficient-form polynomials: in [G][L][N] -> out [G][LL][N]
@@ -228,42 +478,9 @@ void launch_extend(const Launch& lc, const uint64_t* in, uint64_t* out, size_t G
 }
 
 // ---------------------------------------------------------------------------------------------
-// Tensor product in the transformed domain over Q u B: (a0 b0, a0 b1 + a1 b0, a1 b1)
-// ---------------------------------------------------------------------------------------------
-__global__ void k_tensor(const CtxConst* __restrict__ K, const uint32_t* __restrict__ refs,
-                         const uint64_t* __restrict__ leaves, const uint64_t* __restrict__ nodes,
-                         uint64_t* __restrict__ X, uint32_t E) {
-    const uint32_t N = K->N, LL = K->LL;
-    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (size_t)E * LL * N) return;
-    const size_t c = gid % N, el = gid / N;
-    const uint32_t l = (uint32_t)(el % LL);
-    const size_t e = el / LL;
-    const size_t ct = (size_t)2 * LL * N;
-    const uint32_t ra = refs[2 * e], rb = refs[2 * e + 1];
-    const uint64_t* A = (ra & REF_NODE) ? nodes + (size_t)(ra & ~REF_NODE) * ct : leaves + (size_t)ra * ct;
-    const uint64_t* B = (rb & REF_NODE) ? nodes + (size_t)(rb & ~REF_NODE) * ct : leaves + (size_t)rb * ct;
-    const uint64_t p = K->p[l], mu = K->bar_mu[l];
-    const uint32_t s = K->bar_s[l];
-    const size_t o0 = (size_t)l * N + c, o1 = (size_t)(LL + l) * N + c;
-    const uint64_t a0 = A[o0], a1 = A[o1], b0 = B[o0], b1 = B[o1];
-    uint64_t* x = X + e * 3 * LL * N + (size_t)l * N + c;
-    x[0] = mul_barrett(a0, b0, p, mu, s);
-    x[(size_t)LL * N] = add_mod(mul_barrett(a0, b1, p, mu, s), mul_barrett(a1, b0, p, mu, s), p);
-    x[(size_t)2 * LL * N] = mul_barrett(a1, b1, p, mu, s);
-}
-
-void launch_tensor(const Launch& lc, const uint32_t* refs, const uint64_t* leaves, const uint64_t* nodes, uint64_t* X,
-                   uint32_t E) {
-    if (!E) return;
-    hipLaunchKernelGGL(k_tensor, dim3(blocks_for((size_t)E * lc.LL * lc.N)), dim3(EW_THREADS), 0, lc.stream, lc.K,
-                       refs, leaves, nodes, X, E);
-}
-
-// ---------------------------------------------------------------------------------------------
 // Exact scale-and-round of a coefficient-form tensor product X over Q u B:
 //   r = [t X]_q (centred, exact Q -> B), y = (t X - r) / q in B, c = y (exact centred B -> Q).
-// mode SCALE_STAGING writes the relinearization staging layout, SCALE_PLAIN writes [E][3][L][N].
+// Output: coefficient form [E][3][L][N].
 // ---------------------------------------------------------------------------------------------
 template <int NL, int NB>
 __device__ __forceinline__ bool scale_coeff(const CtxConst* K, const uint64_t* x, size_t xs, uint64_t* cq, bool exact) {
@@ -291,48 +508,29 @@ __device__ __forceinline__ bool scale_coeff(const CtxConst* K, const uint64_t* x
 }
 
 template <int NL>
-__device__ __forceinline__ void scale_store(const CtxConst* K, const uint64_t* cq, uint64_t* out, size_t e, uint32_t r,
-                                            size_t c, int mode) {
+__device__ __forceinline__ void scale_store(const CtxConst* K, const uint64_t* cq, uint64_t* out, size_t er, size_t c) {
     const uint32_t N = K->N, L = K->L;
-    if (mode == SCALE_PLAIN) {
-        uint64_t* o = out + ((e * 3 + r) * L) * N + c;
+    uint64_t* o = out + er * L * N + c;
 #pragma unroll
-        for (int i = 0; i < NL; ++i)
-            if (i < (int)L) o[(size_t)i * N] = cq[i];
-        return;
-    }
-    uint64_t* base = out + e * (L + 2) * L * N + c;
-    if (r < 2) {
-        uint64_t* o = base + (size_t)(L + r) * L * N;
-#pragma unroll
-        for (int i = 0; i < NL; ++i)
-            if (i < (int)L) o[(size_t)i * N] = cq[i];
-    } else {
-#pragma unroll
-        for (int i = 0; i < NL; ++i)
-            if (i < (int)L)
-                for (uint32_t j = 0; j < L; ++j)
-                    base[((size_t)i * L + j) * N] = (i == (int)j) ? cq[i] : reduce64(cq[i], K->p[j], K->r1[j]);
-    }
+    for (int i = 0; i < NL; ++i)
+        if (i < (int)L) o[(size_t)i * N] = cq[i];
 }
 
 template <int NL, int NB>
 __global__ void k_scale(const CtxConst* __restrict__ K, const uint64_t* __restrict__ X, uint64_t* __restrict__ out,
-                        uint32_t E, int mode, uint64_t* fix, uint32_t* fixcnt) {
+                        uint32_t E, uint64_t* fix, uint32_t* fixcnt) {
     const uint32_t N = K->N, LL = K->LL;
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (size_t)E * 3 * N) return;
     const size_t c = gid % N, er = gid / N;
-    const uint32_t r = (uint32_t)(er % 3);
-    const size_t e = er / 3;
     uint64_t cq[NL];
     if (scale_coeff<NL, NB>(K, X + er * LL * N + c, N, cq, false)) fix[atomicAdd(fixcnt, 1u)] = gid;
-    scale_store<NL>(K, cq, out, e, r, c, mode);
+    scale_store<NL>(K, cq, out, er, c);
 }
 
 template <int NL, int NB>
 __global__ void k_scale_fix(const CtxConst* __restrict__ K, const uint64_t* __restrict__ X, uint64_t* __restrict__ out,
-                            int mode, uint64_t* fix, uint32_t* fixcnt) {
+                            uint64_t* fix, uint32_t* fixcnt) {
     const uint32_t N = K->N, LL = K->LL;
     const uint32_t n = *fixcnt;
     for (uint32_t f = threadIdx.x; f < n; f += blockDim.x) {
@@ -340,20 +538,19 @@ __global__ void k_scale_fix(const CtxConst* __restrict__ K, const uint64_t* __re
         const size_t c = gid % N, er = gid / N;
         uint64_t cq[NL];
         scale_coeff<NL, NB>(K, X + er * LL * N + c, N, cq, true);
-        scale_store<NL>(K, cq, out, er / 3, (uint32_t)(er % 3), c, mode);
+        scale_store<NL>(K, cq, out, er, c);
     }
     __syncthreads();
     if (threadIdx.x == 0) *fixcnt = 0;
 }
 
-void launch_scale(const Launch& lc, const uint64_t* X, uint64_t* out, uint32_t E, int mode) {
+void launch_scale(const Launch& lc, const uint64_t* X, uint64_t* out, uint32_t E) {
     if (!E) return;
     const unsigned nb = blocks_for((size_t)E * 3 * lc.N);
 #define CW_SCALE(NLV, NBV)                                                                                    \
-    hipLaunchKernelGGL((k_scale<NLV, NBV>), dim3(nb), dim3(EW_THREADS), 0, lc.stream, lc.K, X, out, E, mode, \
-                       lc.fix, lc.fixcnt);                                                                    \
-    hipLaunchKernelGGL((k_scale_fix<NLV, NBV>), dim3(1), dim3(256), 0, lc.stream, lc.K, X, out, mode, lc.fix, \
-                       lc.fixcnt);
+    hipLaunchKernelGGL((k_scale<NLV, NBV>), dim3(nb), dim3(EW_THREADS), 0, lc.stream, lc.K, X, out, E, lc.fix, \
+                       lc.fixcnt);                                                                            \
+    hipLaunchKernelGGL((k_scale_fix<NLV, NBV>), dim3(1), dim3(256), 0, lc.stream, lc.K, X, out, lc.fix, lc.fixcnt);
     if (lc.L <= 4 && lc.LB <= 5) {
         CW_SCALE(4, 5)
     } else if (lc.L <= 8 && lc.LB <= 9) {
@@ -362,31 +559,6 @@ void launch_scale(const Launch& lc, const uint64_t* X, uint64_t* out, uint32_t E
         CW_SCALE(12, 13)
     }
 #undef CW_SCALE
-}
-
-// Relinearization staging from a plain [E][3][L][N] coefficient-form ciphertext.
-__global__ void k_relin_stage(const CtxConst* __restrict__ K, const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
-                              uint32_t E) {
-    const uint32_t N = K->N, L = K->L;
-    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (size_t)E * N) return;
-    const size_t c = gid % N, e = gid / N;
-    const uint64_t* src = in + e * 3 * L * N + c;
-    uint64_t* base = out + e * (L + 2) * L * N + c;
-    for (uint32_t j = 0; j < L; ++j) {
-        base[((size_t)L * L + j) * N] = src[(size_t)j * N];
-        base[((size_t)(L + 1) * L + j) * N] = src[(size_t)(L + j) * N];
-    }
-    for (uint32_t i = 0; i < L; ++i) {
-        const uint64_t d = src[(size_t)(2 * L + i) * N];
-        for (uint32_t j = 0; j < L; ++j) base[((size_t)i * L + j) * N] = (i == j) ? d : reduce64(d, K->p[j], K->r1[j]);
-    }
-}
-
-void launch_relin_stage(const Launch& lc, const uint64_t* in, uint64_t* out, uint32_t E) {
-    if (!E) return;
-    hipLaunchKernelGGL(k_relin_stage, dim3(blocks_for((size_t)E * lc.N)), dim3(EW_THREADS), 0, lc.stream, lc.K, in,
-                       out, E);
 }
 
 // ---------------------------------------------------------------------------------------------
