@@ -52,6 +52,7 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="override the database size")
     ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle sample elements (0: skip)")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--chunk", type=int, default=0, help="elements per processing chunk (0: library default)")
     return ap.parse_args()
 
 
@@ -78,7 +79,7 @@ def main():
     B = max(1, args.batch)
     log(f"workload {cfg.name}: N={cfg.N} L={cfg.L} k={cfg.k} m={cfg.m} n={n} s={cfg.s} batch={B}")
     rlk, queries, payload = synthetic_inputs(cfg, n, B)
-    ctx = Context(cfg.N, cfg.primes, cfg.t)
+    ctx = Context(cfg.N, cfg.primes, cfg.t, chunk_elems=args.chunk)
     key = ctx.load_key(rlk)
     ids = datagen.identifier_permutation(cfg, n) if not cfg.keyword else None
     if cfg.keyword:
@@ -146,7 +147,7 @@ def main():
         "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"index PIR {cfg.name}: N={cfg.N}, {cfg.L} primes ({math.prod(cfg.primes).bit_length()}"
                                f" bits), t={cfg.t}, k={cfg.k}, m={cfg.m}, n={n}, s={cfg.s}",
-                   "batch_queries": B},
+                   "batch_queries": B, "chunk_elems": args.chunk or None},
         "plain": {"value": n * args.steps / t_plain, "unit": "elements/s", "ms_per_query": t_plain / args.steps * 1e3,
                   **lat(per_plain)},
         "batched": {"value": value, "ms_per_step": ms_step, **lat(per_b)},
@@ -156,7 +157,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-NTT_FAMILIES = ("ntt_fwd", "ntt_inv", "ntt_inv_tensor", "ntt_digits", "payload_ntt")
+NTT_FAMILIES = ("ntt_fwd", "ntt_inv", "ntt_inv_tensor", "ntt_digits", "relin", "payload_ntt")
 
 
 def roofline(prof, steps, N):

@@ -260,7 +260,7 @@ extern "C" int pir_setup(const pir_params* params, pir_ctx** out) {
     ctx->primes.insert(ctx->primes.end(), B.begin(), B.end());
     cw::host::build_const(ctx->K, ctx->N, q, B, ctx->t);
     if (params->chunk_elems > 4096) return cleanup_early(fail(PIR_E_INVALID, "chunk_elems must be <= 4096"), ctx);
-    ctx->chunk = params->chunk_elems ? params->chunk_elems : (ctx->N >= 16384 ? 64 : 128);
+    ctx->chunk = params->chunk_elems ? params->chunk_elems : (ctx->N >= 16384 ? 128 : 256);
     ctx->memo_cap = params->memo_bytes ? params->memo_bytes : (ctx->budget ? ctx->budget / 4 : (8ull << 30));
     auto cleanup = [&](int rc) {
         pir_free(ctx);
@@ -522,7 +522,7 @@ extern "C" uint64_t pir_db_pair_count(const pir_db* db) { return db ? db->total_
 struct Bufs {
     uint64_t* X = nullptr;   // [E][3][LL][N]  tensor product over Q u B
     uint64_t* C = nullptr;   // [E][3][L][N]   after scale-and-round, coefficient form
-    uint64_t* R = nullptr;   // [E][L+2][L][N] transformed relinearization staging
+    uint64_t* R = nullptr;   // [E][L+2][L][N] transformed digits (only where key switching is staged)
     uint64_t* Ph = nullptr;  // [E][s][L][N]   transformed payload rows
 };
 
@@ -530,7 +530,7 @@ static int get_bufs(pir_ctx* ctx, uint32_t E, uint32_t s, Bufs& b) {
     const size_t N = ctx->N, L = ctx->L, LL = ctx->LL;
     CW_TRY(ws_get_t(ctx, "X", (size_t)E * 3 * LL * N, &b.X));
     CW_TRY(ws_get_t(ctx, "C", (size_t)E * 3 * L * N, &b.C));
-    CW_TRY(ws_get_t(ctx, "R", (size_t)E * (L + 2) * L * N, &b.R));
+    if (cw::relin_needs_staging(ctx->logN)) CW_TRY(ws_get_t(ctx, "R", (size_t)E * (L + 2) * L * N, &b.R));
     if (s) CW_TRY(ws_get_t(ctx, "Ph", (size_t)E * s * L * N, &b.Ph));
     return PIR_OK;
 }
@@ -563,12 +563,8 @@ static void mult_relin(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint
         Prof pr(ctx, "scale", lc.stream, (double)cnt * 3 * ctx->N);
         cw::launch_scale(lc, b.X, b.C, cnt);
     }
-    {
-        Prof pr(ctx, "ntt_digits", lc.stream, bfly(ctx, (size_t)cnt * (ctx->L + 2) * ctx->L));
-        cw::launch_ntt_digits(lc, b.C, b.R, cnt);
-    }
-    Prof pr(ctx, "relin_mac", lc.stream, (double)cnt * ctx->L * ctx->N);
-    cw::launch_relin_mac(lc, b.R, key->d, sel, cnt);
+    Prof pr(ctx, "relin", lc.stream, bfly(ctx, (size_t)cnt * (ctx->L + 2) * ctx->L));
+    cw::launch_relin(lc, b.C, key->d, sel, cnt, b.R);
 }
 
 // Level-1 products of pairs[0..np) into nodes (extended, transformed), in chunks of E.
@@ -772,8 +768,7 @@ extern "C" int pir_relin(pir_ctx* ctx, const pir_key* key, const uint64_t* in, u
     Launch lc = make_launch(ctx, st);
     Bufs b;
     CW_TRY(get_bufs(ctx, 1, 0, b));
-    cw::launch_ntt_digits(lc, in, b.R, 1);
-    cw::launch_relin_mac(lc, b.R, key->d, out, 1);
+    cw::launch_relin(lc, in, key->d, out, 1, b.R);
     cw::launch_ntt(lc, true, out, out, (size_t)2 * L, L, 0);
     return end_async(ctx, st);
 }

@@ -37,6 +37,12 @@ void launch_ntt_inv_tensor(const Launch& lc, const uint32_t* refs, const uint64_
                            uint64_t* X, uint32_t E);
 void launch_scale(const Launch& lc, const uint64_t* X, uint64_t* out, uint32_t E);
 void launch_relin_mac(const Launch& lc, const uint64_t* R, const uint64_t* rlk, uint64_t* sel, uint32_t E);
+// Key switching of E coefficient-form products [E][3][L][N] into transformed selectors [E][2][L][N]
+// (digit reduction, digit transforms and the multiply-accumulate with the key in one kernel).
+void launch_relin(const Launch& lc, const uint64_t* c3, const uint64_t* rlk, uint64_t* sel, uint32_t E,
+                  uint64_t* staging);
+// Whether launch_relin needs its staging buffer [E][L+2][L][N] at this ring degree.
+bool relin_needs_staging(uint32_t logN);
 void launch_shoup_companions(const Launch& lc, const uint64_t* v, uint64_t* comp, size_t rows, uint32_t nl);
 void launch_gather_leaf(const Launch& lc, const uint32_t* refs, const uint64_t* leaves, uint64_t* sel, uint32_t E);
 void launch_accumulate(const Launch& lc, const QueryPtrs& qp, const uint64_t* Ph, uint32_t nq, uint32_t E,

@@ -57,16 +57,19 @@ struct Shape {
     static_assert(R0 + R1 + R2 + R3 + R4 == LOGN, "passes must cover every stage");
 };
 
-// Shapes used by the library (chosen by measurement on MI355X).
+// The one shape per ring degree used by every kernel that writes or reads the transformed layout:
+// that layout (position u*T + tid) depends on R and the last pass, so all of them must agree.
+// Eight elements per thread leave room for the key-switching accumulators (k_relin); the shape
+// sweep measured them within 3% of the fastest plain transform shapes.
 template <int LOGN>
 struct DefaultShape;
 template <>
 struct DefaultShape<12> {
-    using type = Shape<12, 4, 3, 4, 4, 4>;
+    using type = Shape<12, 3, 4, 3, 3, 3, 3>;
 };
 template <>
 struct DefaultShape<13> {
-    using type = Shape<13, 4, 4, 4, 3, 3, 3>;
+    using type = Shape<13, 3, 5, 3, 3, 3, 2, 2>;
 };
 template <>
 struct DefaultShape<14> {
@@ -372,6 +375,98 @@ __global__ __launch_bounds__(Sh::T) void k_ntt_inv_tensor(const CtxConst* __rest
                                                           const uint64_t* __restrict__ nodes, uint64_t* __restrict__ X) {
     ntt_inv_row<Sh>(K, tw, RowsTensor<Sh>{refs, leaves, nodes, X, K, K->LL});
 }
+
+// ---------------------------------------------------------------------------------------------
+// Key switching fused with the digit transforms: workgroup (e, j) transforms, one after the other,
+// the L digits [c2_i]_{q_i} reduced mod q_j and the rows c0_j, c1_j, and accumulates
+//   sel0 = c0^ + sum_i D_i^ b_ij^,  sel1 = c1^ + sum_i D_i^ a_ij^   (mod q_j)
+// in registers, so the transformed digits never leave the chip.  rlk: [L][2][L][N] transformed
+// values followed by [L][2][L][N] Shoup companions; out: sel [E][2][L][N] (transformed).
+// ---------------------------------------------------------------------------------------------
+
+
+template <class Sh>
+__global__ __launch_bounds__(Sh::T) void k_relin(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
+                                                 const uint64_t* __restrict__ c3, const uint64_t* __restrict__ rlk,
+                                                 uint64_t* __restrict__ sel) {
+    __shared__ uint64_t sm[Sh::LDS_WORDS];
+    constexpr int N = Sh::N, T = Sh::T, EPT = Sh::EPT;
+    const uint32_t L = K->L, tid = threadIdx.x;
+    const uint32_t j = blockIdx.x % L;
+    const size_t e = blockIdx.x / L;
+    const uint64_t p = K->p[j], r1 = K->r1[j];
+    const uint64_t p2 = 2 * p;
+    const uint64_t* psi = tw + (size_t)j * 4 * N;
+    const uint64_t* base = c3 + e * 3 * L * N;
+    const size_t LN = (size_t)L * N, half = (size_t)L * 2 * LN;
+    uint64_t acc0[EPT], acc1[EPT], a[EPT];
+    for (uint32_t i = 0; i < L + 2; ++i) {
+        // The transform's index and twiddle arithmetic does not depend on i; opaque copies of the
+        // thread index and table pointer per iteration keep the compiler from hoisting all of it
+        // out of the loop into registers (which would spill).
+        uint32_t t = tid;
+        const uint64_t* psi_i = psi;
+        asm volatile("" : "+v"(t), "+v"(psi_i));
+        const uint64_t* src = i < L ? base + ((size_t)2 * L + i) * N : base + ((size_t)(i - L) * L + j) * N;
+        if (i < L && i != j) {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) a[u] = reduce64(src[elem_index<Sh, 0>(t, u)], p, r1);
+        } else {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) a[u] = src[elem_index<Sh, 0>(t, u)];
+        }
+        fwd_passes<Sh, 0>(a, sm, t, psi_i, psi_i + N, p);
+        asm volatile("" ::: "memory");  // keep the key loads below the transform
+        if (i < L) {
+            const uint64_t* bh = rlk + ((size_t)i * 2 + 0) * LN + (size_t)j * N + t;
+            const uint64_t* ah = rlk + ((size_t)i * 2 + 1) * LN + (size_t)j * N + t;
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                const size_t o = (size_t)u * T;
+                // Shoup accepts any 64-bit input, so the lazy transform output needs no reduction
+                const uint64_t tb = mul_shoup(a[u], bh[o], bh[half + o], p);
+                const uint64_t ta = mul_shoup(a[u], ah[o], ah[half + o], p);
+                acc0[u] = i == 0 ? tb : add_mod(acc0[u], tb, p);
+                acc1[u] = i == 0 ? ta : add_mod(acc1[u], ta, p);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                uint64_t v = a[u];
+                v = v >= p2 ? v - p2 : v;
+                v = v >= p ? v - p : v;
+                if (i == L) acc0[u] = add_mod(acc0[u], v, p);
+                else acc1[u] = add_mod(acc1[u], v, p);
+            }
+        }
+        asm volatile("" ::: "memory");
+    }
+    uint64_t* o0 = sel + e * 2 * LN + (size_t)j * N + tid;
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        o0[(size_t)u * T] = acc0[u];
+        o0[LN + (size_t)u * T] = acc1[u];
+    }
+}
+
+// N = 16384 does not fit 16 elements plus two accumulators per thread in the 128 registers that a
+// 1024-thread workgroup allows; there the digits are transformed to `staging` [E][L+2][L][N] and
+// multiplied-accumulated by a second kernel.
+void launch_relin(const Launch& lc, const uint64_t* c3, const uint64_t* rlk, uint64_t* sel, uint32_t E,
+                  uint64_t* staging) {
+    if (!E) return;
+    const unsigned blocks = (unsigned)((size_t)E * lc.L);
+    switch (lc.logN) {
+        case 12: { using Sh = DefaultShape<12>::type; hipLaunchKernelGGL(k_relin<Sh>, dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, c3, rlk, sel); } break;
+        case 13: { using Sh = DefaultShape<13>::type; hipLaunchKernelGGL(k_relin<Sh>, dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, c3, rlk, sel); } break;
+        case 14:
+            launch_ntt_digits(lc, c3, staging, E);
+            launch_relin_mac(lc, staging, rlk, sel, E);
+            break;
+    }
+}
+
+bool relin_needs_staging(uint32_t logN) { return logN >= 14; }
 
 #define CW_BY_N(LOGNV, CALL)                                 \
     switch (LOGNV) {                                         \
