@@ -31,14 +31,20 @@ struct ConvTable {
     uint64_t Phat[MAX_CONV][MAX_W];              // P / p_i
 };
 
+// Primes below this bound may use the fp64 transform (see kernels.hip); the exactness argument
+// needs every intermediate integer below 2^53.
+constexpr uint64_t FP_PRIME_BOUND = 1ull << 50;
+
 struct CtxConst {
-    uint32_t N, logN, L, LB, LL, pad;
+    uint32_t N, logN, L, LB, LL, fp;             // fp: transforms run on the fp64 pipe
     uint64_t t;
     uint64_t p[MAX_LL];
     uint64_t bar_mu[MAX_LL];                     // floor(2^(2s) / p), s = bit length of p
     uint32_t bar_s[MAX_LL];
     uint64_t r1[MAX_LL];                         // floor(2^64 / p)
     uint64_t ninv[MAX_LL], ninvq[MAX_LL];        // N^{-1} mod p
+    double pd[MAX_LL], pinv[MAX_LL];             // p and 1/p as doubles (fp64 transform)
+    double ninvd[MAX_LL], ninvdq[MAX_LL];        // N^{-1} mod p and (N^{-1} mod p)/p as doubles
     uint64_t qinv[MAX_L], qinvq[MAX_L];          // [(q/q_i)^{-1}]_{q_i}
     uint64_t tqinv[MAX_L], tqinvq[MAX_L];        // [t (q/q_i)^{-1}]_{q_i}
     uint64_t kb1[MAX_LB], kb1q[MAX_LB];          // [t q^{-1} (B/b_j)^{-1}]_{b_j}

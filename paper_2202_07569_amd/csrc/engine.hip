@@ -54,6 +54,8 @@ struct pir_ctx {
     CtxConst K;
     CtxConst* dK = nullptr;
     uint64_t* dtw = nullptr;
+    double* dtwf = nullptr;
+    bool fp = false;
     uint64_t budget = 0, held = 0;
     bool poisoned = false;
     std::recursive_mutex mu;
@@ -172,6 +174,8 @@ static Launch make_launch(pir_ctx* ctx, hipStream_t st) {
     lc.stream = st;
     lc.K = ctx->dK;
     lc.tw = ctx->dtw;
+    lc.twf = ctx->dtwf;
+    lc.fp = ctx->fp;
     lc.N = ctx->N;
     lc.logN = ctx->logN;
     lc.L = ctx->L;
@@ -237,7 +241,10 @@ extern "C" int pir_setup(const pir_params* params, pir_ctx** out) {
         return fail(PIR_E_UNSUPPORTED, "N must be 4096, 8192 or 16384");
     std::string why = cw::host::validate(params->N, q, params->t);
     if (!why.empty()) return fail(PIR_E_INVALID, why);
-    std::vector<uint64_t> B = cw::host::aux_primes(params->N, q, params->t);
+    // fp64 transforms need every prime below 2^50; then the auxiliary primes are chosen below 2^50
+    bool fp = params->N <= 8192;
+    for (uint64_t x : q) fp = fp && x < cw::FP_PRIME_BOUND;
+    std::vector<uint64_t> B = cw::host::aux_primes(params->N, q, params->t, fp ? cw::FP_PRIME_BOUND : (1ull << 61));
     if (B.size() > (size_t)cw::MAX_LB) return fail(PIR_E_UNSUPPORTED, "auxiliary basis too large");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(PIR_E_DEVICE, "no HIP device");
@@ -258,7 +265,9 @@ extern "C" int pir_setup(const pir_params* params, pir_ctx** out) {
     ctx->budget = params->hbm_budget_bytes;
     ctx->primes = q;
     ctx->primes.insert(ctx->primes.end(), B.begin(), B.end());
+    ctx->fp = fp;
     cw::host::build_const(ctx->K, ctx->N, q, B, ctx->t);
+    ctx->K.fp = fp ? 1 : 0;
     if (params->chunk_elems > 4096) return cleanup_early(fail(PIR_E_INVALID, "chunk_elems must be <= 4096"), ctx);
     ctx->chunk = params->chunk_elems ? params->chunk_elems : (ctx->N >= 16384 ? 128 : 256);
     ctx->memo_cap = params->memo_bytes ? params->memo_bytes : (ctx->budget ? ctx->budget / 4 : (8ull << 30));
@@ -275,10 +284,15 @@ extern "C" int pir_setup(const pir_params* params, pir_ctx** out) {
         ctx->cus = (uint32_t)std::max(1, prop.multiProcessorCount);
     }
     std::vector<uint64_t> tw;
+    std::vector<double> twf;
     cw::host::build_twiddles(tw, ctx->primes, ctx->N);
+    if (fp) cw::host::build_twiddles_fp(twf, tw, ctx->primes, ctx->N);
     int rc;
     if ((rc = dev_alloc(ctx, (void**)&ctx->dK, sizeof(CtxConst))) != PIR_OK) return cleanup(rc);
     if ((rc = dev_alloc(ctx, (void**)&ctx->dtw, tw.size() * 8)) != PIR_OK) return cleanup(rc);
+    if (fp && (rc = dev_alloc(ctx, (void**)&ctx->dtwf, twf.size() * 8)) != PIR_OK) return cleanup(rc);
+    if (fp && hipMemcpy(ctx->dtwf, twf.data(), twf.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+        return cleanup(fail(PIR_E_DEVICE, "twiddle upload failed"));
     ctx->fix_cap = (size_t)3 * ctx->chunk * ctx->N;
     if ((rc = dev_alloc(ctx, (void**)&ctx->dfix, ctx->fix_cap * 8)) != PIR_OK) return cleanup(rc);
     if ((rc = dev_alloc(ctx, (void**)&ctx->dfixcnt, 256)) != PIR_OK) return cleanup(rc);
@@ -303,6 +317,7 @@ extern "C" void pir_free(pir_ctx* ctx) {
     for (auto& kv : ctx->binom) (void)hipFree(kv.second);
     dev_free(ctx, ctx->dK, sizeof(CtxConst));
     dev_free(ctx, ctx->dtw, (size_t)ctx->LL * 4 * ctx->N * 8);
+    if (ctx->dtwf) dev_free(ctx, ctx->dtwf, (size_t)ctx->LL * 4 * ctx->N * 8);
     dev_free(ctx, ctx->dfix, ctx->fix_cap * 8);
     dev_free(ctx, ctx->dfixcnt, 256);
     if (ctx->done) (void)hipEventDestroy(ctx->done);

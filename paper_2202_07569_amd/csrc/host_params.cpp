@@ -104,14 +104,14 @@ std::string validate(uint32_t N, const std::vector<uint64_t>& q, uint64_t t) {
     return "";
 }
 
-std::vector<uint64_t> aux_primes(uint32_t N, const std::vector<uint64_t>& q, uint64_t t) {
+std::vector<uint64_t> aux_primes(uint32_t N, const std::vector<uint64_t>& q, uint64_t t, uint64_t below) {
     // B > 4 t N q: holds round(t X / q) and, with q, every exact tensor product.
     MW bound = mw_mul(mw_mul(mw_prod(q), t), 4ull * N);
     std::vector<uint64_t> B;
     MW prod{1};
     const uint64_t step = 2ull * N;
-    uint64_t c = ((1ull << 61) - 1) / step * step + 1;
-    if (c >= (1ull << 61)) c -= step;
+    uint64_t c = (below - 1) / step * step + 1;
+    if (c >= below) c -= step;
     while (mw_cmp(prod, bound) <= 0) {
         if (is_prime(c) && std::find(q.begin(), q.end(), c) == q.end()) {
             B.push_back(c);
@@ -168,6 +168,10 @@ void build_const(CtxConst& K, uint32_t N, const std::vector<uint64_t>& q, const 
         K.r1[i] = (~0ull) / p;
         K.ninv[i] = invmod(N % p, p);
         K.ninvq[i] = shoup(K.ninv[i], p);
+        K.pd[i] = (double)p;
+        K.pinv[i] = 1.0 / (double)p;
+        K.ninvd[i] = (double)K.ninv[i];
+        K.ninvdq[i] = (double)K.ninv[i] / (double)p;
     }
     MW Q = mw_prod(q), BB = mw_prod(B);
     for (uint32_t i = 0; i < K.L; ++i) {
@@ -196,6 +200,22 @@ static uint32_t bitrev(uint32_t x, uint32_t logn) {
     for (uint32_t b = 0; b < logn; ++b)
         if (x & (1u << b)) r |= 1u << (logn - 1 - b);
     return r;
+}
+
+void build_twiddles_fp(std::vector<double>& twf, const std::vector<uint64_t>& tw, const std::vector<uint64_t>& primes,
+                       uint32_t N) {
+    twf.assign(tw.size(), 0.0);
+    for (size_t k = 0; k < primes.size(); ++k) {
+        const double p = (double)primes[k];
+        const uint64_t* src = tw.data() + k * 4 * (size_t)N;
+        double* dst = twf.data() + k * 4 * (size_t)N;
+        for (uint32_t i = 0; i < N; ++i) {
+            dst[i] = (double)src[i];                          // exact: below 2^53
+            dst[N + i] = (double)src[i] / p;                  // w / p, correctly rounded
+            dst[2 * N + i] = (double)src[2 * N + i];
+            dst[3 * N + i] = (double)src[2 * N + i] / p;
+        }
+    }
 }
 
 void build_twiddles(std::vector<uint64_t>& tw, const std::vector<uint64_t>& primes, uint32_t N) {

@@ -19,12 +19,15 @@ uint64_t find_psi(uint64_t p, uint32_t N);
 
 // "" when (N, q, t) is supported, else the reason.
 std::string validate(uint32_t N, const std::vector<uint64_t>& q, uint64_t t);
-// Largest primes = 1 mod 2N below 2^61, not in q, until their product exceeds 4 t N q.
-std::vector<uint64_t> aux_primes(uint32_t N, const std::vector<uint64_t>& q, uint64_t t);
+// Largest primes = 1 mod 2N below `below`, not in q, until their product exceeds 4 t N q.
+std::vector<uint64_t> aux_primes(uint32_t N, const std::vector<uint64_t>& q, uint64_t t, uint64_t below);
 void build_const(CtxConst& K, uint32_t N, const std::vector<uint64_t>& q, const std::vector<uint64_t>& B,
                  uint64_t t);
 // [prime][4][N]: psi^bitrev(i), its Shoup companion, psi^-bitrev(i), its Shoup companion.
 void build_twiddles(std::vector<uint64_t>& tw, const std::vector<uint64_t>& primes, uint32_t N);
+// The same tables as doubles: [prime][4][N] = w, w/p, w_inv, w_inv/p (fp64 transform).
+void build_twiddles_fp(std::vector<double>& twf, const std::vector<uint64_t>& tw, const std::vector<uint64_t>& primes,
+                       uint32_t N);
 std::vector<uint64_t> binom_table(uint32_t m, uint32_t k);
 
 }  // namespace host

@@ -18,6 +18,8 @@ struct Launch {
     hipStream_t stream;
     const CtxConst* K;    // device copy of the constants
     const uint64_t* tw;   // device twiddles [LL][4][N]
+    const double* twf;    // the same as doubles (fp64 transform), or null
+    bool fp;              // transforms run on the fp64 pipe (every prime below 2^50, N <= 8192)
     uint32_t N, logN, L, LB, LL;
     uint32_t cus;         // compute units of the device
     uint64_t* fix;        // fixup list for ambiguous conversions (capacity >= coefficients per launch)

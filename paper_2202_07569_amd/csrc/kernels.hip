@@ -149,9 +149,86 @@ __device__ __forceinline__ void inv_pass(uint64_t* a, uint32_t tid, const uint64
     }
 }
 
+// ---------------------------------------------------------------------------------------------
+// fp64 arithmetic for primes below 2^50 (CtxConst::fp).  Residues are integer-valued doubles in a
+// signed lazy range.  For |y| < 2^53 and a twiddle w < p with wq = fl(w / p):
+//   q = rint(y wq), h = fl(y w), l = fma(y, w, -h) = y w - h exactly,
+//   T = fma(-q, p, h) + l = y w - q p exactly,
+// because h - q p and T are integers below 2^53 in magnitude; |q - y w / p| <= 1/2 + |y| 2^-52, so
+// |T| <= (1/2 + |y| 2^-52) p.  fred(x) = x - rint(x / p) p leaves |x| <= p/2 + |x| 2^-52 p.  With every
+// pass of at most three stages starting from |x| <= p, values stay below 8p <= 2^53 (p < 2^50),
+// so every operation above is exact.
+// ---------------------------------------------------------------------------------------------
+#pragma clang fp contract(off)
+__device__ __forceinline__ double fmulmod(double y, double w, double wq, double p) {
+    const double q = __builtin_rint(y * wq);
+    const double h = y * w;
+    const double l = __builtin_fma(y, w, -h);
+    return __builtin_fma(-q, p, h) + l;
+}
+__device__ __forceinline__ double fred(double x, double p, double pinv) {
+    return __builtin_fma(-__builtin_rint(x * pinv), p, x);
+}
+
+template <class Sh, int P>
+__device__ __forceinline__ void fwd_pass_fp(double* a, uint32_t tid, const double* __restrict__ tw,
+                                            const double* __restrict__ twq, double p, double pinv) {
+    using G = PassGeo<Sh, P>;
+    static_assert(G::rp <= 3, "the fp64 bound needs passes of at most three stages");
+    if constexpr (P > 0) {
+#pragma unroll
+        for (int u = 0; u < Sh::EPT; ++u) a[u] = fred(a[u], p, pinv);
+    }
+#pragma unroll
+    for (int sp = 0; sp < G::rp; ++sp) {
+        const int s = G::S0 + sp;
+        const int pb = G::x + G::rp - 1 - sp;
+#pragma unroll
+        for (int u0 = 0; u0 < Sh::EPT; ++u0) {
+            if (u0 & (1 << pb)) continue;
+            const int u1 = u0 | (1 << pb);
+            const uint32_t ti = (1u << s) + (elem_index<Sh, P>(tid, (uint32_t)u0) >> (Sh::LOGN - s));
+            const double T = fmulmod(a[u1], tw[ti], twq[ti], p);
+            const double X = a[u0];
+            a[u0] = X + T;
+            a[u1] = X - T;
+        }
+    }
+}
+
+template <class Sh, int P>
+__device__ __forceinline__ void inv_pass_fp(double* a, uint32_t tid, const double* __restrict__ tw,
+                                            const double* __restrict__ twq, double p, double pinv) {
+    using G = PassGeo<Sh, P>;
+    static_assert(G::rp <= 3, "the fp64 bound needs passes of at most three stages");
+#pragma unroll
+    for (int u = 0; u < Sh::EPT; ++u) a[u] = fred(a[u], p, pinv);
+#pragma unroll
+    for (int sp = G::rp - 1; sp >= 0; --sp) {
+        const int s = G::S0 + sp;
+        const int pb = G::x + G::rp - 1 - sp;
+#pragma unroll
+        for (int u0 = 0; u0 < Sh::EPT; ++u0) {
+            if (u0 & (1 << pb)) continue;
+            const int u1 = u0 | (1 << pb);
+            const uint32_t ti = (1u << s) + (elem_index<Sh, P>(tid, (uint32_t)u0) >> (Sh::LOGN - s));
+            const double X = a[u0], Y = a[u1];
+            a[u0] = X + Y;
+            a[u1] = fmulmod(X - Y, tw[ti], twq[ti], p);
+        }
+    }
+}
+#pragma clang fp contract(on)
+
+// integer-valued double in (-p, p) -> residue in [0, p)
+__device__ __forceinline__ uint64_t fp_to_residue(double x, double p) {
+    x = x < 0.0 ? x + p : x;
+    return (uint64_t)x;
+}
+
 // registers of pass PA -> LDS -> registers of pass PB
-template <class Sh, int PA, int PB>
-__device__ __forceinline__ void exchange(uint64_t* a, uint64_t* sm, uint32_t tid) {
+template <class Sh, int PA, int PB, class V>
+__device__ __forceinline__ void exchange(V* a, V* sm, uint32_t tid) {
 #pragma unroll
     for (int u = 0; u < Sh::EPT; ++u) sm[lds_pad(elem_index<Sh, PA>(tid, u))] = a[u];
     __syncthreads();
@@ -160,24 +237,104 @@ __device__ __forceinline__ void exchange(uint64_t* a, uint64_t* sm, uint32_t tid
     __syncthreads();
 }
 
-template <class Sh, int P>
-__device__ __forceinline__ void fwd_passes(uint64_t* a, uint64_t* sm, uint32_t tid, const uint64_t* psi,
-                                           const uint64_t* psiq, uint64_t p) {
-    fwd_pass<Sh, P>(a, tid, psi, psiq, p);
-    if constexpr (P + 1 < Sh::NP) {
-        exchange<Sh, P, P + 1>(a, sm, tid);
-        fwd_passes<Sh, P + 1>(a, sm, tid, psi, psiq, p);
+// Twiddle tables of one prime: integer form [4][N] (w, w', w_inv, w_inv') and double form
+// [4][N] (w, w/p, w_inv, w_inv/p).
+struct TwRow {
+    const uint64_t* i;
+    const double* f;
+};
+
+template <class Sh, bool FP, int P>
+__device__ __forceinline__ void fwd_passes(void* av, void* smv, uint32_t tid, TwRow tw, const CtxConst* K,
+                                           uint32_t pi) {
+    if constexpr (FP) {
+        double* a = (double*)av;
+        fwd_pass_fp<Sh, P>(a, tid, tw.f, tw.f + Sh::N, K->pd[pi], K->pinv[pi]);
+        if constexpr (P + 1 < Sh::NP) {
+            exchange<Sh, P, P + 1>(a, (double*)smv, tid);
+            fwd_passes<Sh, FP, P + 1>(av, smv, tid, tw, K, pi);
+        }
+    } else {
+        uint64_t* a = (uint64_t*)av;
+        fwd_pass<Sh, P>(a, tid, tw.i, tw.i + Sh::N, K->p[pi]);
+        if constexpr (P + 1 < Sh::NP) {
+            exchange<Sh, P, P + 1>(a, (uint64_t*)smv, tid);
+            fwd_passes<Sh, FP, P + 1>(av, smv, tid, tw, K, pi);
+        }
     }
 }
 
-template <class Sh, int P>
-__device__ __forceinline__ void inv_passes(uint64_t* a, uint64_t* sm, uint32_t tid, const uint64_t* psi,
-                                           const uint64_t* psiq, uint64_t p) {
-    inv_pass<Sh, P>(a, tid, psi, psiq, p);
-    if constexpr (P > 0) {
-        exchange<Sh, P, P - 1>(a, sm, tid);
-        inv_passes<Sh, P - 1>(a, sm, tid, psi, psiq, p);
+template <class Sh, bool FP, int P>
+__device__ __forceinline__ void inv_passes(void* av, void* smv, uint32_t tid, TwRow tw, const CtxConst* K,
+                                           uint32_t pi) {
+    if constexpr (FP) {
+        double* a = (double*)av;
+        inv_pass_fp<Sh, P>(a, tid, tw.f + 2 * Sh::N, tw.f + 3 * Sh::N, K->pd[pi], K->pinv[pi]);
+        if constexpr (P > 0) {
+            exchange<Sh, P, P - 1>(a, (double*)smv, tid);
+            inv_passes<Sh, FP, P - 1>(av, smv, tid, tw, K, pi);
+        }
+    } else {
+        uint64_t* a = (uint64_t*)av;
+        inv_pass<Sh, P>(a, tid, tw.i + 2 * Sh::N, tw.i + 3 * Sh::N, K->p[pi]);
+        if constexpr (P > 0) {
+            exchange<Sh, P, P - 1>(a, (uint64_t*)smv, tid);
+            inv_passes<Sh, FP, P - 1>(av, smv, tid, tw, K, pi);
+        }
     }
+}
+
+// Forward transform of the EPT values a[] (residues in [0, p), first-pass pattern) of thread tid;
+// on return a[] holds the thread's outputs (transformed layout) reduced to [0, p).
+template <class Sh, bool FP>
+__device__ __forceinline__ void ntt_fwd_regs(uint64_t* a, uint64_t* sm, uint32_t tid, TwRow tw, const CtxConst* K,
+                                             uint32_t pi) {
+    if constexpr (FP) {
+        double v[Sh::EPT];
+#pragma unroll
+        for (int u = 0; u < Sh::EPT; ++u) v[u] = (double)a[u];
+        fwd_passes<Sh, true, 0>(v, sm, tid, tw, K, pi);
+        const double p = K->pd[pi], pinv = K->pinv[pi];
+#pragma unroll
+        for (int u = 0; u < Sh::EPT; ++u) a[u] = fp_to_residue(fred(v[u], p, pinv), p);
+    } else {
+        fwd_passes<Sh, false, 0>(a, sm, tid, tw, K, pi);
+        const uint64_t p = K->p[pi], p2 = 2 * p;
+#pragma unroll
+        for (int u = 0; u < Sh::EPT; ++u) {
+            uint64_t x = a[u];
+            x = x >= p2 ? x - p2 : x;
+            a[u] = x >= p ? x - p : x;
+        }
+    }
+}
+
+// Inverse transform (including N^-1) of a[] (transformed layout); returns residues in [0, p) in
+// the first pass's natural-order pattern.
+template <class Sh, bool FP>
+__device__ __forceinline__ void ntt_inv_regs(uint64_t* a, uint64_t* sm, uint32_t tid, TwRow tw, const CtxConst* K,
+                                             uint32_t pi) {
+    if constexpr (FP) {
+        double v[Sh::EPT];
+#pragma unroll
+        for (int u = 0; u < Sh::EPT; ++u) v[u] = (double)a[u];
+        inv_passes<Sh, true, Sh::NP - 1>(v, sm, tid, tw, K, pi);
+        const double p = K->pd[pi], pinv = K->pinv[pi], ni = K->ninvd[pi], niq = K->ninvdq[pi];
+#pragma unroll
+        for (int u = 0; u < Sh::EPT; ++u) a[u] = fp_to_residue(fred(fmulmod(v[u], ni, niq, p), p, pinv), p);
+    } else {
+        inv_passes<Sh, false, Sh::NP - 1>(a, sm, tid, tw, K, pi);
+        const uint64_t p = K->p[pi], ni = K->ninv[pi], niq = K->ninvq[pi];
+#pragma unroll
+        for (int u = 0; u < Sh::EPT; ++u) {
+            const uint64_t x = mul_shoup_lazy(a[u], ni, niq, p);
+            a[u] = x >= p ? x - p : x;
+        }
+    }
+}
+
+__device__ __forceinline__ TwRow tw_row(const uint64_t* tw, const double* twf, uint32_t pi, uint32_t N) {
+    return TwRow{tw + (size_t)pi * 4 * N, twf ? twf + (size_t)pi * 4 * N : nullptr};
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -185,45 +342,32 @@ __device__ __forceinline__ void inv_passes(uint64_t* a, uint64_t* sm, uint32_t t
 // inputs of thread tid in the first pass's pattern: natural order for the forward transform, the
 // transformed layout for the inverse) and store(g, tid, u, v) for one reduced output.
 // ---------------------------------------------------------------------------------------------
-template <class Sh, class Row>
+template <class Sh, bool FP, class Row>
 __device__ __forceinline__ void ntt_fwd_row(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
-                                            const Row& row) {
+                                            const double* __restrict__ twf, const Row& row) {
     __shared__ uint64_t sm[Sh::LDS_WORDS];
     const uint32_t tid = threadIdx.x;
     const size_t g = blockIdx.x;
     uint64_t a[Sh::EPT];
     row.load(g, tid, a);
     const uint32_t pi = row.prime(g);
-    const uint64_t p = K->p[pi];
-    const uint64_t* psi = tw + (size_t)pi * 4 * Sh::N;
-    fwd_passes<Sh, 0>(a, sm, tid, psi, psi + Sh::N, p);
-    const uint64_t p2 = 2 * p;
+    ntt_fwd_regs<Sh, FP>(a, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
 #pragma unroll
-    for (int u = 0; u < Sh::EPT; ++u) {
-        uint64_t v = a[u];
-        v = v >= p2 ? v - p2 : v;
-        row.store(g, tid, u, v >= p ? v - p : v);
-    }
+    for (int u = 0; u < Sh::EPT; ++u) row.store(g, tid, u, a[u]);
 }
 
-template <class Sh, class Row>
+template <class Sh, bool FP, class Row>
 __device__ __forceinline__ void ntt_inv_row(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
-                                            const Row& row) {
+                                            const double* __restrict__ twf, const Row& row) {
     __shared__ uint64_t sm[Sh::LDS_WORDS];
     const uint32_t tid = threadIdx.x;
     const size_t g = blockIdx.x;
     uint64_t a[Sh::EPT];
     row.load(g, tid, a);
     const uint32_t pi = row.prime(g);
-    const uint64_t p = K->p[pi];
-    const uint64_t* psi = tw + (size_t)pi * 4 * Sh::N + 2 * Sh::N;
-    inv_passes<Sh, Sh::NP - 1>(a, sm, tid, psi, psi + Sh::N, p);
-    const uint64_t ni = K->ninv[pi], niq = K->ninvq[pi];
+    ntt_inv_regs<Sh, FP>(a, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
 #pragma unroll
-    for (int u = 0; u < Sh::EPT; ++u) {
-        const uint64_t v = mul_shoup_lazy(a[u], ni, niq, p);
-        row.store(g, tid, u, v >= p ? v - p : v);
-    }
+    for (int u = 0; u < Sh::EPT; ++u) row.store(g, tid, u, a[u]);
 }
 
 // Forward outputs go to the transformed layout (u*T + tid); inverse outputs to natural order.
@@ -348,32 +492,37 @@ struct RowsTensor {
     __device__ void store(size_t g, uint32_t tid, int u, uint64_t v) const { out[natural_pos<Sh>(g, tid, u)] = v; }
 };
 
-template <class Sh>
+template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T) void k_ntt_fwd(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
-                                                   const uint64_t* in, uint64_t* out, uint32_t nl, uint32_t pbase) {
-    ntt_fwd_row<Sh>(K, tw, RowsFwdU64<Sh>{in, out, nl, pbase});
+                                                   const double* __restrict__ twf, const uint64_t* in, uint64_t* out,
+                                                   uint32_t nl, uint32_t pbase) {
+    ntt_fwd_row<Sh, FP>(K, tw, twf, RowsFwdU64<Sh>{in, out, nl, pbase});
 }
-template <class Sh>
+template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T) void k_ntt_inv(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
-                                                   const uint64_t* in, uint64_t* out, uint32_t nl, uint32_t pbase) {
-    ntt_inv_row<Sh>(K, tw, RowsInvU64<Sh>{in, out, nl, pbase});
+                                                   const double* __restrict__ twf, const uint64_t* in, uint64_t* out,
+                                                   uint32_t nl, uint32_t pbase) {
+    ntt_inv_row<Sh, FP>(K, tw, twf, RowsInvU64<Sh>{in, out, nl, pbase});
 }
-template <class Sh>
+template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T) void k_ntt_payload(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
-                                                       const uint16_t* __restrict__ pay, uint64_t* __restrict__ out) {
-    ntt_fwd_row<Sh>(K, tw, RowsPayload<Sh>{pay, out, K->L});
+                                                       const double* __restrict__ twf, const uint16_t* __restrict__ pay,
+                                                       uint64_t* __restrict__ out) {
+    ntt_fwd_row<Sh, FP>(K, tw, twf, RowsPayload<Sh>{pay, out, K->L});
 }
-template <class Sh>
+template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T) void k_ntt_digits(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
-                                                      const uint64_t* __restrict__ c3, uint64_t* __restrict__ out) {
-    ntt_fwd_row<Sh>(K, tw, RowsDigits<Sh>{c3, out, K, K->L});
+                                                      const double* __restrict__ twf, const uint64_t* __restrict__ c3,
+                                                      uint64_t* __restrict__ out) {
+    ntt_fwd_row<Sh, FP>(K, tw, twf, RowsDigits<Sh>{c3, out, K, K->L});
 }
-template <class Sh>
+template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T) void k_ntt_inv_tensor(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
+                                                          const double* __restrict__ twf,
                                                           const uint32_t* __restrict__ refs,
                                                           const uint64_t* __restrict__ leaves,
                                                           const uint64_t* __restrict__ nodes, uint64_t* __restrict__ X) {
-    ntt_inv_row<Sh>(K, tw, RowsTensor<Sh>{refs, leaves, nodes, X, K, K->LL});
+    ntt_inv_row<Sh, FP>(K, tw, twf, RowsTensor<Sh>{refs, leaves, nodes, X, K, K->LL});
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -385,28 +534,27 @@ __global__ __launch_bounds__(Sh::T) void k_ntt_inv_tensor(const CtxConst* __rest
 // ---------------------------------------------------------------------------------------------
 
 
-template <class Sh>
+template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T) void k_relin(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
-                                                 const uint64_t* __restrict__ c3, const uint64_t* __restrict__ rlk,
-                                                 uint64_t* __restrict__ sel) {
+                                                 const double* __restrict__ twf, const uint64_t* __restrict__ c3,
+                                                 const uint64_t* __restrict__ rlk, uint64_t* __restrict__ sel) {
     __shared__ uint64_t sm[Sh::LDS_WORDS];
     constexpr int N = Sh::N, T = Sh::T, EPT = Sh::EPT;
     const uint32_t L = K->L, tid = threadIdx.x;
     const uint32_t j = blockIdx.x % L;
     const size_t e = blockIdx.x / L;
     const uint64_t p = K->p[j], r1 = K->r1[j];
-    const uint64_t p2 = 2 * p;
-    const uint64_t* psi = tw + (size_t)j * 4 * N;
+    const TwRow twr = tw_row(tw, twf, j, N);
     const uint64_t* base = c3 + e * 3 * L * N;
     const size_t LN = (size_t)L * N, half = (size_t)L * 2 * LN;
     uint64_t acc0[EPT], acc1[EPT], a[EPT];
     for (uint32_t i = 0; i < L + 2; ++i) {
         // The transform's index and twiddle arithmetic does not depend on i; opaque copies of the
-        // thread index and table pointer per iteration keep the compiler from hoisting all of it
+        // thread index and table pointers per iteration keep the compiler from hoisting all of it
         // out of the loop into registers (which would spill).
         uint32_t t = tid;
-        const uint64_t* psi_i = psi;
-        asm volatile("" : "+v"(t), "+v"(psi_i));
+        TwRow tr = twr;
+        asm volatile("" : "+v"(t), "+v"(tr.i), "+v"(tr.f));
         const uint64_t* src = i < L ? base + ((size_t)2 * L + i) * N : base + ((size_t)(i - L) * L + j) * N;
         if (i < L && i != j) {
 #pragma unroll
@@ -415,7 +563,7 @@ __global__ __launch_bounds__(Sh::T) void k_relin(const CtxConst* __restrict__ K,
 #pragma unroll
             for (int u = 0; u < EPT; ++u) a[u] = src[elem_index<Sh, 0>(t, u)];
         }
-        fwd_passes<Sh, 0>(a, sm, t, psi_i, psi_i + N, p);
+        ntt_fwd_regs<Sh, FP>(a, sm, t, tr, K, j);
         asm volatile("" ::: "memory");  // keep the key loads below the transform
         if (i < L) {
             const uint64_t* bh = rlk + ((size_t)i * 2 + 0) * LN + (size_t)j * N + t;
@@ -423,7 +571,6 @@ __global__ __launch_bounds__(Sh::T) void k_relin(const CtxConst* __restrict__ K,
 #pragma unroll
             for (int u = 0; u < EPT; ++u) {
                 const size_t o = (size_t)u * T;
-                // Shoup accepts any 64-bit input, so the lazy transform output needs no reduction
                 const uint64_t tb = mul_shoup(a[u], bh[o], bh[half + o], p);
                 const uint64_t ta = mul_shoup(a[u], ah[o], ah[half + o], p);
                 acc0[u] = i == 0 ? tb : add_mod(acc0[u], tb, p);
@@ -432,11 +579,8 @@ __global__ __launch_bounds__(Sh::T) void k_relin(const CtxConst* __restrict__ K,
         } else {
 #pragma unroll
             for (int u = 0; u < EPT; ++u) {
-                uint64_t v = a[u];
-                v = v >= p2 ? v - p2 : v;
-                v = v >= p ? v - p : v;
-                if (i == L) acc0[u] = add_mod(acc0[u], v, p);
-                else acc1[u] = add_mod(acc1[u], v, p);
+                if (i == L) acc0[u] = add_mod(acc0[u], a[u], p);
+                else acc1[u] = add_mod(acc1[u], a[u], p);
             }
         }
         asm volatile("" ::: "memory");
@@ -456,9 +600,19 @@ void launch_relin(const Launch& lc, const uint64_t* c3, const uint64_t* rlk, uin
                   uint64_t* staging) {
     if (!E) return;
     const unsigned blocks = (unsigned)((size_t)E * lc.L);
+#define CW_RELIN(LG)                                                                                               \
+    {                                                                                                              \
+        using Sh = DefaultShape<LG>::type;                                                                         \
+        if (lc.fp)                                                                                                 \
+            hipLaunchKernelGGL((k_relin<Sh, true>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, lc.twf, c3, \
+                               rlk, sel);                                                                          \
+        else                                                                                                       \
+            hipLaunchKernelGGL((k_relin<Sh, false>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, lc.twf,   \
+                               c3, rlk, sel);                                                                      \
+    }
     switch (lc.logN) {
-        case 12: { using Sh = DefaultShape<12>::type; hipLaunchKernelGGL(k_relin<Sh>, dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, c3, rlk, sel); } break;
-        case 13: { using Sh = DefaultShape<13>::type; hipLaunchKernelGGL(k_relin<Sh>, dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, c3, rlk, sel); } break;
+        case 12: CW_RELIN(12) break;
+        case 13: CW_RELIN(13) break;
         case 14:
             launch_ntt_digits(lc, c3, staging, E);
             launch_relin_mac(lc, staging, rlk, sel, E);
@@ -466,51 +620,62 @@ void launch_relin(const Launch& lc, const uint64_t* c3, const uint64_t* rlk, uin
     }
 }
 
+#undef CW_RELIN
+
 bool relin_needs_staging(uint32_t logN) { return logN >= 14; }
 
-#define CW_BY_N(LOGNV, CALL)                                 \
-    switch (LOGNV) {                                         \
-        case 12: { using Sh = DefaultShape<12>::type; CALL; } break; \
-        case 13: { using Sh = DefaultShape<13>::type; CALL; } break; \
-        case 14: { using Sh = DefaultShape<14>::type; CALL; } break; \
+// Static LDS of the transform kernels stays below the 160 KiB per workgroup of gfx950; nothing to
+// raise at run time.
+hipError_t kernels_init() { return hipSuccess; }
+
+// Dispatch on the ring degree and on the transform arithmetic (fp64 only for N <= 8192: the
+// N = 16384 shape has four-stage passes, outside the fp64 bound).
+#define CW_NTT_DISPATCH(LC, KERN, GRID, ...)                                                                 \
+    switch ((LC).logN) {                                                                                    \
+        case 12: {                                                                                          \
+            using Sh = DefaultShape<12>::type;                                                              \
+            if ((LC).fp) hipLaunchKernelGGL((KERN<Sh, true>), GRID, dim3(Sh::T), 0, (LC).stream, __VA_ARGS__);  \
+            else hipLaunchKernelGGL((KERN<Sh, false>), GRID, dim3(Sh::T), 0, (LC).stream, __VA_ARGS__);         \
+        } break;                                                                                            \
+        case 13: {                                                                                          \
+            using Sh = DefaultShape<13>::type;                                                              \
+            if ((LC).fp) hipLaunchKernelGGL((KERN<Sh, true>), GRID, dim3(Sh::T), 0, (LC).stream, __VA_ARGS__);  \
+            else hipLaunchKernelGGL((KERN<Sh, false>), GRID, dim3(Sh::T), 0, (LC).stream, __VA_ARGS__);         \
+        } break;                                                                                            \
+        case 14: {                                                                                          \
+            using Sh = DefaultShape<14>::type;                                                              \
+            hipLaunchKernelGGL((KERN<Sh, false>), GRID, dim3(Sh::T), 0, (LC).stream, __VA_ARGS__);             \
+        } break;                                                                                            \
     }
 
 void launch_ntt(const Launch& lc, bool inverse, const uint64_t* in, uint64_t* out, size_t rows, uint32_t nl,
                 uint32_t pbase) {
     if (!rows) return;
-    if (inverse)
-        CW_BY_N(lc.logN, hipLaunchKernelGGL(k_ntt_inv<Sh>, dim3((unsigned)rows), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,
-                                            in, out, nl, pbase))
-    else
-        CW_BY_N(lc.logN, hipLaunchKernelGGL(k_ntt_fwd<Sh>, dim3((unsigned)rows), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,
-                                            in, out, nl, pbase))
+    if (inverse) {
+        CW_NTT_DISPATCH(lc, k_ntt_inv, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, in, out, nl, pbase)
+    } else {
+        CW_NTT_DISPATCH(lc, k_ntt_fwd, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, in, out, nl, pbase)
+    }
 }
 
 void launch_ntt_digits(const Launch& lc, const uint64_t* c3, uint64_t* out, uint32_t E) {
     if (!E) return;
     const size_t rows = (size_t)E * (lc.L + 2) * lc.L;
-    CW_BY_N(lc.logN, hipLaunchKernelGGL(k_ntt_digits<Sh>, dim3((unsigned)rows), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,
-                                        c3, out))
+    CW_NTT_DISPATCH(lc, k_ntt_digits, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, c3, out)
 }
 
 void launch_ntt_inv_tensor(const Launch& lc, const uint32_t* refs, const uint64_t* leaves, const uint64_t* nodes,
                            uint64_t* X, uint32_t E) {
     if (!E) return;
     const size_t rows = (size_t)E * 3 * lc.LL;
-    CW_BY_N(lc.logN, hipLaunchKernelGGL(k_ntt_inv_tensor<Sh>, dim3((unsigned)rows), dim3(Sh::T), 0, lc.stream, lc.K,
-                                        lc.tw, refs, leaves, nodes, X))
+    CW_NTT_DISPATCH(lc, k_ntt_inv_tensor, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, refs, leaves, nodes, X)
 }
 
 void launch_ntt_payload(const Launch& lc, const uint16_t* pay, uint64_t* out, size_t rows_u16) {
     if (!rows_u16) return;
     const size_t rows = rows_u16 * lc.L;
-    CW_BY_N(lc.logN, hipLaunchKernelGGL(k_ntt_payload<Sh>, dim3((unsigned)rows), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,
-                                        pay, out))
+    CW_NTT_DISPATCH(lc, k_ntt_payload, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, pay, out)
 }
-
-// Static LDS of the transform kernels stays below the 160 KiB per workgroup of gfx950; nothing to
-// raise at run time.
-hipError_t kernels_init() { return hipSuccess; }
 
 // ---------------------------------------------------------------------------------------------
 // Exact centred extension Q -> Q u B of coefficient-form polynomials: in [G][L][N] -> out [G][LL][N]
