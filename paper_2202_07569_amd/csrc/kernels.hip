@@ -151,19 +151,21 @@ __device__ __forceinline__ void inv_pass(uint64_t* a, uint32_t tid, const uint64
 
 // ---------------------------------------------------------------------------------------------
 // fp64 arithmetic for primes below 2^50 (CtxConst::fp).  Residues are integer-valued doubles in a
-// signed lazy range.  For |y| < 2^53 and a twiddle w < p with wq = fl(w / p):
-//   q = rint(y wq), h = fl(y w), l = fma(y, w, -h) = y w - h exactly,
+// signed lazy range.  For |y| < 2^53 and a twiddle w < p:
+//   h = fl(y w), l = fma(y, w, -h) = y w - h exactly, q = rint(h fl(1/p)),
 //   T = fma(-q, p, h) + l = y w - q p exactly,
-// because h - q p and T are integers below 2^53 in magnitude; |q - y w / p| <= 1/2 + |y| 2^-52, so
-// |T| <= (1/2 + |y| 2^-52) p.  fred(x) = x - rint(x / p) p leaves |x| <= p/2 + |x| 2^-52 p.  With every
-// pass of at most three stages starting from |x| <= p, values stay below 8p <= 2^53 (p < 2^50),
-// so every operation above is exact.
+// because h - q p and T are integers below 2^52 in magnitude.  The quotient estimate satisfies
+// |q - y w / p| <= 1/2 + 3 |y| 2^-53, so |T| <= (1/2 + 3 |y| 2^-53) p; for p < 2^50 that is at most
+// (1/2 + 0.375 |y| / p) p.  fred(x) = x - rint(x / p) p leaves |x| <= p/2 (plus 2^-52 |x|).
+// Forward: a pass of at most three stages starting from |x| <= p ends below 4.8p; inverse: from
+// |x| <= p/2 below 4p; the final N^-1 product stays below 2p.  Every value stays below 2^53, so
+// every operation above is exact.
 // ---------------------------------------------------------------------------------------------
 #pragma clang fp contract(off)
-__device__ __forceinline__ double fmulmod(double y, double w, double wq, double p) {
-    const double q = __builtin_rint(y * wq);
+__device__ __forceinline__ double fmulmod(double y, double w, double p, double pinv) {
     const double h = y * w;
     const double l = __builtin_fma(y, w, -h);
+    const double q = __builtin_rint(h * pinv);
     return __builtin_fma(-q, p, h) + l;
 }
 __device__ __forceinline__ double fred(double x, double p, double pinv) {
@@ -171,8 +173,8 @@ __device__ __forceinline__ double fred(double x, double p, double pinv) {
 }
 
 template <class Sh, int P>
-__device__ __forceinline__ void fwd_pass_fp(double* a, uint32_t tid, const double* __restrict__ tw,
-                                            const double* __restrict__ twq, double p, double pinv) {
+__device__ __forceinline__ void fwd_pass_fp(double* a, uint32_t tid, const double* __restrict__ tw, double p,
+                                            double pinv) {
     using G = PassGeo<Sh, P>;
     static_assert(G::rp <= 3, "the fp64 bound needs passes of at most three stages");
     if constexpr (P > 0) {
@@ -188,7 +190,7 @@ __device__ __forceinline__ void fwd_pass_fp(double* a, uint32_t tid, const doubl
             if (u0 & (1 << pb)) continue;
             const int u1 = u0 | (1 << pb);
             const uint32_t ti = (1u << s) + (elem_index<Sh, P>(tid, (uint32_t)u0) >> (Sh::LOGN - s));
-            const double T = fmulmod(a[u1], tw[ti], twq[ti], p);
+            const double T = fmulmod(a[u1], tw[ti], p, pinv);
             const double X = a[u0];
             a[u0] = X + T;
             a[u1] = X - T;
@@ -197,8 +199,8 @@ __device__ __forceinline__ void fwd_pass_fp(double* a, uint32_t tid, const doubl
 }
 
 template <class Sh, int P>
-__device__ __forceinline__ void inv_pass_fp(double* a, uint32_t tid, const double* __restrict__ tw,
-                                            const double* __restrict__ twq, double p, double pinv) {
+__device__ __forceinline__ void inv_pass_fp(double* a, uint32_t tid, const double* __restrict__ tw, double p,
+                                            double pinv) {
     using G = PassGeo<Sh, P>;
     static_assert(G::rp <= 3, "the fp64 bound needs passes of at most three stages");
 #pragma unroll
@@ -214,7 +216,7 @@ __device__ __forceinline__ void inv_pass_fp(double* a, uint32_t tid, const doubl
             const uint32_t ti = (1u << s) + (elem_index<Sh, P>(tid, (uint32_t)u0) >> (Sh::LOGN - s));
             const double X = a[u0], Y = a[u1];
             a[u0] = X + Y;
-            a[u1] = fmulmod(X - Y, tw[ti], twq[ti], p);
+            a[u1] = fmulmod(X - Y, tw[ti], p, pinv);
         }
     }
 }
@@ -238,7 +240,7 @@ __device__ __forceinline__ void exchange(V* a, V* sm, uint32_t tid) {
 }
 
 // Twiddle tables of one prime: integer form [4][N] (w, w', w_inv, w_inv') and double form
-// [4][N] (w, w/p, w_inv, w_inv/p).
+// [4][N] (w, w/p, w_inv, w_inv/p; the fp64 passes read only w and w_inv).
 struct TwRow {
     const uint64_t* i;
     const double* f;
@@ -249,7 +251,7 @@ __device__ __forceinline__ void fwd_passes(void* av, void* smv, uint32_t tid, Tw
                                            uint32_t pi) {
     if constexpr (FP) {
         double* a = (double*)av;
-        fwd_pass_fp<Sh, P>(a, tid, tw.f, tw.f + Sh::N, K->pd[pi], K->pinv[pi]);
+        fwd_pass_fp<Sh, P>(a, tid, tw.f, K->pd[pi], K->pinv[pi]);
         if constexpr (P + 1 < Sh::NP) {
             exchange<Sh, P, P + 1>(a, (double*)smv, tid);
             fwd_passes<Sh, FP, P + 1>(av, smv, tid, tw, K, pi);
@@ -269,7 +271,7 @@ __device__ __forceinline__ void inv_passes(void* av, void* smv, uint32_t tid, Tw
                                            uint32_t pi) {
     if constexpr (FP) {
         double* a = (double*)av;
-        inv_pass_fp<Sh, P>(a, tid, tw.f + 2 * Sh::N, tw.f + 3 * Sh::N, K->pd[pi], K->pinv[pi]);
+        inv_pass_fp<Sh, P>(a, tid, tw.f + 2 * Sh::N, K->pd[pi], K->pinv[pi]);
         if constexpr (P > 0) {
             exchange<Sh, P, P - 1>(a, (double*)smv, tid);
             inv_passes<Sh, FP, P - 1>(av, smv, tid, tw, K, pi);
@@ -319,9 +321,9 @@ __device__ __forceinline__ void ntt_inv_regs(uint64_t* a, uint64_t* sm, uint32_t
 #pragma unroll
         for (int u = 0; u < Sh::EPT; ++u) v[u] = (double)a[u];
         inv_passes<Sh, true, Sh::NP - 1>(v, sm, tid, tw, K, pi);
-        const double p = K->pd[pi], pinv = K->pinv[pi], ni = K->ninvd[pi], niq = K->ninvdq[pi];
+        const double p = K->pd[pi], pinv = K->pinv[pi], ni = K->ninvd[pi];
 #pragma unroll
-        for (int u = 0; u < Sh::EPT; ++u) a[u] = fp_to_residue(fred(fmulmod(v[u], ni, niq, p), p, pinv), p);
+        for (int u = 0; u < Sh::EPT; ++u) a[u] = fp_to_residue(fred(fmulmod(v[u], ni, p, pinv), p, pinv), p);
     } else {
         inv_passes<Sh, false, Sh::NP - 1>(a, sm, tid, tw, K, pi);
         const uint64_t p = K->p[pi], ni = K->ninv[pi], niq = K->ninvq[pi];
@@ -335,6 +337,24 @@ __device__ __forceinline__ void ntt_inv_regs(uint64_t* a, uint64_t* sm, uint32_t
 
 __device__ __forceinline__ TwRow tw_row(const uint64_t* tw, const double* twf, uint32_t pi, uint32_t N) {
     return TwRow{tw + (size_t)pi * 4 * N, twf ? twf + (size_t)pi * 4 * N : nullptr};
+}
+
+// ---------------------------------------------------------------------------------------------
+// XCD-aware workgroup numbering.  MI355X deals workgroups to its 8 XCDs round-robin (workgroup b
+// runs on XCD b mod 8), and each XCD has its own L2.  Workgroups that read the same data are
+// numbered 8 apart so that they share an XCD and run close together: for a grid of `groups`
+// groups of `per` workgroups, workgroup b belongs to group (b / (8 per)) * 8 + b mod 8 and is
+// member (b / 8) mod per of it.  The grid is rounded up to whole sets of 8 groups; workgroups past
+// the last group return at once.
+// ---------------------------------------------------------------------------------------------
+constexpr uint32_t XCDS = 8;
+__host__ __device__ __forceinline__ size_t xcd_grid(size_t groups, uint32_t per) {
+    return (groups + XCDS - 1) / XCDS * XCDS * per;
+}
+__device__ __forceinline__ void xcd_split(size_t b, uint32_t per, size_t& group, uint32_t& member) {
+    const size_t slot = b / XCDS;
+    group = slot / per * XCDS + b % XCDS;
+    member = (uint32_t)(slot % per);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -453,7 +473,9 @@ struct RowsDigits {
 };
 
 // Tensor product rows fused into the inverse transform: row g = (e 3 + r) LL + l of X is
-// (a0 b0, a0 b1 + a1 b0, a1 b1)[r] in limb l of element e's operands, formed while loading.
+// (a0 b0, a0 b1 + a1 b0, a1 b1)[r] in limb l of element e's operands, formed while loading.  The
+// three rows of one (e, l) read the same four operand rows; the kernel numbers its workgroups so
+// that they run on one XCD (see xcd_split).
 template <class Sh>
 struct RowsTensor {
     const uint32_t* refs;
@@ -521,8 +543,23 @@ __global__ __launch_bounds__(Sh::T) void k_ntt_inv_tensor(const CtxConst* __rest
                                                           const double* __restrict__ twf,
                                                           const uint32_t* __restrict__ refs,
                                                           const uint64_t* __restrict__ leaves,
-                                                          const uint64_t* __restrict__ nodes, uint64_t* __restrict__ X) {
-    ntt_inv_row<Sh, FP>(K, tw, twf, RowsTensor<Sh>{refs, leaves, nodes, X, K, K->LL});
+                                                          const uint64_t* __restrict__ nodes, uint64_t* __restrict__ X,
+                                                          size_t groups) {
+    __shared__ uint64_t sm[Sh::LDS_WORDS];
+    size_t el;
+    uint32_t r;
+    xcd_split(blockIdx.x, 3, el, r);
+    if (el >= groups) return;
+    const uint32_t LL = K->LL;
+    const size_t g = ((el / LL) * 3 + r) * LL + el % LL;
+    const RowsTensor<Sh> row{refs, leaves, nodes, X, K, LL};
+    const uint32_t tid = threadIdx.x;
+    uint64_t a[Sh::EPT];
+    row.load(g, tid, a);
+    const uint32_t pi = row.prime(g);
+    ntt_inv_regs<Sh, FP>(a, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
+#pragma unroll
+    for (int u = 0; u < Sh::EPT; ++u) row.store(g, tid, u, a[u]);
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -537,12 +574,14 @@ __global__ __launch_bounds__(Sh::T) void k_ntt_inv_tensor(const CtxConst* __rest
 template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T) void k_relin(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
                                                  const double* __restrict__ twf, const uint64_t* __restrict__ c3,
-                                                 const uint64_t* __restrict__ rlk, uint64_t* __restrict__ sel) {
+                                                 const uint64_t* __restrict__ rlk, uint64_t* __restrict__ sel, size_t E) {
     __shared__ uint64_t sm[Sh::LDS_WORDS];
     constexpr int N = Sh::N, T = Sh::T, EPT = Sh::EPT;
     const uint32_t L = K->L, tid = threadIdx.x;
-    const uint32_t j = blockIdx.x % L;
-    const size_t e = blockIdx.x / L;
+    size_t e;
+    uint32_t j;
+    xcd_split(blockIdx.x, L, e, j);  // the L workgroups of element e share its digit rows: one XCD
+    if (e >= E) return;
     const uint64_t p = K->p[j], r1 = K->r1[j];
     const TwRow twr = tw_row(tw, twf, j, N);
     const uint64_t* base = c3 + e * 3 * L * N;
@@ -599,16 +638,16 @@ __global__ __launch_bounds__(Sh::T) void k_relin(const CtxConst* __restrict__ K,
 void launch_relin(const Launch& lc, const uint64_t* c3, const uint64_t* rlk, uint64_t* sel, uint32_t E,
                   uint64_t* staging) {
     if (!E) return;
-    const unsigned blocks = (unsigned)((size_t)E * lc.L);
+    const unsigned blocks = (unsigned)xcd_grid(E, lc.L);
 #define CW_RELIN(LG)                                                                                               \
     {                                                                                                              \
         using Sh = DefaultShape<LG>::type;                                                                         \
         if (lc.fp)                                                                                                 \
             hipLaunchKernelGGL((k_relin<Sh, true>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, lc.twf, c3, \
-                               rlk, sel);                                                                          \
+                               rlk, sel, (size_t)E);                                                               \
         else                                                                                                       \
             hipLaunchKernelGGL((k_relin<Sh, false>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, lc.twf,   \
-                               c3, rlk, sel);                                                                      \
+                               c3, rlk, sel, (size_t)E);                                                           \
     }
     switch (lc.logN) {
         case 12: CW_RELIN(12) break;
@@ -667,8 +706,9 @@ void launch_ntt_digits(const Launch& lc, const uint64_t* c3, uint64_t* out, uint
 void launch_ntt_inv_tensor(const Launch& lc, const uint32_t* refs, const uint64_t* leaves, const uint64_t* nodes,
                            uint64_t* X, uint32_t E) {
     if (!E) return;
-    const size_t rows = (size_t)E * 3 * lc.LL;
-    CW_NTT_DISPATCH(lc, k_ntt_inv_tensor, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, refs, leaves, nodes, X)
+    const size_t groups = (size_t)E * lc.LL;
+    CW_NTT_DISPATCH(lc, k_ntt_inv_tensor, dim3((unsigned)xcd_grid(groups, 3)), lc.K, lc.tw, lc.twf, refs, leaves,
+                    nodes, X, groups)
 }
 
 void launch_ntt_payload(const Launch& lc, const uint16_t* pay, uint64_t* out, size_t rows_u16) {
