@@ -27,6 +27,8 @@ struct ConvTable {
     uint64_t M[MAX_CONV][MAX_CONV];              // (P/p_i) mod r_j
     uint64_t Mq[MAX_CONV][MAX_CONV];             // Shoup companions
     uint64_t Pm[MAX_CONV], Pmq[MAX_CONV];        // P mod r_j
+    double Md[MAX_CONV][MAX_CONV];               // (P/p_i) mod r_j as doubles (fp64 path)
+    double Pmd[MAX_CONV];                        // P mod r_j as doubles
     uint64_t Pw[MAX_W];                          // P, little-endian words
     uint64_t Phat[MAX_CONV][MAX_W];              // P / p_i
 };
@@ -49,6 +51,7 @@ struct CtxConst {
     uint64_t tqinv[MAX_L], tqinvq[MAX_L];        // [t (q/q_i)^{-1}]_{q_i}
     uint64_t kb1[MAX_LB], kb1q[MAX_LB];          // [t q^{-1} (B/b_j)^{-1}]_{b_j}
     uint64_t kb2[MAX_LB], kb2q[MAX_LB];          // [q^{-1} (B/b_j)^{-1}]_{b_j}
+    double tqinvd[MAX_L], kb1d[MAX_LB], kb2d[MAX_LB];  // the same constants as doubles (fp64 path)
     ConvTable qb;                                // q -> B
     ConvTable bq;                                // B -> q
 };

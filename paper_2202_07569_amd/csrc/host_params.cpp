@@ -139,12 +139,14 @@ static void build_conv(ConvTable& T, const std::vector<uint64_t>& in, const std:
         for (size_t j = 0; j < out.size(); ++j) {
             T.M[i][j] = mw_mod(Ph, out[j]);
             T.Mq[i][j] = shoup(T.M[i][j], out[j]);
+            T.Md[i][j] = (double)T.M[i][j];
         }
     }
     for (size_t j = 0; j < out.size(); ++j) {
         T.pout[j] = out[j];
         T.Pm[j] = mw_mod(P, out[j]);
         T.Pmq[j] = shoup(T.Pm[j], out[j]);
+        T.Pmd[j] = (double)T.Pm[j];
     }
 }
 
@@ -181,6 +183,7 @@ void build_const(CtxConst& K, uint32_t N, const std::vector<uint64_t>& q, const 
         K.qinvq[i] = shoup(K.qinv[i], p);
         K.tqinv[i] = mulmod(t % p, K.qinv[i], p);
         K.tqinvq[i] = shoup(K.tqinv[i], p);
+        K.tqinvd[i] = (double)K.tqinv[i];
     }
     for (uint32_t j = 0; j < K.LB; ++j) {
         uint64_t b = B[j];
@@ -190,6 +193,8 @@ void build_const(CtxConst& K, uint32_t N, const std::vector<uint64_t>& q, const 
         K.kb2q[j] = shoup(K.kb2[j], b);
         K.kb1[j] = mulmod(t % b, K.kb2[j], b);
         K.kb1q[j] = shoup(K.kb1[j], b);
+        K.kb1d[j] = (double)K.kb1[j];
+        K.kb2d[j] = (double)K.kb2[j];
     }
     build_conv(K.qb, q, B);
     build_conv(K.bq, B, q);

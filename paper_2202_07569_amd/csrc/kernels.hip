@@ -807,6 +807,62 @@ __device__ __forceinline__ bool scale_coeff(const CtxConst* K, const uint64_t* x
     return amb;
 }
 
+// fp64 form (every prime below 2^50): the same conversions on signed representatives.  The
+// rounding decisions v, v2 come from double sums whose error is below 2^-45; a sum within 2^-40
+// of a half is reported as ambiguous and the exact integer form redoes the coefficient.  Partial
+// sums are reduced every four terms so every value stays below 2^53 (see fmulmod).
+#pragma clang fp contract(off)
+template <int NL, int NB>
+__device__ __forceinline__ bool scale_coeff_fp(const CtxConst* K, const uint64_t* x, size_t xs, uint64_t* cq) {
+    const uint32_t L = K->L, LB = K->LB;
+    double y[NL];
+    double S = 0.0;
+#pragma unroll
+    for (int i = 0; i < NL; ++i)
+        if (i < (int)L) {
+            const double p = K->pd[i], pinv = K->pinv[i];
+            y[i] = fmulmod((double)x[i * xs], K->tqinvd[i], p, pinv);
+            S += y[i] * pinv;
+        }
+    const double v = __builtin_rint(S);
+    bool amb = __builtin_fabs(S - v) > 0.5 - 0x1p-40;
+    double z[NB];
+    double S2 = 0.0;
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+        if (j < (int)LB) {
+            const uint32_t jj = L + j;
+            const double b = K->pd[jj], binv = K->pinv[jj];
+            double rb = -fmulmod(v, K->qb.Pmd[j], b, binv);
+#pragma unroll
+            for (int i = 0; i < NL; ++i)
+                if (i < (int)L) {
+                    rb += fmulmod(y[i], K->qb.Md[i][j], b, binv);
+                    if ((i & 3) == 3) rb = fred(rb, b, binv);
+                }
+            const double zz = fmulmod((double)x[jj * xs], K->kb1d[j], b, binv) - fmulmod(rb, K->kb2d[j], b, binv);
+            z[j] = fred(zz, b, binv);
+            S2 += z[j] * binv;
+        }
+    const double v2 = __builtin_rint(S2);
+    amb |= __builtin_fabs(S2 - v2) > 0.5 - 0x1p-40;
+#pragma unroll
+    for (int i = 0; i < NL; ++i)
+        if (i < (int)L) {
+            const double p = K->pd[i], pinv = K->pinv[i];
+            double c = -fmulmod(v2, K->bq.Pmd[i], p, pinv);
+#pragma unroll
+            for (int j = 0; j < NB; ++j)
+                if (j < (int)LB) {
+                    c += fmulmod(z[j], K->bq.Md[j][i], p, pinv);
+                    if ((j & 3) == 3) c = fred(c, p, pinv);
+                }
+            cq[i] = fp_to_residue(fred(c, p, pinv), p);
+        }
+    return amb;
+}
+#pragma clang fp contract(on)
+
 template <int NL>
 __device__ __forceinline__ void scale_store(const CtxConst* K, const uint64_t* cq, uint64_t* out, size_t er, size_t c) {
     const uint32_t N = K->N, L = K->L;
@@ -816,7 +872,7 @@ __device__ __forceinline__ void scale_store(const CtxConst* K, const uint64_t* c
         if (i < (int)L) o[(size_t)i * N] = cq[i];
 }
 
-template <int NL, int NB>
+template <int NL, int NB, bool FP>
 __global__ void k_scale(const CtxConst* __restrict__ K, const uint64_t* __restrict__ X, uint64_t* __restrict__ out,
                         uint32_t E, uint64_t* fix, uint32_t* fixcnt) {
     const uint32_t N = K->N, LL = K->LL;
@@ -824,7 +880,10 @@ __global__ void k_scale(const CtxConst* __restrict__ K, const uint64_t* __restri
     if (gid >= (size_t)E * 3 * N) return;
     const size_t c = gid % N, er = gid / N;
     uint64_t cq[NL];
-    if (scale_coeff<NL, NB>(K, X + er * LL * N + c, N, cq, false)) fix[atomicAdd(fixcnt, 1u)] = gid;
+    bool amb;
+    if constexpr (FP) amb = scale_coeff_fp<NL, NB>(K, X + er * LL * N + c, N, cq);
+    else amb = scale_coeff<NL, NB>(K, X + er * LL * N + c, N, cq, false);
+    if (amb) fix[atomicAdd(fixcnt, 1u)] = gid;
     scale_store<NL>(K, cq, out, er, c);
 }
 
@@ -848,8 +907,12 @@ void launch_scale(const Launch& lc, const uint64_t* X, uint64_t* out, uint32_t E
     if (!E) return;
     const unsigned nb = blocks_for((size_t)E * 3 * lc.N);
 #define CW_SCALE(NLV, NBV)                                                                                    \
-    hipLaunchKernelGGL((k_scale<NLV, NBV>), dim3(nb), dim3(EW_THREADS), 0, lc.stream, lc.K, X, out, E, lc.fix, \
-                       lc.fixcnt);                                                                            \
+    if (lc.fp)                                                                                                \
+        hipLaunchKernelGGL((k_scale<NLV, NBV, true>), dim3(nb), dim3(EW_THREADS), 0, lc.stream, lc.K, X, out, E, \
+                           lc.fix, lc.fixcnt);                                                                \
+    else                                                                                                      \
+        hipLaunchKernelGGL((k_scale<NLV, NBV, false>), dim3(nb), dim3(EW_THREADS), 0, lc.stream, lc.K, X, out, E, \
+                           lc.fix, lc.fixcnt);                                                                \
     hipLaunchKernelGGL((k_scale_fix<NLV, NBV>), dim3(1), dim3(256), 0, lc.stream, lc.K, X, out, lc.fix, lc.fixcnt);
     if (lc.L <= 4 && lc.LB <= 5) {
         CW_SCALE(4, 5)
