@@ -36,6 +36,13 @@ MI355X_HBM_GBPS = 8000.0
 # v_mad_u64_u32) run at half that rate, 39.3 T/s (measured 31-33 T/s with an ALU-only probe).
 MI355X_INT_MUL_PER_S = 256 * 4 * 32 * 2.4e9 / 2
 MULS_PER_BUTTERFLY = 10  # 64-bit Shoup butterfly: hi64(a w') 5 mads, lo64(a w) and lo64(q p) 4 muls + 1 mul_hi
+# fp64 roof: 78.6 TFLOP/s counting an FMA as two flops = 39.3 T fp64 instructions/s.  The fp64
+# butterfly (primes below 2^50) needs 8: y*w, fma, h*(1/p), rint, fma, + l, X + T, X - T.
+MI355X_FP64_INSTR_PER_S = 78.6e12 / 2
+FP64_OPS_PER_BUTTERFLY = 8
+FP_PRIME_BOUND = 1 << 50
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mid_answer_traffic.json")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2202_07569_amd", "csrc", f) for f in ("kernels.hip", "arith.h", "consts.h")]
 
 
 def log(msg):
@@ -53,6 +60,8 @@ def parse():
     ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle sample elements (0: skip)")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--chunk", type=int, default=0, help="elements per processing chunk (0: library default)")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (reference for rocprofv3 byte counters)")
     return ap.parse_args()
 
 
@@ -123,6 +132,16 @@ def main():
         ctx.profile(False)
         return total, per, prof
 
+    if args.copy_calibration_mib:
+        nbytes = args.copy_calibration_mib << 20
+        src = torch.empty(nbytes // 8, dtype=torch.int64, device="cuda").fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"copy calibration: 3 copies of {args.copy_calibration_mib} MiB")
+        del src, dst
+
     log("plain loop")
     t_plain, per_plain, prof_plain = timed(step_plain, args.steps, args.warmup, False)
     log(f"plain {t_plain / args.steps * 1e3:.1f} ms/query")
@@ -132,7 +151,8 @@ def main():
     value = B * n * args.steps / t_b
     log(f"batched {ms_step:.1f} ms/step -> {value:.0f} elements/s")
 
-    roof = roofline(prof, args.steps, cfg.N) if prof else None
+    fp = cfg.N <= 8192 and all(p < FP_PRIME_BOUND for p in tuple(cfg.primes) + ctx.aux_primes)
+    roof = roofline(prof, args.steps, fp, traffic_table(cfg, n, B, args.chunk)) if prof else None
 
     cpu = None
     sample = args.cpu_sample if args.cpu_sample >= 0 else (256 if cfg.N <= 8192 else 32)
@@ -160,13 +180,26 @@ def main():
 NTT_FAMILIES = ("ntt_fwd", "ntt_inv", "ntt_inv_tensor", "ntt_digits", "relin", "payload_ntt")
 
 
-def roofline(prof, steps, N):
+def traffic_table(cfg, n, B, chunk):
+    """Calibrated HBM bytes per launch from the committed rocprofv3 counter summary, when it was
+    taken on this workload shape and the kernel sources have not changed since."""
+    import hashlib
+    if cfg.name != "mid" or n != cfg.n or B != 4 or chunk not in (0, 256) or not os.path.exists(TRAFFIC_FILE):
+        return None
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    data = json.load(open(TRAFFIC_FILE))
+    return data["families"] if data.get("kernel_source_sha256") == h.hexdigest() else None
+
+
+def roofline(prof, steps, fp, traffic):
     """Roofline entry of the kernel family with the largest share of the timed region.
 
-    Transforms are bound by the 32-bit integer multipliers: one lazy Shoup butterfly on 64-bit
-    words takes MULS_PER_BUTTERFLY multiplies, so the peak is MI355X_INT_MUL_PER_S /
-    MULS_PER_BUTTERFLY butterflies per second; achieved = algorithmic butterflies of one launch
-    (rows x N/2 x log2 N) / the launch's average duration from HIP events on its stream.
+    Transforms are ALU-bound.  Integer path: one lazy Shoup butterfly on 64-bit words takes
+    MULS_PER_BUTTERFLY 32-bit multiplies; fp64 path (every prime below 2^50): FP64_OPS_PER_BUTTERFLY
+    fp64 instructions.  peak = the unit's rate / that count; achieved = algorithmic butterflies of
+    one launch (rows x N/2 x log2 N) / the launch's average duration from HIP events on its stream.
     """
     name, (tot_ms, launches, work) = max(prof.items(), key=lambda kv: kv[1][0])
     avg_ms = tot_ms / launches
@@ -176,9 +209,12 @@ def roofline(prof, steps, N):
     if name in NTT_FAMILIES:
         per_launch = work / launches
         achieved = per_launch / (avg_ms * 1e-3)
-        peak = MI355X_INT_MUL_PER_S / MULS_PER_BUTTERFLY
+        peak = (MI355X_FP64_INSTR_PER_S / FP64_OPS_PER_BUTTERFLY) if fp else (MI355X_INT_MUL_PER_S / MULS_PER_BUTTERFLY)
+        tr = traffic.get(name, {}).get("bytes_per_launch") if traffic else None
         out.update({"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12, "unit": "Tbutterfly/s",
-                    "frac": achieved / peak, "traffic": None, "butterflies_per_launch": per_launch})
+                    "frac": achieved / peak, "traffic": tr, "arith": "fp64" if fp else "int64",
+                    "butterflies_per_launch": per_launch,
+                    "hbm_GBps_at_traffic": (tr / (avg_ms * 1e-3) / 1e9) if tr else None})
     return out
 
 

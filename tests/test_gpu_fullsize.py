@@ -1,0 +1,88 @@
+"""Full-size checks of the HIP path in the configuration the benchmark times.
+
+The oracle cannot compute a whole answer over tens of thousands of elements in seconds, so at
+full size the checks use what holds at any size: the decrypted answer is the queried payload (zero
+for an absent keyword), sampled selectors equal the oracle's bit for bit, the answer is linear over
+a split of the database, and a batch equals the single answers.
+"""
+import numpy as np
+import pytest
+
+import datagen
+from oracle.client import build_instance, encrypt_query
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev(a):
+    return _torch().from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _host(t):
+    _torch().cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def _say(msg):
+    print(f"[gpu-full] {msg}", flush=True)
+
+
+def _check(cfg, ins, samples, absent=False, split=None):
+    from paper_2202_07569_amd import Context
+    ctx = Context(cfg.N, cfg.primes, cfg.t)
+    key = ctx.load_key(ins.rlk)
+    db = ctx.encode_db(ins.codewords, ins.payload, cfg.m)
+    _say(f"{cfg.name}: answer over n={cfg.n}")
+    ans = _host(ctx.answer(key, db, _dev(ins.query)))
+    for r in range(cfg.s):
+        msg, noise = ins.orc.decrypt(ins.sk, ans[r])
+        want = np.zeros(cfg.N, np.uint64) if absent else ins.payload[ins.target][r].astype(np.uint64)
+        assert np.array_equal(msg, want), r
+        assert noise < ins.orc.log2_half_delta() - 8
+    _say(f"{cfg.name}: sampled selectors {list(samples)}")
+    sel = _host(ctx.selectors(key, db, _dev(ins.query), np.array(samples, dtype=np.uint64)))
+    for i, j in enumerate(samples):
+        assert np.array_equal(sel[i], ins.orc.selector(ins.key, ins.query, ins.codewords[j])), j
+    if split:
+        _say(f"{cfg.name}: linearity at {split}")
+        q = np.array(cfg.primes, dtype=np.uint64).reshape(1, 1, -1, 1)
+        da = ctx.encode_db(ins.codewords[:split], ins.payload[:split], cfg.m)
+        dbb = ctx.encode_db(ins.codewords[split:], ins.payload[split:], cfg.m)
+        a = _host(ctx.answer(key, da, _dev(ins.query)))
+        b = _host(ctx.answer(key, dbb, _dev(ins.query)))
+        assert np.array_equal(ans, (a + b) % q)
+    return ctx, key, db, ans
+
+
+def test_mid_full_size():
+    cfg = datagen.CONFIGS["mid"]
+    ins = build_instance(cfg)
+    ctx, key, db, ans = _check(cfg, ins, [ins.target, 0, cfg.n - 1], split=9001)
+    assert db.pair_count <= 351
+    # a batch of two queries on the database (the second for another element) equals the singles
+    other = (ins.target + 777) % cfg.n
+    q2 = encrypt_query(ins.orc, ins.sk, [int(v) for v in ins.codewords[other]], cfg.m, cfg.seed, draw=5)
+    _say("mid: batch of two")
+    outs = ctx.answer_batch([key, key], [db, db], [_dev(ins.query), _dev(q2)])
+    assert np.array_equal(_host(outs[0]), ans)
+    msg, _ = ins.orc.decrypt(ins.sk, _host(outs[1])[0])
+    assert np.array_equal(msg, ins.payload[other][0].astype(np.uint64))
+
+
+def test_large_full_size():
+    cfg = datagen.CONFIGS["large"]
+    ins = build_instance(cfg)
+    _check(cfg, ins, [ins.target, 1, cfg.n - 1])
+
+
+@pytest.mark.parametrize("absent", [False, True])
+def test_keyword_full_size(absent):
+    cfg = datagen.CONFIGS["keyword"]
+    ins = build_instance(cfg, absent=absent)
+    samples = [0, cfg.n - 1] if absent else [ins.target, cfg.n - 1]
+    _check(cfg, ins, samples, absent=absent)
