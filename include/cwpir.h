@@ -60,7 +60,7 @@ extern "C" {
 #define PIR_E_INVALID (-1)     /* bad shape or parameter, residue >= q_i, bad codeword          */
 #define PIR_E_NOMEM (-2)       /* allocation failed or the HBM budget is exceeded               */
 #define PIR_E_DEVICE (-3)      /* HIP runtime error; the context is poisoned                    */
-#define PIR_E_BUSY (-4)        /* no free serving slot                                          */
+#define PIR_E_BUSY (-4)        /* reserved                                                      */
 #define PIR_E_UNSUPPORTED (-5) /* N not in {4096, 8192, 16384}, L or k out of range             */
 
 #define PIR_MAX_L 12           /* ciphertext primes */
@@ -69,6 +69,7 @@ extern "C" {
 typedef struct pir_ctx pir_ctx;
 typedef struct pir_key pir_key;
 typedef struct pir_db pir_db;
+typedef struct pir_server pir_server;
 
 typedef struct {
     uint32_t N;                /* ring degree: 4096, 8192 or 16384                                */
@@ -110,6 +111,41 @@ int pir_answer(pir_ctx* ctx, const pir_key* key, const pir_db* db, const uint64_
  * answers[b] are as in pir_answer.  Every answer is bit-identical to pir_answer's.  Asynchronous. */
 int pir_answer_batch(pir_ctx* ctx, uint32_t B, const pir_key* const* keys, const pir_db* const* dbs,
                      const uint64_t* const* queries, uint64_t* const* answers, void* stream);
+
+/* Serving with continuous batching (Section 3.3.3 "Process", applied to a stream of queries on
+ * several resident databases).  A server queues submitted queries and, at every pir_serve_step,
+ * admits waiting queries into free slots and then advances each database that has active queries
+ * by one chunk of elements: all its active queries compute their selectors for that chunk side by
+ * side (as in pir_answer_batch) and share one transform of the chunk's payload.  A database's chunk
+ * cursor rotates, so a query admitted mid-scan starts at the current chunk and completes after
+ * one full cycle.  The answer is a sum over all elements and is bit-identical to pir_answer's.
+ *
+ *   pir_serve_open    server with max_slots (1..1024) concurrent queries and its own HIP stream
+ *                     (default priority).  Synchronous.
+ *   pir_serve_submit  queue one query; *ticket receives its id.  key/db from this context; query
+ *                     (dev [m][2][L][N]) must be ready on the device when submitted and stay
+ *                     unmodified, and answer (dev [s][2][L][N]) stays unread, until the ticket
+ *                     completes.  Host-side only: enqueues no device work.
+ *   pir_serve_step    admit (in submission order, while each query's buffers fit the context's
+ *                     HBM budget) and run one round; returns the number of queries queued or active
+ *                     (>= 0), or an error.  PIR_E_NOMEM when no query is active and the oldest
+ *                     waiting one does not fit (it stays queued).  Keeps at most two rounds queued
+ *                     on the device.  Ordered after the context's other asynchronous calls.
+ *   pir_serve_poll    1 when the ticket's answer is complete in device memory (the ticket is then
+ *                     released), 0 while it is queued or running, PIR_E_INVALID for an unknown or
+ *                     released ticket.
+ *   pir_serve_stats   counters: rounds run, queries admitted, tickets released; slots in use and
+ *                     queries waiting now.  Any output pointer may be NULL.
+ *   pir_serve_close   wait for the server's queued work and release its slots and stream.
+ * A server belongs to one context; calls on it are serialised with that context's other calls. */
+int pir_serve_open(pir_ctx* ctx, uint32_t max_slots, pir_server** out);
+int pir_serve_submit(pir_server* srv, const pir_key* key, const pir_db* db, const uint64_t* query,
+                     uint64_t* answer, uint64_t* ticket);
+int pir_serve_step(pir_server* srv);
+int pir_serve_poll(pir_server* srv, uint64_t ticket);
+int pir_serve_stats(pir_server* srv, uint64_t* rounds, uint64_t* admitted, uint64_t* completed,
+                    uint32_t* active, uint32_t* pending);
+void pir_serve_close(pir_server* srv);
 
 /* FV operations on single ciphertexts (Section 2.1.1: Multiplication, Plain multiplication), the
  * building blocks of the path, exposed for checking.  All pointers dev; asynchronous.

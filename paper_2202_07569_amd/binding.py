@@ -20,7 +20,8 @@ EXPORTS = [
     "pir_setup", "pir_load_key", "pir_encode_db", "pir_answer", "pir_answer_batch", "pir_mult", "pir_relin",
     "pir_pm", "pir_selectors", "pir_map_perfect", "pir_map_lossy", "pir_ctx_aux_primes", "pir_ctx_device_bytes",
     "pir_db_pair_count", "pir_profile_enable", "pir_profile_read", "pir_db_free", "pir_key_free", "pir_free",
-    "pir_last_error",
+    "pir_last_error", "pir_serve_open", "pir_serve_submit", "pir_serve_step", "pir_serve_poll", "pir_serve_stats",
+    "pir_serve_close",
 ]
 
 
@@ -74,6 +75,14 @@ def lib():
             "pir_key_free": (None, [vp]),
             "pir_free": (None, [vp]),
             "pir_last_error": (ctypes.c_char_p, []),
+            "pir_serve_open": (i32, [vp, u32, pp]),
+            "pir_serve_submit": (i32, [vp, vp, vp, vp, vp, ctypes.POINTER(ctypes.c_uint64)]),
+            "pir_serve_step": (i32, [vp]),
+            "pir_serve_poll": (i32, [vp, u64]),
+            "pir_serve_stats": (i32, [vp, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64),
+                                      ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32),
+                                      ctypes.POINTER(ctypes.c_uint32)]),
+            "pir_serve_close": (None, [vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -299,3 +308,79 @@ class Context:
         if n < 0:
             _check(n)
         return {names[i].decode(): (ms[i], int(cnt[i]), work[i]) for i in range(min(n, cap))}
+
+
+class Server:
+    """Continuous-batching server over one context's resident databases (pir_serve_*).
+
+    submit() queues a query and returns its ticket; step() admits waiting queries and runs one
+    round; poll(ticket) is True once that answer is complete, after which result(ticket) hands
+    back the answer tensor.  The binding keeps each query and answer tensor alive until then.
+    """
+
+    def __init__(self, ctx: Context, max_slots: int = 16):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        _check(lib().pir_serve_open(ctx._h, max_slots, ctypes.byref(h)))
+        self._h = h
+        self._live = {}   # ticket -> (query, answer) while queued or running
+        self._done = {}   # ticket -> answer once complete
+
+    def submit(self, key: Key, db: Database, query, out=None) -> int:
+        ctx = self.ctx
+        query = _dev_u64(query, ctx.device)
+        assert tuple(query.shape) == (db.m, 2, ctx.L, ctx.N)
+        if out is None:
+            out = ctx.empty(db.s, 2, ctx.L, ctx.N)
+        _torch().cuda.current_stream(ctx.device).synchronize()  # the query must be on the device
+        t = ctypes.c_uint64()
+        _check(lib().pir_serve_submit(self._h, key._h, db._h, _ptr(query), _ptr(out), ctypes.byref(t)))
+        self._live[t.value] = (query, out)
+        return t.value
+
+    def step(self) -> int:
+        rc = lib().pir_serve_step(self._h)
+        if rc < 0:
+            _check(rc)
+        return rc
+
+    def poll(self, ticket: int) -> bool:
+        if ticket in self._done:
+            return True
+        rc = lib().pir_serve_poll(self._h, ticket)
+        if rc < 0:
+            _check(rc)
+        if rc == 1:
+            self._done[ticket] = self._live.pop(ticket)[1]
+        return rc == 1
+
+    def result(self, ticket: int):
+        return self._done.pop(ticket)
+
+    def stats(self) -> dict:
+        r, a, c = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+        act, pend = ctypes.c_uint32(), ctypes.c_uint32()
+        _check(lib().pir_serve_stats(self._h, ctypes.byref(r), ctypes.byref(a), ctypes.byref(c), ctypes.byref(act),
+                                     ctypes.byref(pend)))
+        return {"rounds": r.value, "admitted": a.value, "completed": c.value, "active": act.value,
+                "pending": pend.value}
+
+    def drain(self, tickets=None):
+        """Step until every given ticket (default: all submitted) is complete."""
+        want = list(self._live) if tickets is None else list(tickets)
+        while True:
+            if all(self.poll(t) for t in want):
+                return
+            self.step()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pir_serve_close(self._h)
+            self._h = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

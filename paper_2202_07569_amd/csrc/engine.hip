@@ -14,6 +14,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <deque>
 #include <map>
 #include <mutex>
 #include <set>
@@ -293,7 +294,7 @@ extern "C" int pir_setup(const pir_params* params, pir_ctx** out) {
     if (fp && (rc = dev_alloc(ctx, (void**)&ctx->dtwf, twf.size() * 8)) != PIR_OK) return cleanup(rc);
     if (fp && hipMemcpy(ctx->dtwf, twf.data(), twf.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
         return cleanup(fail(PIR_E_DEVICE, "twiddle upload failed"));
-    ctx->fix_cap = (size_t)3 * ctx->chunk * ctx->N;
+    ctx->fix_cap = (size_t)3 * ctx->chunk * ctx->N * cw::MAX_QB;  // coefficients of one batched launch
     if ((rc = dev_alloc(ctx, (void**)&ctx->dfix, ctx->fix_cap * 8)) != PIR_OK) return cleanup(rc);
     if ((rc = dev_alloc(ctx, (void**)&ctx->dfixcnt, 256)) != PIR_OK) return cleanup(rc);
     if (hipMemcpy(ctx->dK, &ctx->K, sizeof(CtxConst), hipMemcpyHostToDevice) != hipSuccess ||
@@ -535,19 +536,39 @@ extern "C" uint64_t pir_db_pair_count(const pir_db* db) { return db ? db->total_
 // the path
 // ------------------------------------------------------------------------------------------------
 struct Bufs {
-    uint64_t* X = nullptr;   // [E][3][LL][N]  tensor product over Q u B
-    uint64_t* C = nullptr;   // [E][3][L][N]   after scale-and-round, coefficient form
-    uint64_t* R = nullptr;   // [E][L+2][L][N] transformed digits (only where key switching is staged)
-    uint64_t* Ph = nullptr;  // [E][s][L][N]   transformed payload rows
+    uint64_t* X = nullptr;   // [QB E][3][LL][N]  tensor products over Q u B
+    uint64_t* C = nullptr;   // [QB E][3][L][N]   after scale-and-round, coefficient form
+    uint64_t* R = nullptr;   // [QB E][L+2][L][N] transformed digits (only where key switching is staged)
+    uint64_t* Ph = nullptr;  // [E][s][L][N]      transformed payload rows
 };
 
-static int get_bufs(pir_ctx* ctx, uint32_t E, uint32_t s, Bufs& b) {
-    const size_t N = ctx->N, L = ctx->L, LL = ctx->LL;
-    CW_TRY(ws_get_t(ctx, "X", (size_t)E * 3 * LL * N, &b.X));
-    CW_TRY(ws_get_t(ctx, "C", (size_t)E * 3 * L * N, &b.C));
-    if (cw::relin_needs_staging(ctx->logN)) CW_TRY(ws_get_t(ctx, "R", (size_t)E * (L + 2) * L * N, &b.R));
+// Work buffers for launches over up to `nq` queries of E elements each.
+static int get_bufs(pir_ctx* ctx, uint32_t E, uint32_t nq, uint32_t s, Bufs& b) {
+    const size_t N = ctx->N, L = ctx->L, LL = ctx->LL, EQ = (size_t)E * nq;
+    CW_TRY(ws_get_t(ctx, "X", EQ * 3 * LL * N, &b.X));
+    CW_TRY(ws_get_t(ctx, "C", EQ * 3 * L * N, &b.C));
+    if (cw::relin_needs_staging(ctx->logN)) CW_TRY(ws_get_t(ctx, "R", EQ * (L + 2) * L * N, &b.R));
     if (s) CW_TRY(ws_get_t(ctx, "Ph", (size_t)E * s * L * N, &b.Ph));
     return PIR_OK;
+}
+
+// Per-query state of one answer in progress.
+struct QState {
+    const pir_key* key = nullptr;
+    const uint64_t* query = nullptr;  // caller's [m][2][L][N]
+    uint64_t* answer = nullptr;       // caller's [s][2][L][N]; accumulates in the transformed domain
+    uint64_t* QX = nullptr;           // resident query [m][2][LL][N]
+    uint64_t* nodes = nullptr;        // level-1 products [max_pairs][2][LL][N] (k >= 3)
+    uint64_t* sel = nullptr;          // selectors [E][2][L][N]
+};
+
+static size_t qx_words(const pir_ctx* ctx, const pir_db* db) { return (size_t)db->m * 2 * ctx->LL * ctx->N; }
+static size_t node_words(const pir_ctx* ctx, const pir_db* db) {
+    return db->k >= 3 ? (size_t)std::max<uint32_t>(db->max_pairs, 1) * 2 * ctx->LL * ctx->N : 0;
+}
+static size_t sel_words(const pir_ctx* ctx) { return (size_t)ctx->chunk * 2 * ctx->L * ctx->N; }
+static uint32_t num_chunks(const pir_ctx* ctx, const pir_db* db) {
+    return (uint32_t)((db->n + ctx->chunk - 1) / ctx->chunk);
 }
 
 // Query residency: extend [m][2][L][N] to Q u B and transform.
@@ -566,37 +587,49 @@ static int make_leaves(pir_ctx* ctx, const Launch& lc, const uint64_t* query, ui
     return check_launch(ctx);
 }
 
-// Mult + Relin of `cnt` operand pairs (refs into leaves/nodes); result transformed over Q in sel.
-static void mult_relin(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint32_t* refs, const uint64_t* leaves,
-                       const uint64_t* nodes, const pir_key* key, uint64_t* sel, uint32_t cnt) {
-    const uint32_t LL = ctx->LL;
+// Mult + Relin of bt.E operand pairs (refs into leaves/nodes) for each query of the batch; the
+// results, transformed over Q, go to bt.sel[q].
+static void mult_relin(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint32_t* refs, const cw::Batch& bt) {
+    const size_t rows = (size_t)bt.nq * bt.E;
     {
-        Prof pr(ctx, "ntt_inv_tensor", lc.stream, bfly(ctx, (size_t)cnt * 3 * LL));
-        cw::launch_ntt_inv_tensor(lc, refs, leaves, nodes, b.X, cnt);
+        Prof pr(ctx, "ntt_inv_tensor", lc.stream, bfly(ctx, rows * 3 * ctx->LL));
+        cw::launch_ntt_inv_tensor(lc, refs, bt, b.X);
     }
     {
-        Prof pr(ctx, "scale", lc.stream, (double)cnt * 3 * ctx->N);
-        cw::launch_scale(lc, b.X, b.C, cnt);
+        Prof pr(ctx, "scale", lc.stream, (double)rows * 3 * ctx->N);
+        cw::launch_scale(lc, b.X, b.C, (uint32_t)rows);
     }
-    Prof pr(ctx, "relin", lc.stream, bfly(ctx, (size_t)cnt * (ctx->L + 2) * ctx->L));
-    cw::launch_relin(lc, b.C, key->d, sel, cnt, b.R);
+    Prof pr(ctx, "relin", lc.stream, bfly(ctx, rows * (ctx->L + 2) * ctx->L));
+    cw::launch_relin(lc, b.C, bt, b.R);
 }
 
-// Level-1 products of pairs[0..np) into nodes (extended, transformed), in chunks of E.
+static cw::Batch one_query(uint32_t E, const uint64_t* leaves, const uint64_t* nodes, const pir_key* key, uint64_t* sel) {
+    cw::Batch bt{};
+    bt.nq = 1;
+    bt.E = E;
+    bt.leaves[0] = leaves;
+    bt.nodes[0] = nodes;
+    bt.rlk[0] = key->d;
+    bt.sel[0] = sel;
+    return bt;
+}
+
+// Level-1 products of pairs[0..np) into nodes (extended, transformed), in chunks of E; `tmp` holds
+// E selectors.
 static void make_nodes(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint32_t* pairs, uint32_t np,
-                       const uint64_t* leaves, const pir_key* key, uint64_t* tmp_sel, uint64_t* nodes, uint32_t E) {
+                       const uint64_t* leaves, const pir_key* key, uint64_t* tmp, uint64_t* nodes, uint32_t E) {
     const size_t N = ctx->N, L = ctx->L, LL = ctx->LL;
     for (uint32_t p0 = 0; p0 < np; p0 += E) {
         const uint32_t cnt = std::min(E, np - p0);
-        mult_relin(ctx, lc, b, pairs + 2 * (size_t)p0, leaves, nullptr, key, tmp_sel, cnt);
+        mult_relin(ctx, lc, b, pairs + 2 * (size_t)p0, one_query(cnt, leaves, nullptr, key, tmp));
         {
             Prof pr(ctx, "ntt_inv", lc.stream, bfly(ctx, (size_t)cnt * 2 * L));
-            cw::launch_ntt(lc, true, tmp_sel, tmp_sel, (size_t)cnt * 2 * L, L, 0);
+            cw::launch_ntt(lc, true, tmp, tmp, (size_t)cnt * 2 * L, L, 0);
         }
         uint64_t* dst = nodes + (size_t)p0 * 2 * LL * N;
         {
             Prof pr(ctx, "extend", lc.stream, (double)2 * cnt * N);
-            cw::launch_extend(lc, tmp_sel, dst, (size_t)2 * cnt);
+            cw::launch_extend(lc, tmp, dst, (size_t)2 * cnt);
         }
         Prof pr(ctx, "ntt_fwd", lc.stream, bfly(ctx, (size_t)cnt * 2 * LL));
         cw::launch_ntt(lc, false, dst, dst, (size_t)cnt * 2 * LL, LL, 0);
@@ -604,69 +637,107 @@ static void make_nodes(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint
 }
 
 static void roots(pir_ctx* ctx, const Launch& lc, const Bufs& b, uint32_t k, const uint32_t* refs,
-                  const uint64_t* leaves, const uint64_t* nodes, const pir_key* key, uint64_t* sel, uint32_t cnt) {
+                  const cw::Batch& bt) {
     if (k == 1) {
         Prof pr(ctx, "gather", lc.stream);
-        cw::launch_gather_leaf(lc, refs, leaves, sel, cnt);
+        cw::launch_gather_leaf(lc, refs, bt);
         return;
     }
-    mult_relin(ctx, lc, b, refs, leaves, nodes, key, sel, cnt);
+    mult_relin(ctx, lc, b, refs, bt);
+}
+
+// Start an answer: resident query, zeroed accumulator and, when the database shares its level-1
+// products across all elements, those products.
+static int prepare_query(pir_ctx* ctx, const Launch& lc, const Bufs& b, const pir_db* db, QState& qs) {
+    CW_TRY(make_leaves(ctx, lc, qs.query, db->m, qs.QX));
+    {
+        Prof pr(ctx, "fill", lc.stream);
+        cw::launch_fill(lc.stream, qs.answer, (size_t)db->s * 2 * ctx->L * ctx->N, 0);
+    }
+    if (db->groups.size() == 1 && db->groups[0].np)
+        make_nodes(ctx, lc, b, db->dpairs, db->groups[0].np, qs.QX, qs.key, qs.sel, qs.nodes, ctx->chunk);
+    return check_launch(ctx);
+}
+
+// One chunk of the database for a set of queries: their selectors (one launch per stage for up to
+// MAX_QB queries), one transform of the chunk's payload rows, and one multiply-accumulate launch
+// for up to MAX_BATCH queries.
+static int chunk_step(pir_ctx* ctx, const Launch& lc, const Bufs& b, const pir_db* db, uint32_t c, QState* const* qs,
+                      uint32_t nq) {
+    const size_t N = ctx->N, L = ctx->L;
+    const uint32_t E = ctx->chunk, s = db->s, k = db->k;
+    const uint64_t e0 = (uint64_t)c * E;
+    const uint32_t cnt = (uint32_t)std::min<uint64_t>(E, db->n - e0);
+    if (db->groups.size() > 1 && db->groups[c].np)  // level-1 products shared within this chunk only
+        for (uint32_t q = 0; q < nq; ++q)
+            make_nodes(ctx, lc, b, db->dpairs + 2 * (size_t)db->groups[c].p0, db->groups[c].np, qs[q]->QX, qs[q]->key,
+                       qs[q]->sel, qs[q]->nodes, E);
+    const uint32_t* refs = db->drefs + 2 * e0;
+    for (uint32_t q0 = 0; q0 < nq; q0 += cw::MAX_QB) {
+        cw::Batch bt{};
+        bt.nq = std::min<uint32_t>(cw::MAX_QB, nq - q0);
+        bt.E = cnt;
+        for (uint32_t q = 0; q < bt.nq; ++q) {
+            const QState* x = qs[q0 + q];
+            bt.leaves[q] = x->QX;
+            bt.nodes[q] = x->nodes;
+            bt.rlk[q] = x->key->d;
+            bt.sel[q] = x->sel;
+        }
+        roots(ctx, lc, b, k, refs, bt);
+    }
+    {
+        Prof pr(ctx, "payload_ntt", lc.stream, bfly(ctx, (size_t)cnt * s * L));
+        cw::launch_ntt_payload(lc, db->dpay + e0 * s * N, b.Ph, (size_t)cnt * s);
+    }
+    Prof pr(ctx, "accumulate", lc.stream, (double)nq * cnt * s * 2 * L * N);
+    for (uint32_t q0 = 0; q0 < nq; q0 += cw::MAX_BATCH) {
+        cw::QueryPtrs qp;
+        const uint32_t n = std::min<uint32_t>(cw::MAX_BATCH, nq - q0);
+        for (uint32_t q = 0; q < n; ++q) {
+            qp.sel[q] = qs[q0 + q]->sel;
+            qp.acc[q] = qs[q0 + q]->answer;
+        }
+        cw::launch_accumulate(lc, qp, b.Ph, n, cnt, s);
+    }
+    return check_launch(ctx);
+}
+
+static int finalize_query(pir_ctx* ctx, const Launch& lc, const pir_db* db, QState& qs) {
+    Prof pr(ctx, "ntt_inv", lc.stream, bfly(ctx, (size_t)db->s * 2 * ctx->L));
+    cw::launch_ntt(lc, true, qs.answer, qs.answer, (size_t)db->s * 2 * ctx->L, ctx->L, 0);
+    return check_launch(ctx);
 }
 
 // B queries against one database.
 static int answer_same_db(pir_ctx* ctx, hipStream_t st, const pir_db* db, uint32_t B, const pir_key* const* keys,
                           const uint64_t* const* queries, uint64_t* const* answers) {
-    const size_t N = ctx->N, L = ctx->L, LL = ctx->LL;
-    const uint32_t E = ctx->chunk, s = db->s, m = db->m, k = db->k;
+    const uint32_t E = ctx->chunk;
     Launch lc = make_launch(ctx, st);
     Bufs b;
-    CW_TRY(get_bufs(ctx, E, s, b));
-    uint64_t *QX, *nodes, *sel;
-    const size_t qx_one = (size_t)m * 2 * LL * N, node_one = (size_t)std::max<uint32_t>(db->max_pairs, 1) * 2 * LL * N;
-    const size_t sel_one = (size_t)E * 2 * L * N;
+    CW_TRY(get_bufs(ctx, E, std::min<uint32_t>(B, cw::MAX_QB), db->s, b));
+    uint64_t *QX, *nodes = nullptr, *sel;
+    const size_t qx_one = qx_words(ctx, db), node_one = node_words(ctx, db), sel_one = sel_words(ctx);
     CW_TRY(ws_get_t(ctx, "QX", qx_one * B, &QX));
-    if (k >= 3) CW_TRY(ws_get_t(ctx, "nodes", node_one * B, &nodes));
-    else nodes = nullptr;
+    if (node_one) CW_TRY(ws_get_t(ctx, "nodes", node_one * B, &nodes));
     CW_TRY(ws_get_t(ctx, "sel", sel_one * B, &sel));
-    const size_t acc_n = (size_t)s * 2 * L * N;
+    std::vector<QState> st_q(B);
+    std::vector<QState*> ptrs(B);
     for (uint32_t q = 0; q < B; ++q) {
-        CW_TRY(make_leaves(ctx, lc, queries[q], m, QX + q * qx_one));
-        Prof pr(ctx, "fill", st);
-        cw::launch_fill(st, answers[q], acc_n, 0);
+        QState& x = st_q[q];
+        x.key = keys[q];
+        x.query = queries[q];
+        x.answer = answers[q];
+        x.QX = QX + q * qx_one;
+        x.nodes = node_one ? nodes + q * node_one : nullptr;
+        x.sel = sel + q * sel_one;
+        ptrs[q] = &x;
+        CW_TRY(prepare_query(ctx, lc, b, db, x));
     }
-    for (const Group& g : db->groups) {
-        if (g.np)
-            for (uint32_t q = 0; q < B; ++q)
-                make_nodes(ctx, lc, b, db->dpairs + 2 * (size_t)g.p0, g.np, QX + q * qx_one, keys[q], sel + q * sel_one,
-                           nodes + q * node_one, E);
-        for (uint64_t c0 = 0; c0 < g.ne; c0 += E) {
-            const uint32_t cnt = (uint32_t)std::min<uint64_t>(E, g.ne - c0);
-            const uint32_t* refs = db->drefs + 2 * (g.e0 + c0);
-            for (uint32_t q = 0; q < B; ++q)
-                roots(ctx, lc, b, k, refs, QX + q * qx_one, nodes ? nodes + q * node_one : nullptr, keys[q],
-                      sel + q * sel_one, cnt);
-            {
-                Prof pr(ctx, "payload_ntt", st, bfly(ctx, (size_t)cnt * s * L));
-                cw::launch_ntt_payload(lc, db->dpay + (g.e0 + c0) * s * N, b.Ph, (size_t)cnt * s);
-            }
-            Prof pr(ctx, "accumulate", st, (double)B * cnt * s * 2 * L * N);
-            for (uint32_t q0 = 0; q0 < B; q0 += cw::MAX_BATCH) {
-                cw::QueryPtrs qp;
-                const uint32_t nq = std::min<uint32_t>(cw::MAX_BATCH, B - q0);
-                for (uint32_t q = 0; q < nq; ++q) {
-                    qp.sel[q] = sel + (q0 + q) * sel_one;
-                    qp.acc[q] = answers[q0 + q];
-                }
-                cw::launch_accumulate(lc, qp, b.Ph, nq, cnt, s);
-            }
-        }
-        CW_TRY(check_launch(ctx));
-    }
-    for (uint32_t q = 0; q < B; ++q) {
-        Prof pr(ctx, "ntt_inv", st, bfly(ctx, (size_t)s * 2 * L));
-        cw::launch_ntt(lc, true, answers[q], answers[q], (size_t)s * 2 * L, L, 0);
-    }
-    return check_launch(ctx);
+    const uint32_t nc = num_chunks(ctx, db);
+    for (uint32_t c = 0; c < nc; ++c) CW_TRY(chunk_step(ctx, lc, b, db, c, ptrs.data(), B));
+    for (uint32_t q = 0; q < B; ++q) CW_TRY(finalize_query(ctx, lc, db, st_q[q]));
+    return PIR_OK;
 }
 
 extern "C" int pir_answer_batch(pir_ctx* ctx, uint32_t B, const pir_key* const* keys, const pir_db* const* dbs,
@@ -717,7 +788,7 @@ extern "C" int pir_selectors(pir_ctx* ctx, const pir_key* key, const pir_db* db,
     const uint32_t E = ctx->chunk, k = db->k;
     Launch lc = make_launch(ctx, st);
     Bufs b;
-    CW_TRY(get_bufs(ctx, E, 0, b));
+    CW_TRY(get_bufs(ctx, E, 1, 0, b));
     uint64_t *QX, *sel, *nodes = nullptr;
     CW_TRY(ws_get_t(ctx, "QX", (size_t)db->m * 2 * LL * N, &QX));
     CW_TRY(ws_get_t(ctx, "sel", (size_t)E * 2 * L * N, &sel));
@@ -740,11 +811,237 @@ extern "C" int pir_selectors(pir_ctx* ctx, const pir_key* key, const pir_db* db,
             CW_TRY(ws_get_t(ctx, "sel_nodes", (size_t)np * 2 * LL * N, &nodes));
             make_nodes(ctx, lc, b, dpairs, np, QX, key, sel, nodes, E);
         }
-        roots(ctx, lc, b, k, drefs, QX, nodes, key, sel, cnt);
+        roots(ctx, lc, b, k, drefs, one_query(cnt, QX, nodes, key, sel));
         cw::launch_ntt(lc, true, sel, out + (size_t)c0 * 2 * L * N, (size_t)cnt * 2 * L, L, 0);
         CW_HIP(ctx, hipStreamSynchronize(st));  // the plan lives in pageable host memory
     }
     return end_async(ctx, st);
+}
+
+// ------------------------------------------------------------------------------------------------
+// serving: continuous batching
+//
+// A server owns a stream and up to max_slots query slots.  Each call of pir_serve_step admits
+// waiting requests into free slots (when their buffers fit the HBM budget) and then runs one round:
+// every database with active queries advances by one chunk, and all its active queries process
+// that same chunk together (one selector launch per stage for up to MAX_QB queries, one payload
+// transform, one multiply-accumulate).  A database's chunk cursor keeps rotating, so a query that
+// joins mid-scan starts at the current chunk and leaves after one full cycle: the answer is a sum
+// over all chunks and does not depend on their order.  At most two rounds are in flight.
+// ------------------------------------------------------------------------------------------------
+struct ServeReq {
+    const pir_key* key;
+    const pir_db* db;
+    const uint64_t* query;
+    uint64_t* answer;
+    uint64_t ticket;
+};
+
+struct ServeSlot {
+    bool used = false;
+    const pir_db* db = nullptr;
+    uint64_t ticket = 0;
+    uint32_t chunks_left = 0;
+    QState qs;
+    uint64_t* buf = nullptr;  // QX, nodes and sel of this slot
+    size_t buf_words = 0;
+};
+
+struct pir_server {
+    pir_ctx* ctx = nullptr;
+    hipStream_t stream = nullptr;
+    std::vector<ServeSlot> slots;
+    std::deque<ServeReq> pending;
+    std::map<const pir_db*, uint32_t> cursor;
+    std::unordered_map<uint64_t, hipEvent_t> done;   // ticket -> completion event
+    std::set<uint64_t> in_flight;                    // tickets submitted and not yet completed
+    std::deque<hipEvent_t> rounds;
+    uint64_t next_ticket = 1;
+    uint64_t n_rounds = 0, n_admitted = 0, n_completed = 0;
+};
+
+extern "C" int pir_serve_open(pir_ctx* ctx, uint32_t max_slots, pir_server** out) {
+    CW_ENTER(ctx);
+    if (!out || max_slots == 0 || max_slots > 1024) return fail(PIR_E_INVALID, "max_slots must be in [1, 1024]");
+    *out = nullptr;
+    CW_HIP(ctx, hipSetDevice(ctx->device));
+    pir_server* srv = new pir_server();
+    srv->ctx = ctx;
+    srv->slots.resize(max_slots);
+    if (hipStreamCreateWithFlags(&srv->stream, hipStreamNonBlocking) != hipSuccess) {
+        delete srv;
+        return fail(PIR_E_DEVICE, "stream creation failed");
+    }
+    *out = srv;
+    return PIR_OK;
+}
+
+extern "C" int pir_serve_submit(pir_server* srv, const pir_key* key, const pir_db* db, const uint64_t* query,
+                                uint64_t* answer, uint64_t* ticket) {
+    if (!srv) return fail(PIR_E_INVALID, "null server");
+    pir_ctx* ctx = srv->ctx;
+    CW_ENTER(ctx);
+    if (!key || !db || !query || !answer || !ticket) return fail(PIR_E_INVALID, "null argument");
+    if (key->ctx != ctx || db->ctx != ctx) return fail(PIR_E_INVALID, "handle from another context");
+    *ticket = srv->next_ticket++;
+    srv->pending.push_back({key, db, query, answer, *ticket});
+    srv->in_flight.insert(*ticket);
+    return PIR_OK;
+}
+
+static int serve_admit(pir_server* srv, const Launch& lc, const Bufs& b) {
+    pir_ctx* ctx = srv->ctx;
+    for (ServeSlot& sl : srv->slots) {
+        if (srv->pending.empty()) break;
+        if (sl.used) continue;
+        const ServeReq r = srv->pending.front();
+        const size_t qxw = qx_words(ctx, r.db), nw = node_words(ctx, r.db), sw = sel_words(ctx);
+        const size_t need = qxw + nw + sw;
+        if (sl.buf_words < need) {
+            if (sl.buf) {
+                CW_HIP(ctx, hipStreamSynchronize(srv->stream));
+                dev_free(ctx, sl.buf, sl.buf_words * 8);
+                sl.buf = nullptr;
+                sl.buf_words = 0;
+            }
+            if (dev_alloc(ctx, (void**)&sl.buf, need * 8) != PIR_OK) {
+                bool any = false;
+                for (const ServeSlot& o : srv->slots) any = any || o.used;
+                if (!any) return PIR_E_NOMEM;  // nothing running will free memory: report it
+                g_err.clear();                 // the request waits for a running query to finish
+                return PIR_OK;
+            }
+            sl.buf_words = need;
+        }
+        sl.used = true;
+        sl.db = r.db;
+        sl.ticket = r.ticket;
+        sl.chunks_left = num_chunks(ctx, r.db);
+        sl.qs = QState{};
+        sl.qs.key = r.key;
+        sl.qs.query = r.query;
+        sl.qs.answer = r.answer;
+        sl.qs.QX = sl.buf;
+        sl.qs.nodes = nw ? sl.buf + qxw : nullptr;
+        sl.qs.sel = sl.buf + qxw + nw;
+        srv->pending.pop_front();
+        ++srv->n_admitted;
+        CW_TRY(prepare_query(ctx, lc, b, r.db, sl.qs));
+    }
+    return PIR_OK;
+}
+
+static int serve_finish(pir_server* srv, const Launch& lc, ServeSlot& sl) {
+    pir_ctx* ctx = srv->ctx;
+    CW_TRY(finalize_query(ctx, lc, sl.db, sl.qs));
+    hipEvent_t ev;
+    CW_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    CW_HIP(ctx, hipEventRecord(ev, srv->stream));
+    srv->done[sl.ticket] = ev;
+    sl.used = false;  // stream order keeps the slot's buffers until the queued work has run
+    return PIR_OK;
+}
+
+extern "C" int pir_serve_step(pir_server* srv) {
+    if (!srv) return fail(PIR_E_INVALID, "null server");
+    pir_ctx* ctx = srv->ctx;
+    CW_ENTER(ctx);
+    CW_TRY(begin_async(ctx, srv->stream));  // work buffers are shared with the context's other calls
+    while (srv->rounds.size() >= 2) {  // bound the queued work
+        CW_HIP(ctx, hipEventSynchronize(srv->rounds.front()));
+        (void)hipEventDestroy(srv->rounds.front());
+        srv->rounds.pop_front();
+    }
+    Launch lc = make_launch(ctx, srv->stream);
+    uint32_t max_s = 1;
+    for (const ServeSlot& sl : srv->slots)
+        if (sl.used) max_s = std::max(max_s, sl.db->s);
+    for (const ServeReq& r : srv->pending) max_s = std::max(max_s, r.db->s);
+    Bufs b;
+    CW_TRY(get_bufs(ctx, ctx->chunk, cw::MAX_QB, max_s, b));
+    CW_TRY(serve_admit(srv, lc, b));
+    // one round: every database with active queries advances by one chunk
+    std::vector<const pir_db*> dbs;
+    for (const ServeSlot& sl : srv->slots)
+        if (sl.used && std::find(dbs.begin(), dbs.end(), sl.db) == dbs.end()) dbs.push_back(sl.db);
+    for (const pir_db* db : dbs) {
+        std::vector<ServeSlot*> active;
+        std::vector<QState*> qs;
+        for (ServeSlot& sl : srv->slots)
+            if (sl.used && sl.db == db) {
+                active.push_back(&sl);
+                qs.push_back(&sl.qs);
+            }
+        const uint32_t nc = num_chunks(ctx, db);
+        if (nc) {
+            uint32_t& c = srv->cursor[db];
+            c %= nc;
+            CW_TRY(chunk_step(ctx, lc, b, db, c, qs.data(), (uint32_t)qs.size()));
+            c = (c + 1) % nc;
+        }
+        for (ServeSlot* sl : active) {
+            if (sl->chunks_left) --sl->chunks_left;
+            if (!sl->chunks_left) CW_TRY(serve_finish(srv, lc, *sl));
+        }
+    }
+    CW_TRY(end_async(ctx, srv->stream));
+    hipEvent_t ev;
+    CW_HIP(ctx, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+    CW_HIP(ctx, hipEventRecord(ev, srv->stream));
+    srv->rounds.push_back(ev);
+    ++srv->n_rounds;
+    uint32_t busy = (uint32_t)srv->pending.size();
+    for (const ServeSlot& sl : srv->slots) busy += sl.used ? 1 : 0;
+    return (int)busy;
+}
+
+extern "C" int pir_serve_poll(pir_server* srv, uint64_t ticket) {
+    if (!srv) return fail(PIR_E_INVALID, "null server");
+    pir_ctx* ctx = srv->ctx;
+    CW_ENTER(ctx);
+    auto it = srv->done.find(ticket);
+    if (it == srv->done.end()) {
+        if (srv->in_flight.count(ticket)) return 0;
+        return fail(PIR_E_INVALID, "unknown or already collected ticket");
+    }
+    hipError_t e = hipEventQuery(it->second);
+    if (e == hipErrorNotReady) return 0;
+    if (e != hipSuccess) {
+        ctx->poisoned = true;
+        return fail(PIR_E_DEVICE, std::string("hipEventQuery failed: ") + hipGetErrorString(e));
+    }
+    (void)hipEventDestroy(it->second);
+    srv->done.erase(it);
+    srv->in_flight.erase(ticket);
+    ++srv->n_completed;
+    return 1;
+}
+
+extern "C" int pir_serve_stats(pir_server* srv, uint64_t* rounds, uint64_t* admitted, uint64_t* completed,
+                               uint32_t* active, uint32_t* pending) {
+    if (!srv) return fail(PIR_E_INVALID, "null server");
+    CW_ENTER(srv->ctx);
+    if (rounds) *rounds = srv->n_rounds;
+    if (admitted) *admitted = srv->n_admitted;
+    if (completed) *completed = srv->n_completed;
+    uint32_t a = 0;
+    for (const ServeSlot& sl : srv->slots) a += sl.used ? 1 : 0;
+    if (active) *active = a;
+    if (pending) *pending = (uint32_t)srv->pending.size();
+    return PIR_OK;
+}
+
+extern "C" void pir_serve_close(pir_server* srv) {
+    if (!srv) return;
+    pir_ctx* ctx = srv->ctx;
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(srv->stream);
+    for (ServeSlot& sl : srv->slots) dev_free(ctx, sl.buf, sl.buf_words * 8);
+    for (auto& kv : srv->done) (void)hipEventDestroy(kv.second);
+    for (hipEvent_t e : srv->rounds) (void)hipEventDestroy(e);
+    (void)hipStreamDestroy(srv->stream);
+    delete srv;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -758,7 +1055,7 @@ extern "C" int pir_mult(pir_ctx* ctx, const uint64_t* a, const uint64_t* b_, uin
     const size_t N = ctx->N, L = ctx->L, LL = ctx->LL;
     Launch lc = make_launch(ctx, st);
     Bufs b;
-    CW_TRY(get_bufs(ctx, 1, 0, b));
+    CW_TRY(get_bufs(ctx, 1, 1, 0, b));
     uint64_t* QX;
     uint32_t* refs;
     CW_TRY(ws_get_t(ctx, "op_leaves", (size_t)2 * 2 * LL * N, &QX));
@@ -768,7 +1065,11 @@ extern "C" int pir_mult(pir_ctx* ctx, const uint64_t* a, const uint64_t* b_, uin
     cw::launch_extend(lc, a, QX, 2);
     cw::launch_extend(lc, b_, QX + 2 * LL * N, 2);
     cw::launch_ntt(lc, false, QX, QX, 4 * LL, LL, 0);
-    cw::launch_ntt_inv_tensor(lc, refs, QX, nullptr, b.X, 1);
+    cw::Batch bt{};
+    bt.nq = 1;
+    bt.E = 1;
+    bt.leaves[0] = QX;
+    cw::launch_ntt_inv_tensor(lc, refs, bt, b.X);
     cw::launch_scale(lc, b.X, out, 1);
     (void)L;
     return end_async(ctx, st);
@@ -782,8 +1083,8 @@ extern "C" int pir_relin(pir_ctx* ctx, const pir_key* key, const uint64_t* in, u
     const uint32_t L = ctx->L;
     Launch lc = make_launch(ctx, st);
     Bufs b;
-    CW_TRY(get_bufs(ctx, 1, 0, b));
-    cw::launch_relin(lc, in, key->d, out, 1, b.R);
+    CW_TRY(get_bufs(ctx, 1, 1, 0, b));
+    cw::launch_relin(lc, in, one_query(1, nullptr, nullptr, key, out), b.R);
     cw::launch_ntt(lc, true, out, out, (size_t)2 * L, L, 0);
     return end_async(ctx, st);
 }

@@ -14,6 +14,18 @@ struct QueryPtrs {  // passed by value as a kernel argument
     uint64_t* acc[MAX_BATCH];
 };
 
+// Up to MAX_QB queries whose selectors are computed in one launch per stage.  They process the
+// same E elements (the operand references are shared); element e of query q is row q*E + e of the
+// launch's work buffers.  Passed by value as a kernel argument.
+constexpr int MAX_QB = 8;
+struct Batch {
+    uint32_t nq, E;
+    const uint64_t* leaves[MAX_QB];  // resident query [m][2][LL][N]
+    const uint64_t* nodes[MAX_QB];   // level-1 products [pairs][2][LL][N] (or null)
+    const uint64_t* rlk[MAX_QB];     // transformed key and companions
+    uint64_t* sel[MAX_QB];           // selectors out [E][2][L][N]
+};
+
 struct Launch {
     hipStream_t stream;
     const CtxConst* K;    // device copy of the constants
@@ -35,18 +47,16 @@ void launch_ntt_digits(const Launch& lc, const uint64_t* c3, uint64_t* out, uint
 void launch_extend(const Launch& lc, const uint64_t* in, uint64_t* out, size_t G);
 // Tensor product (a0 b0, a0 b1 + a1 b0, a1 b1) of E operand pairs over Q u B, formed while loading
 // and inverse-transformed: X [E][3][LL][N] in coefficient form.
-void launch_ntt_inv_tensor(const Launch& lc, const uint32_t* refs, const uint64_t* leaves, const uint64_t* nodes,
-                           uint64_t* X, uint32_t E);
+void launch_ntt_inv_tensor(const Launch& lc, const uint32_t* refs, const Batch& bt, uint64_t* X);
 void launch_scale(const Launch& lc, const uint64_t* X, uint64_t* out, uint32_t E);
-void launch_relin_mac(const Launch& lc, const uint64_t* R, const uint64_t* rlk, uint64_t* sel, uint32_t E);
+void launch_relin_mac(const Launch& lc, const uint64_t* R, const Batch& bt);
 // Key switching of E coefficient-form products [E][3][L][N] into transformed selectors [E][2][L][N]
 // (digit reduction, digit transforms and the multiply-accumulate with the key in one kernel).
-void launch_relin(const Launch& lc, const uint64_t* c3, const uint64_t* rlk, uint64_t* sel, uint32_t E,
-                  uint64_t* staging);
+void launch_relin(const Launch& lc, const uint64_t* c3, const Batch& bt, uint64_t* staging);
 // Whether launch_relin needs its staging buffer [E][L+2][L][N] at this ring degree.
 bool relin_needs_staging(uint32_t logN);
 void launch_shoup_companions(const Launch& lc, const uint64_t* v, uint64_t* comp, size_t rows, uint32_t nl);
-void launch_gather_leaf(const Launch& lc, const uint32_t* refs, const uint64_t* leaves, uint64_t* sel, uint32_t E);
+void launch_gather_leaf(const Launch& lc, const uint32_t* refs, const Batch& bt);
 void launch_accumulate(const Launch& lc, const QueryPtrs& qp, const uint64_t* Ph, uint32_t nq, uint32_t E,
                        uint32_t s);
 void launch_pointwise_pt(const Launch& lc, const uint64_t* ct, const uint64_t* pt, uint64_t* out);

@@ -484,6 +484,7 @@ struct RowsTensor {
     uint64_t* out;
     const CtxConst* K;
     uint32_t LL;
+    size_t eshift;  // rows of earlier queries in a batched launch: refs index = element - eshift
     __device__ uint32_t prime(size_t g) const { return (uint32_t)(g % LL); }
     __device__ void load(size_t g, uint32_t tid, uint64_t* a) const {
         constexpr int N = Sh::N, T = Sh::T;
@@ -492,7 +493,7 @@ struct RowsTensor {
         const uint32_t r = (uint32_t)(er % 3);
         const size_t e = er / 3;
         const size_t ct = (size_t)2 * LL * N;
-        const uint32_t ra = refs[2 * e], rb = refs[2 * e + 1];
+        const uint32_t ra = refs[2 * (e - eshift)], rb = refs[2 * (e - eshift) + 1];
         const uint64_t* A = (ra & REF_NODE) ? nodes + (size_t)(ra & ~REF_NODE) * ct : leaves + (size_t)ra * ct;
         const uint64_t* B = (rb & REF_NODE) ? nodes + (size_t)(rb & ~REF_NODE) * ct : leaves + (size_t)rb * ct;
         const uint64_t p = K->p[l], mu = K->bar_mu[l];
@@ -541,18 +542,18 @@ __global__ __launch_bounds__(Sh::T) void k_ntt_digits(const CtxConst* __restrict
 template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T) void k_ntt_inv_tensor(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
                                                           const double* __restrict__ twf,
-                                                          const uint32_t* __restrict__ refs,
-                                                          const uint64_t* __restrict__ leaves,
-                                                          const uint64_t* __restrict__ nodes, uint64_t* __restrict__ X,
-                                                          size_t groups) {
+                                                          const uint32_t* __restrict__ refs, const Batch bt,
+                                                          uint64_t* __restrict__ X, size_t groups) {
     __shared__ uint64_t sm[Sh::LDS_WORDS];
     size_t el;
     uint32_t r;
     xcd_split(blockIdx.x, 3, el, r);
     if (el >= groups) return;
     const uint32_t LL = K->LL;
-    const size_t g = ((el / LL) * 3 + r) * LL + el % LL;
-    const RowsTensor<Sh> row{refs, leaves, nodes, X, K, LL};
+    const size_t eq = el / LL;            // row of the launch: query q, element e
+    const uint32_t q = (uint32_t)(eq / bt.E);
+    const size_t g = (eq * 3 + r) * LL + el % LL;
+    const RowsTensor<Sh> row{refs, bt.leaves[q], bt.nodes[q], X, K, LL, (size_t)q * bt.E};
     const uint32_t tid = threadIdx.x;
     uint64_t a[Sh::EPT];
     row.load(g, tid, a);
@@ -574,17 +575,21 @@ __global__ __launch_bounds__(Sh::T) void k_ntt_inv_tensor(const CtxConst* __rest
 template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T) void k_relin(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
                                                  const double* __restrict__ twf, const uint64_t* __restrict__ c3,
-                                                 const uint64_t* __restrict__ rlk, uint64_t* __restrict__ sel, size_t E) {
+                                                 const Batch bt) {
     __shared__ uint64_t sm[Sh::LDS_WORDS];
     constexpr int N = Sh::N, T = Sh::T, EPT = Sh::EPT;
     const uint32_t L = K->L, tid = threadIdx.x;
-    size_t e;
+    size_t eq;
     uint32_t j;
-    xcd_split(blockIdx.x, L, e, j);  // the L workgroups of element e share its digit rows: one XCD
-    if (e >= E) return;
+    xcd_split(blockIdx.x, L, eq, j);  // the L workgroups of element e share its digit rows: one XCD
+    if (eq >= (size_t)bt.nq * bt.E) return;
+    const uint32_t q = (uint32_t)(eq / bt.E);
+    const size_t e = eq % bt.E;
+    const uint64_t* __restrict__ rlk = bt.rlk[q];
+    uint64_t* __restrict__ sel = bt.sel[q];
     const uint64_t p = K->p[j], r1 = K->r1[j];
     const TwRow twr = tw_row(tw, twf, j, N);
-    const uint64_t* base = c3 + e * 3 * L * N;
+    const uint64_t* base = c3 + eq * 3 * L * N;
     const size_t LN = (size_t)L * N, half = (size_t)L * 2 * LN;
     uint64_t acc0[EPT], acc1[EPT], a[EPT];
     for (uint32_t i = 0; i < L + 2; ++i) {
@@ -635,26 +640,25 @@ __global__ __launch_bounds__(Sh::T) void k_relin(const CtxConst* __restrict__ K,
 // N = 16384 does not fit 16 elements plus two accumulators per thread in the 128 registers that a
 // 1024-thread workgroup allows; there the digits are transformed to `staging` [E][L+2][L][N] and
 // multiplied-accumulated by a second kernel.
-void launch_relin(const Launch& lc, const uint64_t* c3, const uint64_t* rlk, uint64_t* sel, uint32_t E,
-                  uint64_t* staging) {
-    if (!E) return;
-    const unsigned blocks = (unsigned)xcd_grid(E, lc.L);
+void launch_relin(const Launch& lc, const uint64_t* c3, const Batch& bt, uint64_t* staging) {
+    if (!bt.E || !bt.nq) return;
+    const unsigned blocks = (unsigned)xcd_grid((size_t)bt.nq * bt.E, lc.L);
 #define CW_RELIN(LG)                                                                                               \
     {                                                                                                              \
         using Sh = DefaultShape<LG>::type;                                                                         \
         if (lc.fp)                                                                                                 \
             hipLaunchKernelGGL((k_relin<Sh, true>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, lc.twf, c3, \
-                               rlk, sel, (size_t)E);                                                               \
+                               bt);                                                                                \
         else                                                                                                       \
             hipLaunchKernelGGL((k_relin<Sh, false>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, lc.twf,   \
-                               c3, rlk, sel, (size_t)E);                                                           \
+                               c3, bt);                                                                            \
     }
     switch (lc.logN) {
         case 12: CW_RELIN(12) break;
         case 13: CW_RELIN(13) break;
         case 14:
-            launch_ntt_digits(lc, c3, staging, E);
-            launch_relin_mac(lc, staging, rlk, sel, E);
+            launch_ntt_digits(lc, c3, staging, bt.nq * bt.E);
+            launch_relin_mac(lc, staging, bt);
             break;
     }
 }
@@ -703,12 +707,11 @@ void launch_ntt_digits(const Launch& lc, const uint64_t* c3, uint64_t* out, uint
     CW_NTT_DISPATCH(lc, k_ntt_digits, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, c3, out)
 }
 
-void launch_ntt_inv_tensor(const Launch& lc, const uint32_t* refs, const uint64_t* leaves, const uint64_t* nodes,
-                           uint64_t* X, uint32_t E) {
-    if (!E) return;
-    const size_t groups = (size_t)E * lc.LL;
-    CW_NTT_DISPATCH(lc, k_ntt_inv_tensor, dim3((unsigned)xcd_grid(groups, 3)), lc.K, lc.tw, lc.twf, refs, leaves,
-                    nodes, X, groups)
+void launch_ntt_inv_tensor(const Launch& lc, const uint32_t* refs, const Batch& bt, uint64_t* X) {
+    if (!bt.E || !bt.nq) return;
+    const size_t groups = (size_t)bt.nq * bt.E * lc.LL;
+    CW_NTT_DISPATCH(lc, k_ntt_inv_tensor, dim3((unsigned)xcd_grid(groups, 3)), lc.K, lc.tw, lc.twf, refs, bt, X,
+                    groups)
 }
 
 void launch_ntt_payload(const Launch& lc, const uint16_t* pay, uint64_t* out, size_t rows_u16) {
@@ -928,17 +931,19 @@ void launch_scale(const Launch& lc, const uint64_t* X, uint64_t* out, uint32_t E
 // Key switching: sel = (c0 + sum_i D_i b_i, c1 + sum_i D_i a_i), transformed over Q.
 // rlk: [L][2][L][N] transformed values followed by [L][2][L][N] Shoup companions.
 // ---------------------------------------------------------------------------------------------
-__global__ void k_relin_mac(const CtxConst* __restrict__ K, const uint64_t* __restrict__ R,
-                            const uint64_t* __restrict__ rlk, uint64_t* __restrict__ sel, uint32_t E) {
+__global__ void k_relin_mac(const CtxConst* __restrict__ K, const uint64_t* __restrict__ R, const Batch bt) {
     const uint32_t N = K->N, L = K->L;
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (size_t)E * L * N) return;
+    if (gid >= (size_t)bt.nq * bt.E * L * N) return;
     const size_t c = gid % N, ej = gid / N;
     const uint32_t j = (uint32_t)(ej % L);
-    const size_t e = ej / L;
+    const size_t eq = ej / L;
+    const uint32_t q = (uint32_t)(eq / bt.E);
+    const size_t e = eq % bt.E;
+    const uint64_t* __restrict__ rlk = bt.rlk[q];
     const uint64_t p = K->p[j];
     const size_t LN = (size_t)L * N;
-    const uint64_t* r = R + e * (L + 2) * LN + (size_t)j * N + c;
+    const uint64_t* r = R + eq * (L + 2) * LN + (size_t)j * N + c;
     const size_t half = (size_t)L * 2 * LN;
     uint64_t s0 = r[(size_t)L * LN], s1 = r[(size_t)(L + 1) * LN];
     for (uint32_t i = 0; i < L; ++i) {
@@ -948,15 +953,15 @@ __global__ void k_relin_mac(const CtxConst* __restrict__ K, const uint64_t* __re
         s0 = add_mod(s0, mul_shoup(d, rlk[ob], rlk[half + ob], p), p);
         s1 = add_mod(s1, mul_shoup(d, rlk[oa], rlk[half + oa], p), p);
     }
-    uint64_t* o = sel + e * 2 * LN + (size_t)j * N + c;
+    uint64_t* o = bt.sel[q] + e * 2 * LN + (size_t)j * N + c;
     o[0] = s0;
     o[LN] = s1;
 }
 
-void launch_relin_mac(const Launch& lc, const uint64_t* R, const uint64_t* rlk, uint64_t* sel, uint32_t E) {
-    if (!E) return;
-    hipLaunchKernelGGL(k_relin_mac, dim3(blocks_for((size_t)E * lc.L * lc.N)), dim3(EW_THREADS), 0, lc.stream, lc.K,
-                       R, rlk, sel, E);
+void launch_relin_mac(const Launch& lc, const uint64_t* R, const Batch& bt) {
+    if (!bt.E || !bt.nq) return;
+    hipLaunchKernelGGL(k_relin_mac, dim3(blocks_for((size_t)bt.nq * bt.E * lc.L * lc.N)), dim3(EW_THREADS), 0,
+                       lc.stream, lc.K, R, bt);
 }
 
 // Shoup companions of a transformed key: comp[i] = floor(v[i] 2^64 / p) with p from the limb index.
@@ -988,24 +993,26 @@ void launch_shoup_companions(const Launch& lc, const uint64_t* v, uint64_t* comp
 // ---------------------------------------------------------------------------------------------
 // k = 1: the selector is the query ciphertext itself (its Q limbs, transformed).
 // ---------------------------------------------------------------------------------------------
-__global__ void k_gather_leaf(const CtxConst* __restrict__ K, const uint32_t* __restrict__ refs,
-                              const uint64_t* __restrict__ leaves, uint64_t* __restrict__ sel, uint32_t E) {
+__global__ void k_gather_leaf(const CtxConst* __restrict__ K, const uint32_t* __restrict__ refs, const Batch bt) {
     const uint32_t N = K->N, L = K->L, LL = K->LL;
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (size_t)E * 2 * L * N) return;
-    const size_t c = gid % N, rest = gid / N;
+    const size_t per = (size_t)bt.E * 2 * L * N;
+    if (gid >= (size_t)bt.nq * per) return;
+    const uint32_t q = (uint32_t)(gid / per);
+    const size_t gq = gid % per;
+    const size_t c = gq % N, rest = gq / N;
     const uint32_t j = (uint32_t)(rest % L);
     const size_t ep = rest / L;
     const uint32_t poly = (uint32_t)(ep % 2);
     const size_t e = ep / 2;
     const uint32_t leaf = refs[2 * e];
-    sel[gid] = leaves[((size_t)leaf * 2 * LL + (size_t)poly * LL + j) * N + c];
+    bt.sel[q][gq] = bt.leaves[q][((size_t)leaf * 2 * LL + (size_t)poly * LL + j) * N + c];
 }
 
-void launch_gather_leaf(const Launch& lc, const uint32_t* refs, const uint64_t* leaves, uint64_t* sel, uint32_t E) {
-    if (!E) return;
-    hipLaunchKernelGGL(k_gather_leaf, dim3(blocks_for((size_t)E * 2 * lc.L * lc.N)), dim3(EW_THREADS), 0, lc.stream,
-                       lc.K, refs, leaves, sel, E);
+void launch_gather_leaf(const Launch& lc, const uint32_t* refs, const Batch& bt) {
+    if (!bt.E || !bt.nq) return;
+    hipLaunchKernelGGL(k_gather_leaf, dim3(blocks_for((size_t)bt.nq * bt.E * 2 * lc.L * lc.N)), dim3(EW_THREADS), 0,
+                       lc.stream, lc.K, refs, bt);
 }
 
 // ---------------------------------------------------------------------------------------------

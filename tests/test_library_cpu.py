@@ -67,3 +67,14 @@ def test_context_refuses_to_run_without_gpu():
         pytest.skip("a GPU is present")
     with pytest.raises(binding.PirError):
         binding.Context(4096, datagen.Q_N4096)
+
+
+def test_serving_calls_reject_null_server():
+    L = binding.lib()
+    t = ctypes.c_uint64()
+    assert L.pir_serve_step(None) == binding.PIR_E_INVALID
+    assert L.pir_serve_poll(None, 1) == binding.PIR_E_INVALID
+    assert L.pir_serve_submit(None, None, None, None, None, ctypes.byref(t)) == binding.PIR_E_INVALID
+    assert L.pir_serve_stats(None, None, None, None, None, None) == binding.PIR_E_INVALID
+    assert "null server" in L.pir_last_error().decode()
+    L.pir_serve_close(None)  # no-op
