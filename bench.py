@@ -62,6 +62,12 @@ def parse():
     ap.add_argument("--chunk", type=int, default=0, help="elements per processing chunk (0: library default)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (reference for rocprofv3 byte counters)")
+    ap.add_argument("--serve", type=int, default=-1, choices=[-1, 0, 1],
+                    help="also replay the batched-serving trace (4 resident databases, Poisson arrivals)")
+    ap.add_argument("--serve-queries", type=int, default=256)
+    ap.add_argument("--serve-rates", default="2.0", help="arrival rates as multiples of 1/S (S: mean plain service time)")
+    ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-only", action="store_true", help="skip the mid workload")
     return ap.parse_args()
 
 
@@ -82,6 +88,16 @@ def main():
     import torch
 
     from paper_2202_07569_amd import Context
+
+    serve = args.serve == 1 or (args.serve == -1 and args.workload == "mid")
+    if args.serve_only:
+        res = serve_bench(args, torch)
+        first = res["rates"][0]["batched"]
+        print(json.dumps({"metric": "DB elements answered/sec + p50/p99 query latency, batched serving vs plain",
+                          "value": first["elements_per_s"], "unit": "elements/s", "n_gpus": 1,
+                          "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+                          "config": {"workload": res["workload"]}, "serving": res}), flush=True)
+        return
 
     cfg = datagen.CONFIGS[args.workload]
     n = args.n or cfg.n
@@ -174,6 +190,10 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if serve:
+        del db, dq, outs, key, ctx
+        torch.cuda.empty_cache()
+        out["serving"] = serve_bench(args, torch)
     print(json.dumps(out), flush=True)
 
 
@@ -235,6 +255,130 @@ def cpu_baseline(cfg, rlk, query, codewords, payload):
     dt = time.perf_counter() - t0
     return {"value": len(codewords) / dt, "unit": "elements/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(codewords)} of {cfg.n} elements of the same workload, one query, {dt:.1f} s"}
+
+
+# --------------------------------------------------------------------------------------------
+# Batched serving: four resident databases, Poisson arrivals, plain loop vs continuous batching
+# --------------------------------------------------------------------------------------------
+QUERY_POOL = 4  # distinct synthetic query ciphertexts per database, reused round-robin
+
+
+def serve_bench(args, torch):
+    """Replay one seeded arrival trace through (i) the plain loop, which answers one query at a time
+    in arrival order with pir_answer, and (ii) the continuous-batching server (pir_serve_*).
+
+    Latency runs from a query's arrival (host clock; its ciphertexts are already resident) to its
+    answer being complete on the device.  Elements/s = sum of the queried databases' sizes / time
+    from the first arrival to the last completion.  The rate is a multiple of 1/S, S the plain
+    loop's mean service time over the uniform database mix, measured first.
+    """
+    from paper_2202_07569_amd import Context, Server
+    cfgs = datagen.batched_configs()
+    c0 = cfgs[0]
+    ctx = Context(c0.N, c0.primes, c0.t, hbm_budget_bytes=96 << 30)
+    keys = [ctx.load_key(datagen.uniform_residues(c0.primes, (c0.L, 2), c0.N, seed=c0.seed * 100 + 1 + i))
+            for i in range(2)]
+    dbs, pools = [], []
+    for c in cfgs:
+        log(f"serving db {c.name}: n={c.n} s={c.s} k={c.k} m={c.m}")
+        cw = ctx.map_perfect(datagen.identifier_permutation(c).astype(np.uint64), c.m, c.k)
+        torch.cuda.synchronize()
+        pay = datagen.payload(c)
+        dbs.append(ctx.encode_db(cw.cpu().numpy(), pay, c.m))
+        del pay
+        pools.append([torch.from_numpy(datagen.uniform_residues(c.primes, (c.m, 2), c.N,
+                                                                seed=c.seed * 100 + 20 + i)).cuda()
+                      for i in range(QUERY_POOL)])
+    stream = torch.cuda.current_stream()
+    Q = args.serve_queries
+    seed = cfgs[0].seed
+    dbc = datagen.uniform_choice(seed, datagen.S_DBCHOICE, Q, len(cfgs))
+    keyc = np.arange(Q) % len(keys)
+    outs = [ctx.empty(cfgs[d].s, 2, c0.L, c0.N) for d in dbc]
+    elems = float(sum(cfgs[d].n for d in dbc))
+
+    # S: plain service time per database (after a warm-up answer on each)
+    svc = []
+    for d, c in enumerate(cfgs):
+        ctx.answer(keys[0], dbs[d], pools[d][0], out=outs[0] if dbc[0] == d else ctx.empty(c.s, 2, c0.L, c0.N))
+        torch.cuda.synchronize()
+        reps = []
+        for r in range(3):
+            a = time.perf_counter()
+            ctx.answer(keys[r % 2], dbs[d], pools[d][r % QUERY_POOL], out=ctx.empty(c.s, 2, c0.L, c0.N))
+            torch.cuda.synchronize()
+            reps.append(time.perf_counter() - a)
+        svc.append(float(np.median(reps)))
+    S = float(np.mean(svc))
+    log(f"plain service times {[round(x * 1e3, 1) for x in svc]} ms, S = {S * 1e3:.1f} ms")
+
+    def plain(arr):
+        lat = np.zeros(Q)
+        t0 = time.perf_counter()
+        done = 0.0
+        for i in range(Q):
+            now = time.perf_counter() - t0
+            if now < arr[i]:
+                time.sleep(arr[i] - now)
+            d = dbc[i]
+            ctx.answer(keys[keyc[i]], dbs[d], pools[d][i % QUERY_POOL], out=outs[i], stream=stream)
+            stream.synchronize()
+            done = time.perf_counter() - t0
+            lat[i] = done - arr[i]
+        return lat, done - arr[0]
+
+    def batched(arr):
+        srv = Server(ctx, max_slots=args.serve_slots)
+        lat = np.zeros(Q)
+        live = {}
+        i = nd = 0
+        t0 = time.perf_counter()
+        done = 0.0
+        while nd < Q:
+            now = time.perf_counter() - t0
+            while i < Q and arr[i] <= now:
+                d = dbc[i]
+                live[srv.submit(keys[keyc[i]], dbs[d], pools[d][i % QUERY_POOL], out=outs[i])] = i
+                i += 1
+            if not live:
+                time.sleep(max(0.0, arr[i] - (time.perf_counter() - t0)))
+                continue
+            busy = srv.step()
+            for t in [t for t in live if srv.poll(t)]:
+                done = time.perf_counter() - t0
+                j = live.pop(t)
+                lat[j] = done - arr[j]
+                srv.result(t)
+                nd += 1
+            if busy == 0 and live:
+                time.sleep(2e-4)  # only completion events outstanding
+        st = srv.stats()
+        srv.close()
+        return lat, done - arr[0], st
+
+    res = {"workload": "batched serving: 4 resident databases (n, s, k) = "
+                       + ", ".join(f"({c.n}, {c.s}, {c.k})" for c in cfgs)
+                       + f"; N={c0.N}, {c0.L} primes, t={c0.t}; {Q} queries, uniform database choice, "
+                         f"{len(keys)} keys",
+           "plain_service_ms": [x * 1e3 for x in svc], "S_ms": S * 1e3, "slots": args.serve_slots, "rates": []}
+    for mult in [float(x) for x in args.serve_rates.split(",")]:
+        rate = mult / S
+        arr = datagen.poisson_arrivals(seed + int(mult * 1000), Q, rate)
+        arr = arr - arr[0]
+        log(f"rate {mult}/S: plain loop")
+        lp, tp = plain(arr)
+        log(f"rate {mult}/S: continuous batching")
+        lb, tb, st = batched(arr)
+        pct = lambda x: {"p50_ms": float(np.percentile(x, 50) * 1e3),  # noqa: E731
+                         "p99_ms": float(np.percentile(x, 99) * 1e3), "mean_ms": float(x.mean() * 1e3)}
+        entry = {"rate_per_s": rate, "rate_over_S": mult,
+                 "plain": {"elements_per_s": elems / tp, "wall_s": tp, **pct(lp)},
+                 "batched": {"elements_per_s": elems / tb, "wall_s": tb, **pct(lb), "rounds": st["rounds"]}}
+        log(f"rate {mult}/S: plain {entry['plain']['elements_per_s']:.0f} el/s p50 {entry['plain']['p50_ms']:.0f} "
+            f"p99 {entry['plain']['p99_ms']:.0f} ms | batched {entry['batched']['elements_per_s']:.0f} el/s "
+            f"p50 {entry['batched']['p50_ms']:.0f} p99 {entry['batched']['p99_ms']:.0f} ms")
+        res["rates"].append(entry)
+    return res
 
 
 if __name__ == "__main__":

@@ -36,6 +36,7 @@ struct ConvTable {
 // Primes below this bound may use the fp64 transform (see kernels.hip); the exactness argument
 // needs every intermediate integer below 2^53.
 constexpr uint64_t FP_PRIME_BOUND = 1ull << 50;
+constexpr uint64_t FP_LAZY_BOUND = 1ull << 48;  // lazy fp64 forward transforms (no reduction between passes)
 
 struct CtxConst {
     uint32_t N, logN, L, LB, LL, fp;             // fp: transforms run on the fp64 pipe

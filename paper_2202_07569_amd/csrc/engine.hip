@@ -177,6 +177,8 @@ static Launch make_launch(pir_ctx* ctx, hipStream_t st) {
     lc.tw = ctx->dtw;
     lc.twf = ctx->dtwf;
     lc.fp = ctx->fp;
+    lc.q_lazy = ctx->fp;
+    for (uint32_t i = 0; i < ctx->L; ++i) lc.q_lazy = lc.q_lazy && ctx->primes[i] < cw::FP_LAZY_BOUND;
     lc.N = ctx->N;
     lc.logN = ctx->logN;
     lc.L = ctx->L;
@@ -360,7 +362,7 @@ extern "C" int pir_load_key(pir_ctx* ctx, const uint64_t* rlk, pir_key** out) {
     }
     pir_key* key = new pir_key();
     key->ctx = ctx;
-    key->bytes = 2 * half * 8;
+    key->bytes = (ctx->fp ? 1 : 2) * half * 8;  // the integer operand format adds Shoup companions
     int rc = dev_alloc(ctx, (void**)&key->d, key->bytes);
     if (rc != PIR_OK) {
         delete key;
@@ -373,8 +375,8 @@ extern "C" int pir_load_key(pir_ctx* ctx, const uint64_t* rlk, pir_key** out) {
         ctx->poisoned = true;
         return fail(PIR_E_DEVICE, "key upload failed");
     }
-    cw::launch_ntt(lc, false, key->d, key->d, rows, L, 0);
-    cw::launch_shoup_companions(lc, key->d, key->d + half, rows, L);
+    cw::launch_ntt_operand(lc, key->d, key->d, rows, L, 0);
+    if (!ctx->fp) cw::launch_shoup_companions(lc, key->d, key->d + half, rows, L);
     if (hipDeviceSynchronize() != hipSuccess || hipGetLastError() != hipSuccess) {
         pir_key_free(key);
         ctx->poisoned = true;
@@ -438,6 +440,41 @@ static void plan_elements(const uint32_t* cw, uint64_t e0, uint64_t ne, uint32_t
 
 static size_t node_bytes(const pir_ctx* ctx) { return (size_t)2 * ctx->LL * ctx->N * 8; }
 
+// Payload rows [n][s][N] in the internal order: dst row e = src row order[e].  A device source is
+// gathered by a kernel; a host source through a bounded host staging buffer.
+static int upload_payload(pir_ctx* ctx, const uint16_t* src, const std::vector<uint64_t>& order, uint32_t s,
+                          uint16_t* dst) {
+    const uint64_t n = order.size();
+    const size_t row = (size_t)s * ctx->N;  // uint16 per element
+    hipPointerAttribute_t attr{};
+    const bool on_device = hipPointerGetAttributes(&attr, src) == hipSuccess && attr.type == hipMemoryTypeDevice;
+    (void)hipGetLastError();
+    if (on_device) {
+        uint64_t* dorder = nullptr;
+        CW_TRY(dev_alloc(ctx, (void**)&dorder, n * 8));
+        hipError_t e = hipMemcpy(dorder, order.data(), n * 8, hipMemcpyHostToDevice);
+        if (e == hipSuccess) {
+            cw::launch_gather_rows(nullptr, src, dorder, n, row, dst);
+            e = hipDeviceSynchronize();
+            if (e == hipSuccess) e = hipGetLastError();
+        }
+        dev_free(ctx, dorder, n * 8);
+        if (e != hipSuccess) {
+            ctx->poisoned = true;
+            return fail(PIR_E_DEVICE, std::string("payload upload failed: ") + hipGetErrorString(e));
+        }
+        return PIR_OK;
+    }
+    const uint64_t per = std::max<uint64_t>(1, (64ull << 20) / (row * 2));  // rows per 64 MiB staging
+    std::vector<uint16_t> stage(std::min<uint64_t>(per, n) * row);
+    for (uint64_t e0 = 0; e0 < n; e0 += per) {
+        const uint64_t cnt = std::min(per, n - e0);
+        for (uint64_t i = 0; i < cnt; ++i) std::memcpy(&stage[i * row], src + order[e0 + i] * row, row * 2);
+        CW_HIP(ctx, hipMemcpy(dst + e0 * row, stage.data(), cnt * row * 2, hipMemcpyHostToDevice));
+    }
+    return PIR_OK;
+}
+
 extern "C" int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, uint32_t k, const uint32_t* codewords,
                              const uint16_t* payload, pir_db** out) {
     CW_ENTER(ctx);
@@ -463,11 +500,23 @@ extern "C" int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, u
     db->m = m;
     db->k = k;
     db->cw.assign(codewords, codewords + n * k);
+    // Internal element order: ascending codewords.  The answer is a sum over all elements, so the
+    // order does not change it; sorted, consecutive elements share their first operand (a query
+    // ciphertext for k = 2, a level-1 product for k = 4), which then stays in cache, and a chunk
+    // touches fewer distinct level-1 products.
+    std::vector<uint64_t> order(n);
+    for (uint64_t e = 0; e < n; ++e) order[e] = e;
+    std::stable_sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) {
+        return std::lexicographical_compare(codewords + a * k, codewords + a * k + k, codewords + b * k,
+                                            codewords + b * k + k);
+    });
+    std::vector<uint32_t> scw(n * k);
+    for (uint64_t e = 0; e < n; ++e) std::memcpy(&scw[e * k], codewords + order[e] * k, (size_t)k * 4);
     // schedule: one group sharing all level-1 products when they fit the memo budget, else one
     // group per chunk of elements
     const uint32_t E = ctx->chunk;
     PlanBuild all;
-    plan_elements(db->cw.data(), 0, n, k, all);
+    plan_elements(scw.data(), 0, n, k, all);
     const uint64_t memo_cap = ctx->memo_cap;
     const uint64_t np_all = all.pairs.size() / 2;
     PlanBuild pb;
@@ -486,7 +535,7 @@ extern "C" int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, u
             g.ne = std::min<uint64_t>(E, n - e0);
             g.p0 = (uint32_t)(pb.pairs.size() / 2);
             PlanBuild local;
-            plan_elements(db->cw.data(), e0, g.ne, k, local);
+            plan_elements(scw.data(), e0, g.ne, k, local);
             g.np = (uint32_t)(local.pairs.size() / 2);
             pb.pairs.insert(pb.pairs.end(), local.pairs.begin(), local.pairs.end());
             pb.refs.insert(pb.refs.end(), local.refs.begin(), local.refs.end());
@@ -506,8 +555,11 @@ extern "C" int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, u
         pir_db_free(db);
         return rc;
     }
-    if ((pay_bytes && hipMemcpy(db->dpay, payload, pay_bytes, hipMemcpyDefault) != hipSuccess) ||
-        (!pb.pairs.empty() && hipMemcpy(db->dpairs, pb.pairs.data(), pb.pairs.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
+    if (pay_bytes && (rc = upload_payload(ctx, payload, order, s, db->dpay)) != PIR_OK) {
+        pir_db_free(db);
+        return rc;
+    }
+    if ((!pb.pairs.empty() && hipMemcpy(db->dpairs, pb.pairs.data(), pb.pairs.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
         (!pb.refs.empty() && hipMemcpy(db->drefs, pb.refs.data(), pb.refs.size() * 4, hipMemcpyHostToDevice) != hipSuccess) ||
         hipDeviceSynchronize() != hipSuccess) {
         pir_db_free(db);
@@ -583,7 +635,7 @@ static int make_leaves(pir_ctx* ctx, const Launch& lc, const uint64_t* query, ui
         }
     }
     Prof pr(ctx, "ntt_fwd", lc.stream, bfly(ctx, G * LL));
-    cw::launch_ntt(lc, false, QX, QX, G * LL, (uint32_t)LL, 0);
+    cw::launch_ntt_operand(lc, QX, QX, G * LL, (uint32_t)LL, 0);
     return check_launch(ctx);
 }
 
@@ -632,7 +684,7 @@ static void make_nodes(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint
             cw::launch_extend(lc, tmp, dst, (size_t)2 * cnt);
         }
         Prof pr(ctx, "ntt_fwd", lc.stream, bfly(ctx, (size_t)cnt * 2 * LL));
-        cw::launch_ntt(lc, false, dst, dst, (size_t)cnt * 2 * LL, LL, 0);
+        cw::launch_ntt_operand(lc, dst, dst, (size_t)cnt * 2 * LL, LL, 0);
     }
 }
 
@@ -1064,7 +1116,7 @@ extern "C" int pir_mult(pir_ctx* ctx, const uint64_t* a, const uint64_t* b_, uin
     CW_HIP(ctx, hipMemcpyAsync(refs, h_refs, 8, hipMemcpyHostToDevice, st));
     cw::launch_extend(lc, a, QX, 2);
     cw::launch_extend(lc, b_, QX + 2 * LL * N, 2);
-    cw::launch_ntt(lc, false, QX, QX, 4 * LL, LL, 0);
+    cw::launch_ntt_operand(lc, QX, QX, 4 * LL, LL, 0);
     cw::Batch bt{};
     bt.nq = 1;
     bt.E = 1;

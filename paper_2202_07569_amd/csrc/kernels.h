@@ -18,12 +18,15 @@ struct QueryPtrs {  // passed by value as a kernel argument
 // same E elements (the operand references are shared); element e of query q is row q*E + e of the
 // launch's work buffers.  Passed by value as a kernel argument.
 constexpr int MAX_QB = 8;
+// Operand format of transformed extended operands and keys: with the fp64 transforms (Launch::fp)
+// the 8-byte words hold integer-valued doubles in [-p/2, p/2]; otherwise u64 residues in [0, p)
+// (keys followed by their Shoup companions).
 struct Batch {
     uint32_t nq, E;
-    const uint64_t* leaves[MAX_QB];  // resident query [m][2][LL][N]
-    const uint64_t* nodes[MAX_QB];   // level-1 products [pairs][2][LL][N] (or null)
-    const uint64_t* rlk[MAX_QB];     // transformed key and companions
-    uint64_t* sel[MAX_QB];           // selectors out [E][2][L][N]
+    const uint64_t* leaves[MAX_QB];  // resident query [m][2][LL][N], operand format
+    const uint64_t* nodes[MAX_QB];   // level-1 products [pairs][2][LL][N] (or null), operand format
+    const uint64_t* rlk[MAX_QB];     // transformed key [L][2][L][N], operand format
+    uint64_t* sel[MAX_QB];           // selectors out [E][2][L][N], u64 residues
 };
 
 struct Launch {
@@ -32,6 +35,8 @@ struct Launch {
     const uint64_t* tw;   // device twiddles [LL][4][N]
     const double* twf;    // the same as doubles (fp64 transform), or null
     bool fp;              // transforms run on the fp64 pipe (every prime below 2^50, N <= 8192)
+    bool q_lazy;          // fp and every ciphertext prime below 2^48: forward transforms modulo q_j
+                          // need no reduction between passes
     uint32_t N, logN, L, LB, LL;
     uint32_t cus;         // compute units of the device
     uint64_t* fix;        // fixup list for ambiguous conversions (capacity >= coefficients per launch)
@@ -41,6 +46,10 @@ struct Launch {
 hipError_t kernels_init();
 void launch_ntt(const Launch& lc, bool inverse, const uint64_t* in, uint64_t* out, size_t rows, uint32_t nl,
                 uint32_t pbase);
+// Forward transform of coefficient-form rows (u64 in [0, p)) into the operand format (in place
+// allowed).
+void launch_ntt_operand(const Launch& lc, const uint64_t* in, uint64_t* out, size_t rows, uint32_t nl,
+                        uint32_t pbase);
 void launch_ntt_payload(const Launch& lc, const uint16_t* pay, uint64_t* out, size_t rows_u16);
 // Transformed relinearization staging [E][L+2][L][N] straight from a coefficient-form [E][3][L][N].
 void launch_ntt_digits(const Launch& lc, const uint64_t* c3, uint64_t* out, uint32_t E);
@@ -60,6 +69,9 @@ void launch_gather_leaf(const Launch& lc, const uint32_t* refs, const Batch& bt)
 void launch_accumulate(const Launch& lc, const QueryPtrs& qp, const uint64_t* Ph, uint32_t nq, uint32_t E,
                        uint32_t s);
 void launch_pointwise_pt(const Launch& lc, const uint64_t* ct, const uint64_t* pt, uint64_t* out);
+// Row gather: dst row e = src row order[e] for e < n, rows of `row` uint16 (a multiple of 8).
+void launch_gather_rows(hipStream_t st, const uint16_t* src, const uint64_t* order, uint64_t n, size_t row,
+                        uint16_t* dst);
 void launch_fill(hipStream_t st, uint64_t* p, size_t n, uint64_t v);
 void launch_map_perfect(hipStream_t st, const uint64_t* ids, size_t n, uint32_t m, uint32_t k, const uint64_t* binom,
                         uint32_t* out);

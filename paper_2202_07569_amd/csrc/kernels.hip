@@ -160,6 +160,9 @@ __device__ __forceinline__ void inv_pass(uint64_t* a, uint32_t tid, const uint64
 // Forward: a pass of at most three stages starting from |x| <= p ends below 4.8p; inverse: from
 // |x| <= p/2 below 4p; the final N^-1 product stays below 2p.  Every value stays below 2^53, so
 // every operation above is exact.
+// Lazy forward transform (primes below 2^48): with |y| = b p the product satisfies
+// |T| <= (1/2 + 3 b 2^-5) p, so a stage maps a bound b to b (1 + 3/32) + 1/2; from b = 1 the 13
+// stages of N = 8192 end below 15 p < 2^52, and no reduction is needed before the final one.
 // ---------------------------------------------------------------------------------------------
 #pragma clang fp contract(off)
 __device__ __forceinline__ double fmulmod(double y, double w, double p, double pinv) {
@@ -172,12 +175,12 @@ __device__ __forceinline__ double fred(double x, double p, double pinv) {
     return __builtin_fma(-__builtin_rint(x * pinv), p, x);
 }
 
-template <class Sh, int P>
+template <class Sh, int P, bool LAZY = false>
 __device__ __forceinline__ void fwd_pass_fp(double* a, uint32_t tid, const double* __restrict__ tw, double p,
                                             double pinv) {
     using G = PassGeo<Sh, P>;
     static_assert(G::rp <= 3, "the fp64 bound needs passes of at most three stages");
-    if constexpr (P > 0) {
+    if constexpr (P > 0 && !LAZY) {
 #pragma unroll
         for (int u = 0; u < Sh::EPT; ++u) a[u] = fred(a[u], p, pinv);
     }
@@ -246,15 +249,15 @@ struct TwRow {
     const double* f;
 };
 
-template <class Sh, bool FP, int P>
+template <class Sh, bool FP, int P, bool LAZY = false>
 __device__ __forceinline__ void fwd_passes(void* av, void* smv, uint32_t tid, TwRow tw, const CtxConst* K,
                                            uint32_t pi) {
     if constexpr (FP) {
         double* a = (double*)av;
-        fwd_pass_fp<Sh, P>(a, tid, tw.f, K->pd[pi], K->pinv[pi]);
+        fwd_pass_fp<Sh, P, LAZY>(a, tid, tw.f, K->pd[pi], K->pinv[pi]);
         if constexpr (P + 1 < Sh::NP) {
             exchange<Sh, P, P + 1>(a, (double*)smv, tid);
-            fwd_passes<Sh, FP, P + 1>(av, smv, tid, tw, K, pi);
+            fwd_passes<Sh, FP, P + 1, LAZY>(av, smv, tid, tw, K, pi);
         }
     } else {
         uint64_t* a = (uint64_t*)av;
@@ -286,6 +289,28 @@ __device__ __forceinline__ void inv_passes(void* av, void* smv, uint32_t tid, Tw
     }
 }
 
+// fp64 transforms of integer-valued doubles v[] (first-pass pattern in, |v| <= p for the forward
+// transform; any |v| < 2^53 for the inverse, whose passes start by reducing).  On return v[] holds
+// the outputs reduced to [-p/2, p/2]: the forward transform in the transformed layout, the inverse
+// (including N^-1) in the first pass's natural-order pattern.
+template <class Sh, bool LAZY = false>
+__device__ __forceinline__ void ntt_fwd_f(double* v, uint64_t* sm, uint32_t tid, TwRow tw, const CtxConst* K,
+                                          uint32_t pi) {
+    static_assert(!LAZY || Sh::LOGN <= 13, "the lazy bound covers at most 13 stages");
+    fwd_passes<Sh, true, 0, LAZY>(v, sm, tid, tw, K, pi);
+    const double p = K->pd[pi], pinv = K->pinv[pi];
+#pragma unroll
+    for (int u = 0; u < Sh::EPT; ++u) v[u] = fred(v[u], p, pinv);
+}
+template <class Sh>
+__device__ __forceinline__ void ntt_inv_f(double* v, uint64_t* sm, uint32_t tid, TwRow tw, const CtxConst* K,
+                                          uint32_t pi) {
+    inv_passes<Sh, true, Sh::NP - 1>(v, sm, tid, tw, K, pi);
+    const double p = K->pd[pi], pinv = K->pinv[pi], ni = K->ninvd[pi];
+#pragma unroll
+    for (int u = 0; u < Sh::EPT; ++u) v[u] = fred(fmulmod(v[u], ni, p, pinv), p, pinv);
+}
+
 // Forward transform of the EPT values a[] (residues in [0, p), first-pass pattern) of thread tid;
 // on return a[] holds the thread's outputs (transformed layout) reduced to [0, p).
 template <class Sh, bool FP>
@@ -295,10 +320,10 @@ __device__ __forceinline__ void ntt_fwd_regs(uint64_t* a, uint64_t* sm, uint32_t
         double v[Sh::EPT];
 #pragma unroll
         for (int u = 0; u < Sh::EPT; ++u) v[u] = (double)a[u];
-        fwd_passes<Sh, true, 0>(v, sm, tid, tw, K, pi);
-        const double p = K->pd[pi], pinv = K->pinv[pi];
+        ntt_fwd_f<Sh>(v, sm, tid, tw, K, pi);
+        const double p = K->pd[pi];
 #pragma unroll
-        for (int u = 0; u < Sh::EPT; ++u) a[u] = fp_to_residue(fred(v[u], p, pinv), p);
+        for (int u = 0; u < Sh::EPT; ++u) a[u] = fp_to_residue(v[u], p);
     } else {
         fwd_passes<Sh, false, 0>(a, sm, tid, tw, K, pi);
         const uint64_t p = K->p[pi], p2 = 2 * p;
@@ -320,10 +345,10 @@ __device__ __forceinline__ void ntt_inv_regs(uint64_t* a, uint64_t* sm, uint32_t
         double v[Sh::EPT];
 #pragma unroll
         for (int u = 0; u < Sh::EPT; ++u) v[u] = (double)a[u];
-        inv_passes<Sh, true, Sh::NP - 1>(v, sm, tid, tw, K, pi);
-        const double p = K->pd[pi], pinv = K->pinv[pi], ni = K->ninvd[pi];
+        ntt_inv_f<Sh>(v, sm, tid, tw, K, pi);
+        const double p = K->pd[pi];
 #pragma unroll
-        for (int u = 0; u < Sh::EPT; ++u) a[u] = fp_to_residue(fred(fmulmod(v[u], ni, p, pinv), p, pinv), p);
+        for (int u = 0; u < Sh::EPT; ++u) a[u] = fp_to_residue(v[u], p);
     } else {
         inv_passes<Sh, false, Sh::NP - 1>(a, sm, tid, tw, K, pi);
         const uint64_t p = K->p[pi], ni = K->ninv[pi], niq = K->ninvq[pi];
@@ -512,8 +537,55 @@ struct RowsTensor {
                                mul_barrett(A[o1 + u * T], B[o0 + u * T], p, mu, s), p);
         }
     }
+    // fp64 operand format: the operands are integer-valued doubles in [-p/2, p/2]; each product
+    // is below 0.7 p in magnitude (fmulmod's bound), X1 below 1.4 p.
+    __device__ void load_f(size_t g, uint32_t tid, double* a) const {
+        constexpr int N = Sh::N, T = Sh::T;
+        const uint32_t l = (uint32_t)(g % LL);
+        const size_t er = g / LL;
+        const uint32_t r = (uint32_t)(er % 3);
+        const size_t e = er / 3;
+        const size_t ct = (size_t)2 * LL * N;
+        const uint32_t ra = refs[2 * (e - eshift)], rb = refs[2 * (e - eshift) + 1];
+        const double* lv = (const double*)leaves;
+        const double* nd = (const double*)nodes;
+        const double* A = (ra & REF_NODE) ? nd + (size_t)(ra & ~REF_NODE) * ct : lv + (size_t)ra * ct;
+        const double* B = (rb & REF_NODE) ? nd + (size_t)(rb & ~REF_NODE) * ct : lv + (size_t)rb * ct;
+        const double p = K->pd[l], pinv = K->pinv[l];
+        const size_t o0 = (size_t)l * N + tid, o1 = (size_t)(LL + l) * N + tid;
+        if (r == 0) {
+#pragma unroll
+            for (int u = 0; u < Sh::EPT; ++u) a[u] = fmulmod(A[o0 + u * T], B[o0 + u * T], p, pinv);
+        } else if (r == 2) {
+#pragma unroll
+            for (int u = 0; u < Sh::EPT; ++u) a[u] = fmulmod(A[o1 + u * T], B[o1 + u * T], p, pinv);
+        } else {
+#pragma unroll
+            for (int u = 0; u < Sh::EPT; ++u)
+                a[u] = fmulmod(A[o0 + u * T], B[o1 + u * T], p, pinv) + fmulmod(A[o1 + u * T], B[o0 + u * T], p, pinv);
+        }
+    }
     __device__ void store(size_t g, uint32_t tid, int u, uint64_t v) const { out[natural_pos<Sh>(g, tid, u)] = v; }
 };
+
+// Forward transform of coefficient-form rows (u64 residues in [0, p)) into the fp64 operand
+// format: integer-valued doubles in [-p/2, p/2], transformed layout.
+template <class Sh>
+__global__ __launch_bounds__(Sh::T) void k_ntt_fwd_operand(const CtxConst* __restrict__ K,
+                                                           const uint64_t* __restrict__ tw,
+                                                           const double* __restrict__ twf, const uint64_t* in,
+                                                           double* out, uint32_t nl, uint32_t pbase) {
+    __shared__ uint64_t sm[Sh::LDS_WORDS];
+    const uint32_t tid = threadIdx.x;
+    const size_t g = blockIdx.x;
+    const uint32_t pi = pbase + (uint32_t)(g % nl);
+    double v[Sh::EPT];
+#pragma unroll
+    for (int u = 0; u < Sh::EPT; ++u) v[u] = (double)in[natural_pos<Sh>(g, tid, u)];
+    ntt_fwd_f<Sh>(v, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
+#pragma unroll
+    for (int u = 0; u < Sh::EPT; ++u) out[transformed_pos<Sh>(g, tid, u)] = v[u];
+}
 
 template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T) void k_ntt_fwd(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
@@ -555,12 +627,21 @@ __global__ __launch_bounds__(Sh::T) void k_ntt_inv_tensor(const CtxConst* __rest
     const size_t g = (eq * 3 + r) * LL + el % LL;
     const RowsTensor<Sh> row{refs, bt.leaves[q], bt.nodes[q], X, K, LL, (size_t)q * bt.E};
     const uint32_t tid = threadIdx.x;
-    uint64_t a[Sh::EPT];
-    row.load(g, tid, a);
     const uint32_t pi = row.prime(g);
-    ntt_inv_regs<Sh, FP>(a, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
+    if constexpr (FP) {
+        double v[Sh::EPT];
+        row.load_f(g, tid, v);
+        ntt_inv_f<Sh>(v, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
+        const double p = K->pd[pi];
 #pragma unroll
-    for (int u = 0; u < Sh::EPT; ++u) row.store(g, tid, u, a[u]);
+        for (int u = 0; u < Sh::EPT; ++u) row.store(g, tid, u, fp_to_residue(v[u], p));
+    } else {
+        uint64_t a[Sh::EPT];
+        row.load(g, tid, a);
+        ntt_inv_regs<Sh, FP>(a, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
+#pragma unroll
+        for (int u = 0; u < Sh::EPT; ++u) row.store(g, tid, u, a[u]);
+    }
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -572,7 +653,7 @@ __global__ __launch_bounds__(Sh::T) void k_ntt_inv_tensor(const CtxConst* __rest
 // ---------------------------------------------------------------------------------------------
 
 
-template <class Sh, bool FP>
+template <class Sh, bool FP, bool LAZY>
 __global__ __launch_bounds__(Sh::T) void k_relin(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
                                                  const double* __restrict__ twf, const uint64_t* __restrict__ c3,
                                                  const Batch bt) {
@@ -585,55 +666,104 @@ __global__ __launch_bounds__(Sh::T) void k_relin(const CtxConst* __restrict__ K,
     if (eq >= (size_t)bt.nq * bt.E) return;
     const uint32_t q = (uint32_t)(eq / bt.E);
     const size_t e = eq % bt.E;
-    const uint64_t* __restrict__ rlk = bt.rlk[q];
     uint64_t* __restrict__ sel = bt.sel[q];
-    const uint64_t p = K->p[j], r1 = K->r1[j];
     const TwRow twr = tw_row(tw, twf, j, N);
     const uint64_t* base = c3 + eq * 3 * L * N;
-    const size_t LN = (size_t)L * N, half = (size_t)L * 2 * LN;
-    uint64_t acc0[EPT], acc1[EPT], a[EPT];
-    for (uint32_t i = 0; i < L + 2; ++i) {
-        // The transform's index and twiddle arithmetic does not depend on i; opaque copies of the
-        // thread index and table pointers per iteration keep the compiler from hoisting all of it
-        // out of the loop into registers (which would spill).
-        uint32_t t = tid;
-        TwRow tr = twr;
-        asm volatile("" : "+v"(t), "+v"(tr.i), "+v"(tr.f));
-        const uint64_t* src = i < L ? base + ((size_t)2 * L + i) * N : base + ((size_t)(i - L) * L + j) * N;
-        if (i < L && i != j) {
-#pragma unroll
-            for (int u = 0; u < EPT; ++u) a[u] = reduce64(src[elem_index<Sh, 0>(t, u)], p, r1);
-        } else {
-#pragma unroll
-            for (int u = 0; u < EPT; ++u) a[u] = src[elem_index<Sh, 0>(t, u)];
-        }
-        ntt_fwd_regs<Sh, FP>(a, sm, t, tr, K, j);
-        asm volatile("" ::: "memory");  // keep the key loads below the transform
-        if (i < L) {
-            const uint64_t* bh = rlk + ((size_t)i * 2 + 0) * LN + (size_t)j * N + t;
-            const uint64_t* ah = rlk + ((size_t)i * 2 + 1) * LN + (size_t)j * N + t;
-#pragma unroll
-            for (int u = 0; u < EPT; ++u) {
-                const size_t o = (size_t)u * T;
-                const uint64_t tb = mul_shoup(a[u], bh[o], bh[half + o], p);
-                const uint64_t ta = mul_shoup(a[u], ah[o], ah[half + o], p);
-                acc0[u] = i == 0 ? tb : add_mod(acc0[u], tb, p);
-                acc1[u] = i == 0 ? ta : add_mod(acc1[u], ta, p);
-            }
-        } else {
-#pragma unroll
-            for (int u = 0; u < EPT; ++u) {
-                if (i == L) acc0[u] = add_mod(acc0[u], a[u], p);
-                else acc1[u] = add_mod(acc1[u], a[u], p);
-            }
-        }
-        asm volatile("" ::: "memory");
-    }
+    const size_t LN = (size_t)L * N;
     uint64_t* o0 = sel + e * 2 * LN + (size_t)j * N + tid;
+    if constexpr (FP) {
+        // Key in the fp64 operand format; the digits D_i < q_i are exact doubles reduced mod q_j by
+        // fred.  Transformed values and key entries lie in [-p/2, p/2], so each product is below
+        // 0.7 p and each accumulator below (0.7 L + 0.5) p < 2^53.
+        const double* __restrict__ rlk = (const double*)bt.rlk[q];
+        const double p = K->pd[j], pinv = K->pinv[j];
+        double acc0[EPT], acc1[EPT], v[EPT];
+        for (uint32_t i = 0; i < L + 2; ++i) {
+            // The transform's index and twiddle arithmetic does not depend on i; opaque copies of
+            // the thread index and table pointers per iteration keep the compiler from hoisting all
+            // of it out of the loop into registers (which would spill).
+            uint32_t t = tid;
+            TwRow tr = twr;
+            asm volatile("" : "+v"(t), "+v"(tr.i), "+v"(tr.f));
+            const uint64_t* src = i < L ? base + ((size_t)2 * L + i) * N : base + ((size_t)(i - L) * L + j) * N;
+            if (i < L && i != j) {
 #pragma unroll
-    for (int u = 0; u < EPT; ++u) {
-        o0[(size_t)u * T] = acc0[u];
-        o0[LN + (size_t)u * T] = acc1[u];
+                for (int u = 0; u < EPT; ++u) v[u] = fred((double)src[elem_index<Sh, 0>(t, u)], p, pinv);
+            } else {
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) v[u] = (double)src[elem_index<Sh, 0>(t, u)];
+            }
+            ntt_fwd_f<Sh, LAZY>(v, (uint64_t*)sm, t, tr, K, j);
+            asm volatile("" ::: "memory");  // keep the key loads below the transform
+            if (i < L) {
+                const double* bh = rlk + ((size_t)i * 2 + 0) * LN + (size_t)j * N + t;
+                const double* ah = rlk + ((size_t)i * 2 + 1) * LN + (size_t)j * N + t;
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) {
+                    const size_t o = (size_t)u * T;
+                    const double tb = fmulmod(v[u], bh[o], p, pinv);
+                    const double ta = fmulmod(v[u], ah[o], p, pinv);
+                    acc0[u] = i == 0 ? tb : acc0[u] + tb;
+                    acc1[u] = i == 0 ? ta : acc1[u] + ta;
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) {
+                    if (i == L) acc0[u] = acc0[u] + v[u];
+                    else acc1[u] = acc1[u] + v[u];
+                }
+            }
+            asm volatile("" ::: "memory");
+        }
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            o0[(size_t)u * T] = fp_to_residue(fred(acc0[u], p, pinv), p);
+            o0[LN + (size_t)u * T] = fp_to_residue(fred(acc1[u], p, pinv), p);
+        }
+    } else {
+        const uint64_t* __restrict__ rlk = bt.rlk[q];
+        const uint64_t p = K->p[j], r1 = K->r1[j];
+        const size_t half = (size_t)L * 2 * LN;
+        uint64_t acc0[EPT], acc1[EPT], a[EPT];
+        for (uint32_t i = 0; i < L + 2; ++i) {
+            uint32_t t = tid;
+            TwRow tr = twr;
+            asm volatile("" : "+v"(t), "+v"(tr.i), "+v"(tr.f));
+            const uint64_t* src = i < L ? base + ((size_t)2 * L + i) * N : base + ((size_t)(i - L) * L + j) * N;
+            if (i < L && i != j) {
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) a[u] = reduce64(src[elem_index<Sh, 0>(t, u)], p, r1);
+            } else {
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) a[u] = src[elem_index<Sh, 0>(t, u)];
+            }
+            ntt_fwd_regs<Sh, false>(a, sm, t, tr, K, j);
+            asm volatile("" ::: "memory");
+            if (i < L) {
+                const uint64_t* bh = rlk + ((size_t)i * 2 + 0) * LN + (size_t)j * N + t;
+                const uint64_t* ah = rlk + ((size_t)i * 2 + 1) * LN + (size_t)j * N + t;
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) {
+                    const size_t o = (size_t)u * T;
+                    const uint64_t tb = mul_shoup(a[u], bh[o], bh[half + o], p);
+                    const uint64_t ta = mul_shoup(a[u], ah[o], ah[half + o], p);
+                    acc0[u] = i == 0 ? tb : add_mod(acc0[u], tb, p);
+                    acc1[u] = i == 0 ? ta : add_mod(acc1[u], ta, p);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) {
+                    if (i == L) acc0[u] = add_mod(acc0[u], a[u], p);
+                    else acc1[u] = add_mod(acc1[u], a[u], p);
+                }
+            }
+            asm volatile("" ::: "memory");
+        }
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) {
+            o0[(size_t)u * T] = acc0[u];
+            o0[LN + (size_t)u * T] = acc1[u];
+        }
     }
 }
 
@@ -646,12 +776,15 @@ void launch_relin(const Launch& lc, const uint64_t* c3, const Batch& bt, uint64_
 #define CW_RELIN(LG)                                                                                               \
     {                                                                                                              \
         using Sh = DefaultShape<LG>::type;                                                                         \
-        if (lc.fp)                                                                                                 \
-            hipLaunchKernelGGL((k_relin<Sh, true>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, lc.twf, c3, \
-                               bt);                                                                                \
+        if (lc.fp && lc.q_lazy)                                                                                    \
+            hipLaunchKernelGGL((k_relin<Sh, true, true>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,      \
+                               lc.twf, c3, bt);                                                                    \
+        else if (lc.fp)                                                                                            \
+            hipLaunchKernelGGL((k_relin<Sh, true, false>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,     \
+                               lc.twf, c3, bt);                                                                    \
         else                                                                                                       \
-            hipLaunchKernelGGL((k_relin<Sh, false>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, lc.twf,   \
-                               c3, bt);                                                                            \
+            hipLaunchKernelGGL((k_relin<Sh, false, false>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,    \
+                               lc.twf, c3, bt);                                                                    \
     }
     switch (lc.logN) {
         case 12: CW_RELIN(12) break;
@@ -698,6 +831,27 @@ void launch_ntt(const Launch& lc, bool inverse, const uint64_t* in, uint64_t* ou
         CW_NTT_DISPATCH(lc, k_ntt_inv, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, in, out, nl, pbase)
     } else {
         CW_NTT_DISPATCH(lc, k_ntt_fwd, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, in, out, nl, pbase)
+    }
+}
+
+void launch_ntt_operand(const Launch& lc, const uint64_t* in, uint64_t* out, size_t rows, uint32_t nl,
+                        uint32_t pbase) {
+    if (!rows) return;
+    if (!lc.fp) {
+        launch_ntt(lc, false, in, out, rows, nl, pbase);
+        return;
+    }
+    switch (lc.logN) {
+        case 12: {
+            using Sh = DefaultShape<12>::type;
+            hipLaunchKernelGGL(k_ntt_fwd_operand<Sh>, dim3((unsigned)rows), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,
+                               lc.twf, in, (double*)out, nl, pbase);
+        } break;
+        case 13: {
+            using Sh = DefaultShape<13>::type;
+            hipLaunchKernelGGL(k_ntt_fwd_operand<Sh>, dim3((unsigned)rows), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,
+                               lc.twf, in, (double*)out, nl, pbase);
+        } break;
     }
 }
 
@@ -1006,7 +1160,8 @@ __global__ void k_gather_leaf(const CtxConst* __restrict__ K, const uint32_t* __
     const uint32_t poly = (uint32_t)(ep % 2);
     const size_t e = ep / 2;
     const uint32_t leaf = refs[2 * e];
-    bt.sel[q][gq] = bt.leaves[q][((size_t)leaf * 2 * LL + (size_t)poly * LL + j) * N + c];
+    const size_t src = ((size_t)leaf * 2 * LL + (size_t)poly * LL + j) * N + c;
+    bt.sel[q][gq] = K->fp ? fp_to_residue(((const double*)bt.leaves[q])[src], K->pd[j]) : bt.leaves[q][src];
 }
 
 void launch_gather_leaf(const Launch& lc, const uint32_t* refs, const Batch& bt) {
@@ -1047,6 +1202,23 @@ void launch_accumulate(const Launch& lc, const QueryPtrs& qp, const uint64_t* Ph
     if (!E || !nq) return;
     hipLaunchKernelGGL(k_accumulate, dim3(blocks_for((size_t)s * 2 * lc.L * lc.N), nq), dim3(EW_THREADS), 0,
                        lc.stream, lc.K, qp, Ph, E, s);
+}
+
+// dst row e = src row order[e], rows of `row` uint16 (a multiple of 8), copied in 16-byte words.
+__global__ void k_gather_rows(const uint16_t* __restrict__ src, const uint64_t* __restrict__ order, uint64_t n,
+                              size_t row, uint16_t* __restrict__ dst) {
+    const size_t words = row / 8;  // 16-byte words per row
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= n * words) return;
+    const size_t e = gid / words, w = gid % words;
+    ((uint4*)dst)[e * words + w] = ((const uint4*)src)[order[e] * words + w];
+}
+
+void launch_gather_rows(hipStream_t st, const uint16_t* src, const uint64_t* order, uint64_t n, size_t row,
+                        uint16_t* dst) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_gather_rows, dim3(blocks_for(n * (row / 8))), dim3(EW_THREADS), 0, st, src, order, n, row,
+                       dst);
 }
 
 // Pointwise product of a transformed ciphertext [2][L][N] with a transformed plaintext [L][N].
