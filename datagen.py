@@ -29,7 +29,7 @@ GAMMA = 0x9E3779B97F4A7C15
 MASK64 = (1 << 64) - 1
 
 S_SECRET, S_RLK, S_QUERY, S_PAYLOAD, S_PERM, S_TARGET, S_KEYWORDS, S_HASH, S_ARRIVALS, \
-    S_DBCHOICE, S_SYNTH = range(1, 12)
+    S_DBCHOICE, S_SYNTH, S_GALOIS, S_PACKED = range(1, 14)
 
 
 def mix64(z: int) -> int:

@@ -53,6 +53,10 @@ def lib():
             "orc_add": (None, [vp, P64, P64, u32, P64]),
             "orc_selector": (None, [vp, vp, P64, P32, u32, P64]),
             "orc_answer": (None, [vp, vp, P64, u32, u64, u32, P32, P16, P64, ctypes.c_int]),
+            "orc_automorphism": (None, [vp, P64, u32, u32, P64]),
+            "orc_mul_monomial": (None, [vp, P64, u32, u32, P64]),
+            "orc_galois_keygen": (None, [vp, P8, u32, P64, P64, P64]),
+            "orc_sub": (None, [vp, vp, P64, u32, P64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -166,6 +170,15 @@ class Oracle:
         lib().orc_relin_keygen(self._h, _ptr(sk, ctypes.c_int8), _ptr(ra), _ptr(re), _ptr(rlk))
         return rlk
 
+    def galois_keygen(self, sk: np.ndarray, g: int, rnd: np.ndarray) -> np.ndarray:
+        """Key switching from s(x^g) to s (same randomness layout as relin_keygen)."""
+        na = self.L * 2 * self.L * self.N
+        ra = np.ascontiguousarray(rnd[:na], dtype=np.uint64)
+        re = np.ascontiguousarray(rnd[na: na + self.L * self.N], dtype=np.uint64)
+        gk = np.empty((self.L, 2, self.L, self.N), dtype=np.uint64)
+        lib().orc_galois_keygen(self._h, _ptr(sk, ctypes.c_int8), int(g), _ptr(ra), _ptr(re), _ptr(gk))
+        return gk
+
     def decrypt(self, sk: np.ndarray, ct: np.ndarray) -> tuple:
         """Returns (message mod t [N], largest log2 noise)."""
         ct = np.ascontiguousarray(ct, dtype=np.uint64)
@@ -207,6 +220,27 @@ class Oracle:
         b = np.ascontiguousarray(b, dtype=np.uint64)
         out = np.empty_like(a)
         lib().orc_add(self._h, _ptr(a), _ptr(b), a.shape[0], _ptr(out))
+        return out
+
+    def automorphism(self, ct: np.ndarray, g: int) -> np.ndarray:
+        """x -> x^g (g odd) on every polynomial of ct [npoly][L][N]."""
+        ct = np.ascontiguousarray(ct, dtype=np.uint64)
+        out = np.empty_like(ct)
+        lib().orc_automorphism(self._h, _ptr(ct), ct.shape[0], int(g), _ptr(out))
+        return out
+
+    def mul_monomial(self, ct: np.ndarray, e: int) -> np.ndarray:
+        """Multiply every polynomial of ct [npoly][L][N] by x^e (0 <= e < 2N)."""
+        ct = np.ascontiguousarray(ct, dtype=np.uint64)
+        out = np.empty_like(ct)
+        lib().orc_mul_monomial(self._h, _ptr(ct), ct.shape[0], int(e) % (2 * self.N), _ptr(out))
+        return out
+
+    def sub(self, gk: Key, ct: np.ndarray, g: int) -> np.ndarray:
+        """Substitution Sub_g: automorphism, then key switch back to s with the Galois key gk."""
+        ct = np.ascontiguousarray(ct, dtype=np.uint64)
+        out = np.empty(self.ct_shape(2), dtype=np.uint64)
+        lib().orc_sub(self._h, gk._h, _ptr(ct), int(g), _ptr(out))
         return out
 
     def selector(self, key: Key, query: np.ndarray, positions) -> np.ndarray:

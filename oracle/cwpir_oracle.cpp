@@ -714,4 +714,85 @@ void orc_answer(const OrcCtx* c, const OrcKey* key, const uint64_t* query, uint3
             for (uint32_t j = 0; j < L; ++j) c->qntt[j].inverse(answer + (size_t)r * ctsz + ((size_t)poly * L + j) * N);
 }
 
+// ---- query expansion (Section 3.3.3 "Query Expansion", Algorithm 5; Algorithm 1) ---------------
+// The Galois automorphism x -> x^g (g odd) of R_q: coefficient i of a polynomial moves to position
+// i g mod 2N and is negated when that position is N or more (x^N = -1).  Written as the direct
+// definition: a scatter over the input coefficients.  in/out: [npoly][L][N], out != in.
+void orc_automorphism(const OrcCtx* c, const uint64_t* in, uint32_t npoly, uint32_t g, uint64_t* out) {
+    const uint32_t N = c->N, L = c->L;
+    for (uint32_t r = 0; r < npoly * L; ++r) {
+        const uint64_t p = c->qp[r % L];
+        const uint64_t* a = in + (size_t)r * N;
+        uint64_t* b = out + (size_t)r * N;
+        for (uint32_t i = 0; i < N; ++i) {
+            const uint64_t pos = (uint64_t)i * g % (2ull * N);
+            if (pos < N) b[pos] = a[i];
+            else b[pos - N] = a[i] ? p - a[i] : 0;
+        }
+    }
+}
+
+// Multiplication by the monomial x^e, 0 <= e < 2N: coefficient i moves to (i + e) mod 2N, negated
+// past N.  in/out: [npoly][L][N], out != in.
+void orc_mul_monomial(const OrcCtx* c, const uint64_t* in, uint32_t npoly, uint32_t e, uint64_t* out) {
+    const uint32_t N = c->N, L = c->L;
+    for (uint32_t r = 0; r < npoly * L; ++r) {
+        const uint64_t p = c->qp[r % L];
+        const uint64_t* a = in + (size_t)r * N;
+        uint64_t* b = out + (size_t)r * N;
+        for (uint32_t i = 0; i < N; ++i) {
+            const uint64_t pos = ((uint64_t)i + e) % (2ull * N);
+            if (pos < N) b[pos] = a[i];
+            else b[pos - N] = a[i] ? p - a[i] : 0;
+        }
+    }
+}
+
+// Galois key for x -> x^g: gk_i = (b_i, a_i), b_i = [-a_i s + e_i + g_i s(x^g)]_q with the digits and
+// g_i of the relinearization key.  Randomness layout as orc_relin_keygen.  gk: [L][2][L][N].
+void orc_galois_keygen(const OrcCtx* c, const int8_t* sk, uint32_t g, const uint64_t* rnd_a,
+                       const uint64_t* rnd_e, uint64_t* gk) {
+    const uint32_t N = c->N, L = c->L;
+    std::vector<int8_t> sg(N);  // s(x^g): a signed permutation of s, still ternary
+    for (uint32_t i = 0; i < N; ++i) {
+        const uint64_t pos = (uint64_t)i * g % (2ull * N);
+        if (pos < N) sg[pos] = sk[i];
+        else sg[pos - N] = (int8_t)-sk[i];
+    }
+    std::vector<uint64_t> s(N), sgm(N), as(N);
+    for (uint32_t i = 0; i < L; ++i) {
+        Big gi = mul_u64(c->Q.Mk[i], c->Q.inv[i]);
+        for (uint32_t j = 0; j < L; ++j) {
+            uint64_t p = c->qp[j];
+            uint64_t* b = gk + (((size_t)i * 2 + 0) * L + j) * N;
+            uint64_t* a = gk + (((size_t)i * 2 + 1) * L + j) * N;
+            for (uint32_t x = 0; x < N; ++x) {
+                size_t idx = (((size_t)i * L + j) * N + x) * 2;
+                a[x] = uniform_mod(rnd_a[idx], rnd_a[idx + 1], p);
+            }
+            ternary_mod(sk, N, p, s.data());
+            ternary_mod(sg.data(), N, p, sgm.data());
+            poly_mul_mod(c, j, a, s.data(), as.data());
+            uint64_t gm = mod_u64(gi, p);
+            for (uint32_t x = 0; x < N; ++x) {
+                uint64_t e = signed_mod(cbd21(rnd_e[(size_t)i * N + x]), p);
+                b[x] = addm(subm(e, as[x], p), mulm(gm, sgm[x], p), p);
+            }
+        }
+    }
+}
+
+// Substitution Sub_g(ct) (Section 2.1.1): the automorphism on both polynomials, then a key switch of
+// the second back to s with the Galois key:
+//   (sigma(c0) + sum_i D_i b_i, sum_i D_i a_i),  D_i = [sigma(c1)]_{q_i} in [0, q_i).
+// That is the relinearization of the three-polynomial ciphertext (sigma(c0), 0, sigma(c1)) under gk.
+void orc_sub(const OrcCtx* c, const OrcKey* gk, const uint64_t* ct, uint32_t g, uint64_t* out) {
+    const size_t LN = (size_t)c->L * c->N;
+    std::vector<uint64_t> sig(2 * LN), three(3 * LN, 0);
+    orc_automorphism(c, ct, 2, g, sig.data());
+    std::memcpy(three.data(), sig.data(), LN * 8);
+    std::memcpy(three.data() + 2 * LN, sig.data() + LN, LN * 8);
+    orc_relin(c, gk, three.data(), out);
+}
+
 }  // extern "C"

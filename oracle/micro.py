@@ -110,3 +110,43 @@ class Micro:
         P = [int(v) for v in pt]
         return np.stack([self.to_res([v % self.q for v in _negacyclic(self.to_int(ct[r]), P)])
                          for r in range(2)])
+
+    # substitution (query expansion, Algorithm 5): written as polynomial composition over Z
+    def compose(self, poly, g):
+        """poly(x^g) mod x^N + 1 for an integer polynomial: sum_i poly_i (x^g)^i, with (x^g)^i
+        built by repeated negacyclic multiplication by the monomial x^g."""
+        N = self.N
+        mono = [0] * N
+        e = g % (2 * N)
+        if e < N:
+            mono[e] = 1
+        else:
+            mono[e - N] = -1
+        power = [1] + [0] * (N - 1)
+        out = [0] * N
+        for c in poly:
+            if c:
+                out = [u + c * v for u, v in zip(out, power)]
+            power = _negacyclic(power, mono)
+        return out
+
+    def automorphism(self, ct, g):
+        return np.stack([self.to_res([v % self.q for v in self.compose(self.to_int(ct[r]), g)])
+                         for r in range(ct.shape[0])])
+
+    def mul_monomial(self, ct, e):
+        N = self.N
+        mono = [0] * N
+        e %= 2 * N
+        if e < N:
+            mono[e] = 1
+        else:
+            mono[e - N] = -1
+        return np.stack([self.to_res([v % self.q for v in _negacyclic(self.to_int(ct[r]), mono)])
+                         for r in range(ct.shape[0])])
+
+    def sub(self, gk, ct, g):
+        """Sub_g: (sigma(c0), 0, sigma(c1)) relinearized under the Galois key."""
+        sig = self.automorphism(ct, g)
+        zero = np.zeros_like(sig[0])
+        return self.relin(gk, np.stack([sig[0], zero, sig[1]]))
