@@ -59,6 +59,12 @@ def parse():
     ap.add_argument("--n", type=int, default=0, help="override the database size")
     ap.add_argument("--cpu-sample", type=int, default=-1, help="oracle sample elements (0: skip)")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--autotune", type=int, default=-1, choices=[-1, 0, 1],
+                    help="1: tune the launch schedule per batch size before encoding; 0: never; "
+                         "-1: use the package's tuning cache when it has the workload, else tune")
+    ap.add_argument("--record-schedule", default="", help="write tuned schedules into this cache file")
+    ap.add_argument("--schedule", default="",
+                    help="fixed schedule 'chunk,query_group,relin_group' for both loops instead of tuning")
     ap.add_argument("--chunk", type=int, default=0, help="elements per processing chunk (0: library default)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (reference for rocprofv3 byte counters)")
@@ -104,8 +110,38 @@ def main():
     B = max(1, args.batch)
     log(f"workload {cfg.name}: N={cfg.N} L={cfg.L} k={cfg.k} m={cfg.m} n={n} s={cfg.s} batch={B}")
     rlk, queries, payload = synthetic_inputs(cfg, n, B)
-    ctx = Context(cfg.N, cfg.primes, cfg.t, chunk_elems=args.chunk)
-    key = ctx.load_key(rlk)
+
+    def make_ctx(batch):
+        """A context with the launch schedule for `batch` queries per call: fixed by --schedule or
+        --chunk, else the package's tuning cache, else (or with --autotune 1) the autotuner."""
+        c = Context(cfg.N, cfg.primes, cfg.t, chunk_elems=args.chunk)
+        tune, source = None, "default"
+        cached = c.cached_schedule(batch, cfg.k, cfg.s)
+        if args.schedule:
+            ch, qg, rg = (int(x) for x in args.schedule.split(","))
+            c.set_schedule(ch, min(qg, batch), rg)
+            source = "--schedule"
+        elif args.chunk:
+            source = "--chunk"
+        elif cached is not None and args.autotune != 1:
+            c.set_schedule(cached["chunk_elems"], cached["query_group"], cached["relin_group"])
+            source = "tuning cache"
+        elif args.autotune != 0:
+            tune = c.autotune(batch=batch, k=cfg.k, s=cfg.s)
+            source = "autotune"
+            log(f"autotune batch={batch}: {tune['best']} ({len(tune['candidates'])} candidates)")
+            if args.record_schedule:
+                from paper_2202_07569_amd.binding import record_schedule
+                b = tune["best"]
+                record_schedule(cfg.N, cfg.primes, batch, cfg.k, cfg.s,
+                                {k: b[k] for k in ("chunk_elems", "query_group", "relin_group")},
+                                f"pir_autotune on MI355X, {b['ns_per_elem']:.0f} ns per element-query",
+                                path=args.record_schedule)
+        log(f"schedule batch={batch} ({source}): {c.schedule()}")
+        return c, {"source": source, "tuning": tune}
+
+    ctx_plain, tune_plain = make_ctx(1)
+    ctx, tune = make_ctx(B)
     ids = datagen.identifier_permutation(cfg, n) if not cfg.keyword else None
     if cfg.keyword:
         kws = datagen.keywords(cfg, n)
@@ -114,15 +150,17 @@ def main():
         cw = ctx.map_perfect(ids.astype(np.uint64), cfg.m, cfg.k)
     torch.cuda.synchronize()
     codewords = cw.cpu().numpy()
-    db = ctx.encode_db(codewords, payload, cfg.m)
+    key, key_plain = ctx.load_key(rlk), ctx_plain.load_key(rlk)
+    db, db_plain = ctx.encode_db(codewords, payload, cfg.m), ctx_plain.encode_db(codewords, payload, cfg.m)
     dq = [torch.from_numpy(q).cuda() for q in queries]
     outs = [ctx.empty(cfg.s, 2, cfg.L, cfg.N) for _ in range(B)]
+    out_plain = ctx.empty(cfg.s, 2, cfg.L, cfg.N)
     stream = torch.cuda.current_stream()
     log(f"resident: payload {payload.nbytes / 2**20:.0f} MiB, pairs {db.pair_count}, "
         f"library HBM {ctx.device_bytes / 2**30:.2f} GiB")
 
     def step_plain():
-        ctx.answer(key, db, dq[0], out=outs[0], stream=stream)
+        ctx_plain.answer(key_plain, db_plain, dq[0], out=out_plain, stream=stream)
 
     def step_batch():
         ctx.answer_batch([key] * B, [db] * B, dq, outs=outs, stream=stream)
@@ -159,16 +197,24 @@ def main():
         del src, dst
 
     log("plain loop")
-    t_plain, per_plain, prof_plain = timed(step_plain, args.steps, args.warmup, False)
+    t_plain, per_plain, _ = timed(step_plain, args.steps, args.warmup, False)
     log(f"plain {t_plain / args.steps * 1e3:.1f} ms/query")
+    graph = ctx_plain.capture([key_plain], [db_plain], [dq[0]], outs=[out_plain])
+    t_graph, per_graph, _ = timed(lambda: graph.launch(stream=stream), args.steps, args.warmup, False)
+    log(f"plain, captured graph {t_graph / args.steps * 1e3:.1f} ms/query")
     log(f"batched B={B}")
     t_b, per_b, prof = timed(step_batch, args.steps, args.warmup, not args.no_profile)
     ms_step = t_b / args.steps * 1e3
     value = B * n * args.steps / t_b
     log(f"batched {ms_step:.1f} ms/step -> {value:.0f} elements/s")
+    torch.cuda.synchronize()
+    if not np.array_equal(out_plain.cpu().numpy(), outs[0].cpu().numpy()):
+        raise SystemExit("the batched answer of query 0 differs from the plain answer")
+
+    expansion = expansion_bench(args, ctx, cfg, torch, stream)
 
     fp = cfg.N <= 8192 and all(p < FP_PRIME_BOUND for p in tuple(cfg.primes) + ctx.aux_primes)
-    roof = roofline(prof, args.steps, fp, traffic_table(cfg, n, B, args.chunk)) if prof else None
+    roof = roofline(prof, args.steps, fp, traffic_table(cfg, n, B, ctx.schedule())) if prof else None
 
     cpu = None
     sample = args.cpu_sample if args.cpu_sample >= 0 else (256 if cfg.N <= 8192 else 32)
@@ -183,15 +229,21 @@ def main():
         "dtype": "u64", "data": "synthetic",
         "config": {"workload": f"index PIR {cfg.name}: N={cfg.N}, {cfg.L} primes ({math.prod(cfg.primes).bit_length()}"
                                f" bits), t={cfg.t}, k={cfg.k}, m={cfg.m}, n={n}, s={cfg.s}",
-                   "batch_queries": B, "chunk_elems": args.chunk or None},
+                   "batch_queries": B},
+        "schedule": {"batched": ctx.schedule(), "plain": ctx_plain.schedule(),
+                     "source": {"batched": tune, "plain": tune_plain}},
         "plain": {"value": n * args.steps / t_plain, "unit": "elements/s", "ms_per_query": t_plain / args.steps * 1e3,
                   **lat(per_plain)},
+        "plain_graph": {"value": n * args.steps / t_graph, "unit": "elements/s",
+                        "ms_per_query": t_graph / args.steps * 1e3, **lat(per_graph)},
         "batched": {"value": value, "ms_per_step": ms_step, **lat(per_b)},
+        "expansion": expansion,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    graph.close()
     if serve:
-        del db, dq, outs, key, ctx
+        del graph, db, dq, outs, key, ctx, db_plain, key_plain, ctx_plain, out_plain
         torch.cuda.empty_cache()
         out["serving"] = serve_bench(args, torch)
     print(json.dumps(out), flush=True)
@@ -200,22 +252,22 @@ def main():
 NTT_FAMILIES = ("ntt_fwd", "ntt_inv", "ntt_inv_tensor", "ntt_digits", "relin", "payload_ntt")
 
 
-def traffic_table(cfg, n, B, chunk):
+def traffic_table(cfg, n, B, schedule):
     """Calibrated HBM bytes per launch from the committed rocprofv3 counter summary, when it was
-    taken on this workload shape and the kernel sources have not changed since."""
+    taken on this workload, batch size and launch schedule and the kernel sources have not changed
+    since (else None)."""
     import hashlib
-    if cfg.name != "mid" or n != cfg.n or chunk not in (0, 256) or not os.path.exists(TRAFFIC_FILE):
+    if not os.path.exists(TRAFFIC_FILE):
         return None
+    data = json.load(open(TRAFFIC_FILE))
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(f, "rb").read())
-    data = json.load(open(TRAFFIC_FILE))
-    if data.get("kernel_source_sha256") != h.hexdigest():
+    sched = {k: schedule[k] for k in ("chunk_elems", "query_group", "relin_group")}
+    if (data.get("kernel_source_sha256") != h.hexdigest() or data.get("workload") != cfg.name
+            or data.get("n") != n or data.get("batch") != B or data.get("schedule") != sched):
         return None
-    fams = dict(data["families"])
-    if B != 4:  # accumulate reads every query's selectors; the other families do not depend on B
-        fams.pop("accumulate", None)
-    return fams
+    return dict(data["families"])
 
 
 def roofline(prof, steps, fp, traffic):
@@ -255,6 +307,34 @@ def cpu_baseline(cfg, rlk, query, codewords, payload):
     dt = time.perf_counter() - t0
     return {"value": len(codewords) / dt, "unit": "elements/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(codewords)} of {cfg.n} elements of the same workload, one query, {dt:.1f} s"}
+
+
+def expansion_bench(args, ctx, cfg, torch, stream):
+    """Server-side expansion (Algorithm 5) of a query packed with compression factor c (the smallest
+    c with 2^c >= m, at most 5): h = ceil(m / 2^c) packed ciphertexts -> m.  Synthetic uniform
+    residues stand in for the packed ciphertexts and Galois keys (the arithmetic does not depend
+    on the values)."""
+    c = min(5, max(0, (cfg.m - 1).bit_length()))
+    h = -(-cfg.m // (1 << c))
+    keys = [ctx.load_galois_key(cfg.N // (1 << a) + 1,
+                                datagen.uniform_residues(cfg.primes, (cfg.L, 2), cfg.N, seed=cfg.seed * 100 + 50 + a))
+            for a in range(c)]
+    packed = torch.from_numpy(datagen.uniform_residues(cfg.primes, (h, 2), cfg.N, seed=cfg.seed * 100 + 60)).cuda()
+    out = ctx.empty(cfg.m, 2, cfg.L, cfg.N)
+    for _ in range(max(1, args.warmup)):
+        ctx.expand(keys, c, packed, cfg.m, out=out, stream=stream)
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(max(3, args.steps)):
+        a = time.perf_counter()
+        ctx.expand(keys, c, packed, cfg.m, out=out, stream=stream)
+        torch.cuda.synchronize()
+        per.append(time.perf_counter() - a)
+    for k in keys:
+        k.close()
+    log(f"expansion c={c} h={h} m={cfg.m}: {np.median(per) * 1e3:.2f} ms")
+    return {"c": c, "packed_ciphertexts": h, "m": cfg.m, "substitutions": h * ((1 << c) - 1),
+            "ms_median": float(np.median(per) * 1e3), "ms_p99": float(np.percentile(per, 99) * 1e3)}
 
 
 # --------------------------------------------------------------------------------------------
@@ -381,5 +461,80 @@ def serve_bench(args, torch):
     return res
 
 
+# --------------------------------------------------------------------------------------------
+# Counter summary: rocprofv3 FETCH_SIZE / WRITE_SIZE passes -> calibrated HBM bytes per launch
+# --------------------------------------------------------------------------------------------
+FAMILY_OF_KERNEL = [("k_relin", "relin"), ("k_ntt_inv_tensor", "ntt_inv_tensor"), ("k_scale_fix", None),
+                    ("k_scale", "scale"), ("k_accumulate", "accumulate"), ("k_ntt_payload", "payload_ntt"),
+                    ("copyBuffer", "copy")]
+
+
+def summarize_traffic(fetch_csv, write_csv, copy_mib, workload, n, batch, schedule, out_json):
+    """Per kernel family and grid size: average FETCH_SIZE and WRITE_SIZE (KiB per dispatch), each
+    scaled by the factor that makes the same counter read the known size of the plain device copy
+    kernels of the run (copy_mib MiB per copy, split over its dispatches), for the grid size with
+    the most dispatches of each family."""
+    import collections
+    import csv
+    import hashlib
+
+    def family(name):
+        for key, fam in FAMILY_OF_KERNEL:
+            if key in name:
+                return fam
+        return None
+
+    def per_dispatch(path, counter):
+        vals = collections.defaultdict(float)
+        meta = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            fam = family(r["Kernel_Name"])
+            if fam:
+                d = r["Dispatch_Id"]
+                vals[d] += float(r["Counter_Value"])
+                meta[d] = (fam, int(r["Grid_Size"]))
+        groups = collections.defaultdict(list)
+        for d, v in vals.items():
+            groups[meta[d]].append(v)
+        return groups
+
+    fetch, write = per_dispatch(fetch_csv, "FETCH_SIZE"), per_dispatch(write_csv, "WRITE_SIZE")
+    copies = [max((k for k in fetch if k[0] == "copy"), key=lambda k: k[1])]  # the calibration copies
+    ncopy = sum(len(fetch[k]) for k in copies)
+    copy_kib = copy_mib * 1024 * 3 / ncopy  # three copies of copy_mib MiB in the run
+    f_factor = copy_kib / (sum(sum(fetch[k]) for k in copies) / ncopy)
+    w_factor = copy_kib / (sum(sum(write[k]) for k in copies) / ncopy)
+    fams = {}
+    for fam in sorted({k[0] for k in fetch if k[0] != "copy"}):
+        grid = max((k for k in fetch if k[0] == fam), key=lambda k: len(fetch[k]))
+        fk = sum(fetch[grid]) / len(fetch[grid])
+        wk = sum(write.get(grid, [0.0])) / max(1, len(write.get(grid, [])))
+        fams[fam] = {"grid_size": grid[1], "dispatches": len(fetch[grid]), "fetch_kib_raw": fk, "write_kib_raw": wk,
+                     "bytes_per_launch": (fk * f_factor + wk * w_factor) * 1024}
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(f, "rb").read())
+    data = {"kernel_source_sha256": h.hexdigest(), "workload": workload, "n": n, "batch": batch,
+            "schedule": schedule, "fetch_factor": f_factor, "write_factor": w_factor, "families": fams}
+    with open(out_json, "w") as f:
+        json.dump(data, f, indent=1)
+    print(f"calibration: fetch x{f_factor:.3f}, write x{w_factor:.3f} ({ncopy} copy dispatches)")
+    print("| Kernel family | Grid | Dispatches | FETCH_SIZE KiB/dispatch (raw) | WRITE_SIZE KiB/dispatch (raw) "
+          "| HBM MB/launch (calibrated) |")
+    print("|---|---|---|---|---|---|")
+    for fam, v in fams.items():
+        print(f"| `{fam}` | {v['grid_size']} | {v['dispatches']} | {v['fetch_kib_raw']:,.0f} | {v['write_kib_raw']:,.0f} "
+              f"| {v['bytes_per_launch'] / 1e6:,.0f} |")
+
+
 if __name__ == "__main__":
-    main()
+    if len(sys.argv) > 1 and sys.argv[1] == "--summarize-traffic":
+        # bench.py --summarize-traffic FETCH_CSV WRITE_CSV COPY_MIB WORKLOAD N BATCH CHUNK,QG,RG OUT_JSON
+        a = sys.argv[2:]
+        ch, qg, rg = (int(x) for x in a[6].split(","))
+        summarize_traffic(a[0], a[1], int(a[2]), a[3], int(a[4]), int(a[5]),
+                          {"chunk_elems": ch, "query_group": qg, "relin_group": rg}, a[7])
+    else:
+        main()

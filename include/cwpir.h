@@ -147,6 +147,36 @@ int pir_serve_stats(pir_server* srv, uint64_t* rounds, uint64_t* admitted, uint6
                     uint32_t* active, uint32_t* pending);
 void pir_serve_close(pir_server* srv);
 
+/* Query expansion (Section 3.3.3 "Query Expansion", Algorithm 5), for queries packed by the client
+ * with compression factor c (Algorithm 4: h = ceil(m / 2^c) ciphertexts, ciphertext j encrypting
+ * sum_i 2^-c E_q[j 2^c + i] x^i).
+ *   pir_load_galois_key  load a key switching from s(x^g) to s, layout as the relinearization key
+ *                        ([L digits][2][L][N], digit i holds b_i = -a_i s + e_i + g_i s(x^g), a_i);
+ *                        g odd in (1, 2N).  Synchronous.
+ *   pir_expand           packed (dev [h][2][L][N]) -> query (dev [m][2][L][N]): the first m of the
+ *                        h 2^c ciphertexts of Algorithm 5, ciphertext j 2^c + b being slot b of
+ *                        packed ciphertext j.  gkeys[a] (a < c) is the Galois key of
+ *                        g = N / 2^a + 1.  Sub_g is the automorphism x -> x^g followed by the key
+ *                        switch with per-limb digits [.]_{q_i} of the relinearization path.  The
+ *                        output is a c = 0 query for pir_answer.  Asynchronous. */
+int pir_load_galois_key(pir_ctx* ctx, uint32_t galois_elt, const uint64_t* gk, pir_key** out);
+int pir_expand(pir_ctx* ctx, const pir_key* const* gkeys, uint32_t c, const uint64_t* packed, uint32_t h, uint32_t m,
+               uint64_t* query, void* stream);
+
+/* Captured answers (HIP graphs), for callers that answer many queries of the same shape, e.g. a
+ * serving loop with fixed query and answer slots.  pir_graph_capture runs pir_answer_batch once
+ * for the given arguments (the answers for the queries' current contents are written) and records
+ * its whole launch sequence into a HIP graph with work buffers of its own.  pir_graph_launch
+ * replays it on `stream`, answering whatever the query buffers hold when the replay runs; it is
+ * ordered after the context's other asynchronous calls like pir_answer.  Keys, databases, query
+ * and answer buffers named at capture must outlive the graph; free graphs before their context.
+ * While a graph exists the context's schedule is fixed.  pir_graph_capture is synchronous. */
+typedef struct pir_graph pir_graph;
+int pir_graph_capture(pir_ctx* ctx, uint32_t B, const pir_key* const* keys, const pir_db* const* dbs,
+                      const uint64_t* const* queries, uint64_t* const* answers, pir_graph** out);
+int pir_graph_launch(pir_graph* graph, void* stream);
+void pir_graph_free(pir_graph* graph);
+
 /* FV operations on single ciphertexts (Section 2.1.1: Multiplication, Plain multiplication), the
  * building blocks of the path, exposed for checking.  All pointers dev; asynchronous.
  *   pir_mult      a, b [2][L][N] -> out [3][L][N]    (textbook Mult, no relinearization)
@@ -171,6 +201,38 @@ int pir_map_perfect(pir_ctx* ctx, const uint64_t* ids, uint64_t n, uint32_t m, u
                     void* stream);
 int pir_map_lossy(pir_ctx* ctx, const uint64_t* keywords, uint64_t n, uint32_t m, uint32_t k, uint64_t seed,
                   uint32_t* out, void* stream);
+
+/* Launch schedule and its autotuner.  A schedule fixes how the path is cut into launches, never
+ * what it computes (every schedule gives bit-identical answers):
+ *   chunk_elems  elements per chunk (selector launches and payload transform), 1..4096
+ *   query_group  queries whose selectors share one launch per stage, 1..8
+ *   relin_group  order of the key-switching workgroups: 0 = the L output limbs of an element
+ *                side by side on one XCD (they read the same digit rows); G > 0 = blocks of G
+ *                elements, limb-major inside a block (workgroups running together read the same
+ *                key limb).  N = 16384 stages its key switch and ignores it.
+ *   ns_per_elem  measured time per element and query (output of the tuner; ignored on input)
+ * The schedule is per context and can change only while no database is encoded (PIR_E_INVALID
+ * otherwise).
+ *   pir_get_schedule  current schedule.
+ *   pir_set_schedule  apply a schedule (e.g. one tuned earlier for the same N, L, batch and k).
+ *   pir_autotune      time candidate schedules for `batch` queries per call on one database of
+ *                     weight-k codewords and s plaintexts per element, on synthetic inputs of the
+ *                     context's parameters (a grid over chunk and query group, then the
+ *                     key-switch order at the best pair); apply the fastest and write it to *best (may be NULL).
+ *                     records[0..max_records) receive the measured candidates in order (may be
+ *                     NULL).  Candidates that do not fit the HBM budget are skipped.  Returns the
+ *                     number of candidates measured, or an error.  Synchronous; the library's work
+ *                     buffers are released afterwards. */
+typedef struct {
+    uint32_t chunk_elems;
+    uint32_t query_group;
+    uint32_t relin_group;
+    double ns_per_elem;
+} pir_schedule;
+int pir_get_schedule(pir_ctx* ctx, pir_schedule* out);
+int pir_set_schedule(pir_ctx* ctx, const pir_schedule* schedule);
+int pir_autotune(pir_ctx* ctx, uint32_t batch, uint32_t k, uint32_t s, pir_schedule* records, uint32_t max_records,
+                 pir_schedule* best);
 
 /* Introspection. */
 uint32_t pir_ctx_aux_primes(const pir_ctx* ctx, uint64_t* out_primes /* may be NULL */);

@@ -5,4 +5,4 @@ codeword query, the selection vector by the plain constant-weight equality opera
 product with the database (Mahdavi and Kerschbaum, arXiv 2202.07569, Sections 3.1 and 3.3).
 This package holds its HIP sources (csrc/), the build step and a ctypes binding.
 """
-from .binding import Context, Database, Key, PirError, Server, lib, library_path  # noqa: F401
+from .binding import Context, Database, Graph, Key, PirError, Server, lib, library_path  # noqa: F401

@@ -21,7 +21,8 @@ EXPORTS = [
     "pir_pm", "pir_selectors", "pir_map_perfect", "pir_map_lossy", "pir_ctx_aux_primes", "pir_ctx_device_bytes",
     "pir_db_pair_count", "pir_profile_enable", "pir_profile_read", "pir_db_free", "pir_key_free", "pir_free",
     "pir_last_error", "pir_serve_open", "pir_serve_submit", "pir_serve_step", "pir_serve_poll", "pir_serve_stats",
-    "pir_serve_close",
+    "pir_serve_close", "pir_get_schedule", "pir_set_schedule", "pir_autotune", "pir_graph_capture",
+    "pir_graph_launch", "pir_graph_free", "pir_load_galois_key", "pir_expand",
 ]
 
 
@@ -35,6 +36,15 @@ class _Params(ctypes.Structure):
     _fields_ = [("N", ctypes.c_uint32), ("L", ctypes.c_uint32), ("q", ctypes.POINTER(ctypes.c_uint64)),
                 ("t", ctypes.c_uint64), ("hbm_budget_bytes", ctypes.c_uint64), ("device", ctypes.c_int32),
                 ("chunk_elems", ctypes.c_uint32), ("memo_bytes", ctypes.c_uint64)]
+
+
+class _Schedule(ctypes.Structure):
+    _fields_ = [("chunk_elems", ctypes.c_uint32), ("query_group", ctypes.c_uint32), ("relin_group", ctypes.c_uint32),
+                ("ns_per_elem", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        return {"chunk_elems": self.chunk_elems, "query_group": self.query_group, "relin_group": self.relin_group,
+                "ns_per_elem": self.ns_per_elem}
 
 
 _lib = None
@@ -83,6 +93,14 @@ def lib():
                                       ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32),
                                       ctypes.POINTER(ctypes.c_uint32)]),
             "pir_serve_close": (None, [vp]),
+            "pir_get_schedule": (i32, [vp, ctypes.POINTER(_Schedule)]),
+            "pir_set_schedule": (i32, [vp, ctypes.POINTER(_Schedule)]),
+            "pir_autotune": (i32, [vp, u32, u32, u32, ctypes.POINTER(_Schedule), u32, ctypes.POINTER(_Schedule)]),
+            "pir_graph_capture": (i32, [vp, u32, pp, pp, pp, pp, pp]),
+            "pir_graph_launch": (i32, [vp, vp]),
+            "pir_graph_free": (None, [vp]),
+            "pir_load_galois_key": (i32, [vp, u32, vp, pp]),
+            "pir_expand": (i32, [vp, pp, u32, vp, u32, u32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -201,11 +219,52 @@ class Context:
     def device_bytes(self) -> int:
         return lib().pir_ctx_device_bytes(self._h)
 
+    def schedule(self) -> dict:
+        out = _Schedule()
+        _check(lib().pir_get_schedule(self._h, ctypes.byref(out)))
+        return out.as_dict()
+
+    def set_schedule(self, chunk_elems: int, query_group: int, relin_group: int = 0):
+        x = _Schedule(chunk_elems, query_group, relin_group, 0.0)
+        _check(lib().pir_set_schedule(self._h, ctypes.byref(x)))
+
+    def autotune(self, batch: int = 8, k: int = 4, s: int = 1) -> dict:
+        """Time candidate launch schedules on synthetic inputs and apply the fastest (before any
+        database is encoded).  Returns {"best": schedule, "candidates": [schedule, ...]}."""
+        recs = (_Schedule * 64)()
+        best = _Schedule()
+        rc = lib().pir_autotune(self._h, batch, k, s, recs, 64, ctypes.byref(best))
+        if rc < 0:
+            _check(rc)
+        return {"best": best.as_dict(), "candidates": [recs[i].as_dict() for i in range(min(rc, 64))]}
+
+    def cached_schedule(self, batch: int, k: int, s: int):
+        """The schedule the autotuner chose earlier for these parameters and call shape, from the
+        package's tuning cache (schedules.json), or None."""
+        return lookup_schedule(self.N, self.primes, batch, k, s)
+
     def empty(self, *shape, dtype=None):
         torch = _torch()
         return torch.empty(shape, dtype=dtype or torch.uint64, device=self.device)
 
     # ---- Setup ----
+    def load_galois_key(self, g: int, gk) -> Key:
+        gk = _dev_u64(gk, self.device)
+        assert tuple(gk.shape) == (self.L, 2, self.L, self.N)
+        h = ctypes.c_void_p()
+        _check(lib().pir_load_galois_key(self._h, int(g), _ptr(gk), ctypes.byref(h)))
+        return Key(self, h)
+
+    def expand(self, gkeys, c: int, packed, m: int, out=None, stream=None):
+        """Algorithm 5: packed [h][2][L][N] -> query [m][2][L][N]; gkeys[a] for g = N/2^a + 1."""
+        packed = _dev_u64(packed, self.device)
+        h = packed.shape[0]
+        if out is None:
+            out = self.empty(m, 2, self.L, self.N)
+        arr = (ctypes.c_void_p * max(1, c))(*([k._h.value for k in gkeys[:c]] or [None]))
+        _check(lib().pir_expand(self._h, arr, c, _ptr(packed), h, m, _ptr(out), _stream(stream)))
+        return out
+
     def load_key(self, rlk) -> Key:
         rlk = _dev_u64(rlk, self.device)
         assert tuple(rlk.shape) == (self.L, 2, self.L, self.N)
@@ -246,6 +305,22 @@ class Context:
                                       arr([q.data_ptr() for q in queries]), arr([o.data_ptr() for o in outs]),
                                       _stream(stream)))
         return outs
+
+    def capture(self, keys, dbs, queries, outs=None) -> "Graph":
+        """Record pir_answer_batch for these buffers into a HIP graph (see Graph).  queries must be
+        device tensors; they and outs are held by the graph and answered at every replay."""
+        B = len(queries)
+        for q in queries:
+            if not (hasattr(q, "is_cuda") and q.is_cuda and q.is_contiguous()):
+                raise TypeError("captured queries must be contiguous device tensors")
+        if outs is None:
+            outs = [self.empty(db.s, 2, self.L, self.N) for db in dbs]
+        arr = lambda xs: (ctypes.c_void_p * B)(*xs)  # noqa: E731
+        h = ctypes.c_void_p()
+        _check(lib().pir_graph_capture(self._h, B, arr([k._h.value for k in keys]), arr([d._h.value for d in dbs]),
+                                       arr([q.data_ptr() for q in queries]), arr([o.data_ptr() for o in outs]),
+                                       ctypes.byref(h)))
+        return Graph(self, h, list(keys), list(dbs), list(queries), outs)
 
     def selectors(self, key: Key, db: Database, query, elems, out=None, stream=None):
         query = _dev_u64(query, self.device)
@@ -308,6 +383,61 @@ class Context:
         if n < 0:
             _check(n)
         return {names[i].decode(): (ms[i], int(cnt[i]), work[i]) for i in range(min(n, cap))}
+
+
+SCHEDULE_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "schedules.json")
+
+
+def _schedule_key(N, primes, batch, k, s):
+    return {"N": int(N), "primes": [int(p) for p in primes], "batch": int(batch), "k": int(k), "s": int(s)}
+
+
+def lookup_schedule(N, primes, batch, k, s, path=SCHEDULE_CACHE):
+    """Tuning cache lookup: {"chunk_elems", "query_group", "relin_group", ...} or None."""
+    import json
+    if not os.path.exists(path):
+        return None
+    key = _schedule_key(N, primes, batch, k, s)
+    for e in json.load(open(path)).get("entries", []):
+        if {kk: e.get(kk) for kk in key} == key:
+            return e["schedule"]
+    return None
+
+
+def record_schedule(N, primes, batch, k, s, schedule, note, path=SCHEDULE_CACHE):
+    """Add or replace a tuning-cache entry."""
+    import json
+    data = json.load(open(path)) if os.path.exists(path) else {"entries": []}
+    key = _schedule_key(N, primes, batch, k, s)
+    data["entries"] = [e for e in data["entries"] if {kk: e.get(kk) for kk in key} != key]
+    data["entries"].append({**key, "schedule": schedule, "note": note})
+    with open(path, "w") as f:
+        json.dump(data, f, indent=1)
+
+
+class Graph:
+    """A captured answer: launch() replays the recorded pir_answer_batch, answering what the captured
+    query tensors hold at that time into the captured output tensors (self.outs)."""
+
+    def __init__(self, ctx: Context, handle, keys, dbs, queries, outs):
+        self.ctx, self._h = ctx, handle
+        self._keep = (keys, dbs, queries)  # must outlive the graph
+        self.queries, self.outs = queries, outs
+
+    def launch(self, stream=None):
+        _check(lib().pir_graph_launch(self._h, _stream(stream)))
+        return self.outs
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().pir_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Server:

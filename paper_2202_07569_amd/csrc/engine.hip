@@ -64,6 +64,10 @@ struct pir_ctx {
     uint32_t* dfixcnt = nullptr;
     size_t fix_cap = 0;
     uint32_t chunk = 0;  // elements per chunk
+    uint32_t qb = cw::MAX_QB;     // queries per selector launch
+    uint32_t relin_group = 0;     // key-switch workgroup order (Launch::relin_group)
+    uint32_t live_dbs = 0;        // encoded databases not yet freed
+    uint32_t live_graphs = 0;     // captured answers not yet freed
     uint32_t cus = 0;    // compute units
     uint64_t memo_cap = 0;
     std::map<std::string, DevBuf> ws;
@@ -80,6 +84,7 @@ struct pir_ctx {
 
 struct pir_key {
     pir_ctx* ctx = nullptr;
+    uint32_t galois = 0;    // 0: relinearization key; g: key switching from s(x^g) to s
     uint64_t* d = nullptr;  // [L][2][L][N] transformed, then [L][2][L][N] Shoup companions
     size_t bytes = 0;
 };
@@ -101,6 +106,7 @@ struct pir_db {
     uint32_t max_pairs = 0;
     uint64_t total_pairs = 0;
     size_t pay_bytes = 0, pairs_bytes = 0, refs_bytes = 0;
+    bool live = false;           // counted in ctx->live_dbs
 };
 
 // ------------------------------------------------------------------------------------------------
@@ -185,6 +191,7 @@ static Launch make_launch(pir_ctx* ctx, hipStream_t st) {
     lc.LB = ctx->LB;
     lc.LL = ctx->LL;
     lc.cus = ctx->cus;
+    lc.relin_group = ctx->relin_group;
     lc.fix = ctx->dfix;
     lc.fixcnt = ctx->dfixcnt;
     return lc;
@@ -566,6 +573,8 @@ extern "C" int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, u
         ctx->poisoned = true;
         return fail(PIR_E_DEVICE, "database upload failed");
     }
+    db->live = true;
+    ++ctx->live_dbs;
     *out = db;
     return PIR_OK;
 }
@@ -579,6 +588,7 @@ extern "C" void pir_db_free(pir_db* db) {
     dev_free(ctx, db->dpay, db->pay_bytes);
     dev_free(ctx, db->dpairs, db->pairs_bytes);
     dev_free(ctx, db->drefs, db->refs_bytes);
+    if (db->live) --ctx->live_dbs;
     delete db;
 }
 
@@ -725,9 +735,9 @@ static int chunk_step(pir_ctx* ctx, const Launch& lc, const Bufs& b, const pir_d
             make_nodes(ctx, lc, b, db->dpairs + 2 * (size_t)db->groups[c].p0, db->groups[c].np, qs[q]->QX, qs[q]->key,
                        qs[q]->sel, qs[q]->nodes, E);
     const uint32_t* refs = db->drefs + 2 * e0;
-    for (uint32_t q0 = 0; q0 < nq; q0 += cw::MAX_QB) {
+    for (uint32_t q0 = 0; q0 < nq; q0 += ctx->qb) {
         cw::Batch bt{};
-        bt.nq = std::min<uint32_t>(cw::MAX_QB, nq - q0);
+        bt.nq = std::min<uint32_t>(ctx->qb, nq - q0);
         bt.E = cnt;
         for (uint32_t q = 0; q < bt.nq; ++q) {
             const QState* x = qs[q0 + q];
@@ -767,7 +777,7 @@ static int answer_same_db(pir_ctx* ctx, hipStream_t st, const pir_db* db, uint32
     const uint32_t E = ctx->chunk;
     Launch lc = make_launch(ctx, st);
     Bufs b;
-    CW_TRY(get_bufs(ctx, E, std::min<uint32_t>(B, cw::MAX_QB), db->s, b));
+    CW_TRY(get_bufs(ctx, E, std::min<uint32_t>(B, ctx->qb), db->s, b));
     uint64_t *QX, *nodes = nullptr, *sel;
     const size_t qx_one = qx_words(ctx, db), node_one = node_words(ctx, db), sel_one = sel_words(ctx);
     CW_TRY(ws_get_t(ctx, "QX", qx_one * B, &QX));
@@ -792,18 +802,35 @@ static int answer_same_db(pir_ctx* ctx, hipStream_t st, const pir_db* db, uint32
     return PIR_OK;
 }
 
-extern "C" int pir_answer_batch(pir_ctx* ctx, uint32_t B, const pir_key* const* keys, const pir_db* const* dbs,
-                                const uint64_t* const* queries, uint64_t* const* answers, void* stream) {
-    CW_ENTER(ctx);
-    if (B == 0) return PIR_OK;
+static int answer_dbs(pir_ctx* ctx, hipStream_t st, uint32_t B, const pir_key* const* keys, const pir_db* const* dbs,
+                      const uint64_t* const* queries, uint64_t* const* answers);
+
+static int check_batch(pir_ctx* ctx, uint32_t B, const pir_key* const* keys, const pir_db* const* dbs,
+                       const uint64_t* const* queries, uint64_t* const* answers) {
     if (!keys || !dbs || !queries || !answers) return fail(PIR_E_INVALID, "null argument");
     for (uint32_t q = 0; q < B; ++q) {
         if (!keys[q] || !dbs[q] || !queries[q] || !answers[q]) return fail(PIR_E_INVALID, "null argument");
         if (keys[q]->ctx != ctx || dbs[q]->ctx != ctx) return fail(PIR_E_INVALID, "handle from another context");
+        if (keys[q]->galois) return fail(PIR_E_INVALID, "a Galois key is not a relinearization key");
     }
+    return PIR_OK;
+}
+
+extern "C" int pir_answer_batch(pir_ctx* ctx, uint32_t B, const pir_key* const* keys, const pir_db* const* dbs,
+                                const uint64_t* const* queries, uint64_t* const* answers, void* stream) {
+    CW_ENTER(ctx);
+    if (B == 0) return PIR_OK;
+    CW_TRY(check_batch(ctx, B, keys, dbs, queries, answers));
     hipStream_t st = (hipStream_t)stream;
     CW_TRY(begin_async(ctx, st));
-    // queries on the same database share its payload scan; databases run in first-seen order
+    CW_TRY(answer_dbs(ctx, st, B, keys, dbs, queries, answers));
+    return end_async(ctx, st);
+}
+
+// B queries: queries on the same database share its payload scan; databases run in first-seen
+// order.  Enqueues only (no host synchronisation), so it can be captured into a graph.
+static int answer_dbs(pir_ctx* ctx, hipStream_t st, uint32_t B, const pir_key* const* keys, const pir_db* const* dbs,
+                      const uint64_t* const* queries, uint64_t* const* answers) {
     std::vector<const pir_db*> order;
     for (uint32_t q = 0; q < B; ++q)
         if (std::find(order.begin(), order.end(), dbs[q]) == order.end()) order.push_back(dbs[q]);
@@ -819,7 +846,7 @@ extern "C" int pir_answer_batch(pir_ctx* ctx, uint32_t B, const pir_key* const* 
             }
         CW_TRY(answer_same_db(ctx, st, db, (uint32_t)ks.size(), ks.data(), qs.data(), as.data()));
     }
-    return end_async(ctx, st);
+    return PIR_OK;
 }
 
 extern "C" int pir_answer(pir_ctx* ctx, const pir_key* key, const pir_db* db, const uint64_t* query, uint64_t* answer,
@@ -1010,7 +1037,7 @@ extern "C" int pir_serve_step(pir_server* srv) {
         if (sl.used) max_s = std::max(max_s, sl.db->s);
     for (const ServeReq& r : srv->pending) max_s = std::max(max_s, r.db->s);
     Bufs b;
-    CW_TRY(get_bufs(ctx, ctx->chunk, cw::MAX_QB, max_s, b));
+    CW_TRY(get_bufs(ctx, ctx->chunk, ctx->qb, max_s, b));
     CW_TRY(serve_admit(srv, lc, b));
     // one round: every database with active queries advances by one chunk
     std::vector<const pir_db*> dbs;
@@ -1231,4 +1258,412 @@ extern "C" int pir_profile_read(pir_ctx* ctx, uint32_t max, const char** names, 
     }
     if (reset) ctx->prof_acc.clear();
     return (int)i;
+}
+
+// ------------------------------------------------------------------------------------------------
+// schedule autotuner
+//
+// The schedule decides how the work is cut into launches, never what is computed: elements per
+// chunk, queries per selector launch, and the order of the key-switch workgroups.  pir_autotune
+// times candidate schedules on synthetic inputs of the context's own parameters (uniform residues,
+// uniform uint16 payload, the first n weight-k subsets in lexicographic order) and keeps the
+// fastest: a grid over (chunk, query group), then the workgroup order at the best pair.
+// ------------------------------------------------------------------------------------------------
+namespace {
+struct TuneMix {  // SplitMix64 (Steele, Lea and Flood 2014) for the tuner's synthetic inputs
+    uint64_t z;
+    uint64_t next() {
+        uint64_t x = (z += 0x9E3779B97F4A7C15ull);
+        x = (x ^ (x >> 30)) * 0xBF58476D1CE4E5B9ull;
+        x = (x ^ (x >> 27)) * 0x94D049BB133111EBull;
+        return x ^ (x >> 31);
+    }
+};
+
+uint64_t binom_u64(uint32_t m, uint32_t k) {
+    if (k > m) return 0;
+    unsigned __int128 r = 1;
+    for (uint32_t i = 1; i <= k; ++i) r = r * (m - k + i) / i;
+    return r > ~0ull ? ~0ull : (uint64_t)r;
+}
+
+// rows [rows][L][N] of uniform residues mod q_j (row r uses prime r mod L)
+void uniform_rows(TuneMix& g, const std::vector<uint64_t>& q, size_t rows, uint32_t N, std::vector<uint64_t>& out) {
+    const size_t L = q.size();
+    out.resize(rows * L * N);
+    for (size_t r = 0; r < rows * L; ++r)
+        for (uint32_t c = 0; c < N; ++c) out[r * N + c] = g.next() % q[r % L];
+}
+}  // namespace
+
+static void schedule_of(const pir_ctx* ctx, pir_schedule* s, double ns) {
+    s->chunk_elems = ctx->chunk;
+    s->query_group = ctx->qb;
+    s->relin_group = ctx->relin_group;
+    s->ns_per_elem = ns;
+}
+
+// Fixup-list capacity for launches of the current schedule.
+static int ensure_fix(pir_ctx* ctx) {
+    const size_t need = (size_t)3 * ctx->chunk * ctx->N * ctx->qb;
+    if (ctx->fix_cap >= need) return PIR_OK;
+    CW_HIP(ctx, hipDeviceSynchronize());
+    dev_free(ctx, ctx->dfix, ctx->fix_cap * 8);
+    ctx->dfix = nullptr;
+    ctx->fix_cap = 0;
+    CW_TRY(dev_alloc(ctx, (void**)&ctx->dfix, need * 8));
+    ctx->fix_cap = need;
+    return PIR_OK;
+}
+
+static int check_schedule(const pir_ctx* ctx, const pir_schedule* s) {
+    if (s->chunk_elems < 1 || s->chunk_elems > 4096) return fail(PIR_E_INVALID, "chunk_elems must be in [1, 4096]");
+    if (s->query_group < 1 || s->query_group > (uint32_t)cw::MAX_QB)
+        return fail(PIR_E_INVALID, "query_group must be in [1, 8]");
+    if (s->relin_group > 4096) return fail(PIR_E_INVALID, "relin_group must be <= 4096");
+    if (ctx->live_dbs || ctx->live_graphs)
+        return fail(PIR_E_INVALID, "the schedule is fixed once a database is encoded");
+    return PIR_OK;
+}
+
+extern "C" int pir_get_schedule(pir_ctx* ctx, pir_schedule* out) {
+    CW_ENTER(ctx);
+    if (!out) return fail(PIR_E_INVALID, "null argument");
+    schedule_of(ctx, out, 0.0);
+    return PIR_OK;
+}
+
+extern "C" int pir_set_schedule(pir_ctx* ctx, const pir_schedule* s) {
+    CW_ENTER(ctx);
+    if (!s) return fail(PIR_E_INVALID, "null argument");
+    CW_TRY(check_schedule(ctx, s));
+    ctx->chunk = s->chunk_elems;
+    ctx->qb = s->query_group;
+    ctx->relin_group = s->relin_group;
+    return ensure_fix(ctx);
+}
+
+extern "C" int pir_autotune(pir_ctx* ctx, uint32_t batch, uint32_t k, uint32_t s, pir_schedule* records,
+                            uint32_t max_records, pir_schedule* best) {
+    CW_ENTER(ctx);
+    if (batch < 1 || batch > 64) return fail(PIR_E_INVALID, "batch must be in [1, 64]");
+    if (k < 1 || k > PIR_MAX_K) return fail(PIR_E_INVALID, "k must be in [1, 4]");
+    if (s < 1 || s > 8) return fail(PIR_E_INVALID, "s must be in [1, 8]");
+    if (ctx->live_dbs || ctx->live_graphs) return fail(PIR_E_INVALID, "autotune runs before any database is encoded");
+    CW_HIP(ctx, hipSetDevice(ctx->device));
+    const uint32_t N = ctx->N, L = ctx->L;
+    const std::vector<uint64_t> q(ctx->primes.begin(), ctx->primes.begin() + L);
+    const std::vector<uint32_t> chunks = N >= 16384 ? std::vector<uint32_t>{32, 64, 128, 256}
+                                                    : std::vector<uint32_t>{64, 128, 256, 512};
+    // synthetic database: n elements, the first n weight-k subsets of the smallest m that has them
+    const uint64_t n = k == 1 ? 256 : (uint64_t)chunks.back() * 4;
+    uint32_t m = k;
+    while (binom_u64(m, k) < n) ++m;
+    std::vector<uint32_t> cw((size_t)n * k);
+    {
+        std::vector<uint32_t> c(k);
+        for (uint32_t i = 0; i < k; ++i) c[i] = i;
+        for (uint64_t e = 0; e < n; ++e) {
+            std::memcpy(&cw[(size_t)e * k], c.data(), (size_t)k * 4);
+            int i = (int)k - 1;  // next subset in lexicographic order
+            while (i >= 0 && c[i] == m - k + (uint32_t)i) --i;
+            if (i < 0) break;
+            ++c[i];
+            for (uint32_t j = (uint32_t)i + 1; j < k; ++j) c[j] = c[j - 1] + 1;
+        }
+    }
+    TuneMix g{0x5EEDull ^ ((uint64_t)N << 32) ^ L};
+    std::vector<uint16_t> pay((size_t)n * s * N);
+    for (auto& x : pay) x = (uint16_t)g.next();
+    std::vector<uint64_t> host;
+    uniform_rows(g, q, (size_t)L * 2, N, host);
+    pir_key* key = nullptr;
+    CW_TRY(pir_load_key(ctx, host.data(), &key));
+    const size_t qw = (size_t)m * 2 * L * N, aw = (size_t)s * 2 * L * N;
+    uint64_t *dq = nullptr, *da = nullptr;
+    int rc = dev_alloc(ctx, (void**)&dq, qw * 8 * batch);
+    if (rc == PIR_OK) rc = dev_alloc(ctx, (void**)&da, aw * 8 * batch);
+    for (uint32_t b = 0; rc == PIR_OK && b < batch; ++b) {
+        uniform_rows(g, q, (size_t)m * 2, N, host);
+        if (hipMemcpy(dq + b * qw, host.data(), qw * 8, hipMemcpyHostToDevice) != hipSuccess) {
+            ctx->poisoned = true;
+            rc = fail(PIR_E_DEVICE, "tuning input upload failed");
+        }
+    }
+    hipStream_t st = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (rc == PIR_OK && (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess ||
+                         hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) {
+        ctx->poisoned = true;
+        rc = fail(PIR_E_DEVICE, "tuning stream setup failed");
+    }
+    std::vector<const pir_key*> keys(batch, key);
+    std::vector<const uint64_t*> qs(batch);
+    std::vector<uint64_t*> as(batch);
+    for (uint32_t b = 0; b < batch; ++b) {
+        qs[b] = dq + b * qw;
+        as[b] = da + b * aw;
+    }
+    const pir_schedule start{ctx->chunk, ctx->qb, ctx->relin_group, 0.0};
+    pir_schedule cur{ctx->chunk, 1, 0, 0.0};
+    pir_schedule top{0, 0, 0, 0.0};
+    uint32_t nrec = 0;
+    pir_db* db = nullptr;
+    uint32_t db_chunk = 0;
+    // ns per element-query of schedule x (1 warm-up, then the better of 2 timed runs)
+    auto measure = [&](const pir_schedule& x, double& ns) -> int {
+        ctx->chunk = x.chunk_elems;
+        ctx->qb = x.query_group;
+        ctx->relin_group = x.relin_group;
+        CW_TRY(ensure_fix(ctx));
+        if (!db || db_chunk != x.chunk_elems) {  // the element plan depends on the chunk
+            if (db) pir_db_free(db);
+            db = nullptr;
+            CW_TRY(pir_encode_db(ctx, n, s, m, k, cw.data(), pay.data(), &db));
+            db_chunk = x.chunk_elems;
+        }
+        double bestms = 1e30;
+        for (int r = 0; r < 3; ++r) {
+            CW_HIP(ctx, hipEventRecord(e0, st));
+            CW_TRY(answer_same_db(ctx, st, db, batch, keys.data(), qs.data(), as.data()));
+            CW_HIP(ctx, hipEventRecord(e1, st));
+            CW_HIP(ctx, hipEventSynchronize(e1));
+            float ms = 0.f;
+            CW_HIP(ctx, hipEventElapsedTime(&ms, e0, e1));
+            if (r > 0) bestms = std::min(bestms, (double)ms);
+        }
+        ns = bestms * 1e6 / ((double)n * batch);
+        return PIR_OK;
+    };
+    auto consider = [&](const pir_schedule& x) -> int {
+        double ns = 0.0;
+        const int r = measure(x, ns);
+        if (r == PIR_E_NOMEM) {  // does not fit the budget: skipped
+            g_err.clear();
+            return PIR_OK;
+        }
+        CW_TRY(r);
+        pir_schedule rec = x;
+        rec.ns_per_elem = ns;
+        if (records && nrec < max_records) records[nrec] = rec;
+        ++nrec;
+        if (top.chunk_elems == 0 || ns < top.ns_per_elem) top = rec;
+        return PIR_OK;
+    };
+    // the chunk and the query group trade off (both set the rows per launch): a joint grid, then
+    // the key-switch order at the best pair
+    if (rc == PIR_OK) {
+        for (uint32_t c : chunks) {
+            for (uint32_t w : {1u, 2u, 4u, 8u}) {
+                if (w > batch) continue;
+                cur.chunk_elems = c;
+                cur.query_group = w;
+                cur.relin_group = 0;
+                if ((rc = consider(cur)) != PIR_OK) break;
+            }
+            if (rc != PIR_OK) break;
+        }
+    }
+    if (rc == PIR_OK && top.chunk_elems && !cw::relin_needs_staging(ctx->logN)) {
+        cur = top;
+        for (uint32_t G : {8u, 32u, 128u}) {  // the incumbent has G = 0
+            cur.relin_group = G;
+            if ((rc = consider(cur)) != PIR_OK) break;
+        }
+    }
+    if (st) (void)hipStreamSynchronize(st);
+    if (db) pir_db_free(db);
+    pir_key_free(key);
+    dev_free(ctx, dq, qw * 8 * batch);
+    dev_free(ctx, da, aw * 8 * batch);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (st) (void)hipStreamDestroy(st);
+    for (auto& kv : ctx->ws) dev_free(ctx, kv.second.p, kv.second.bytes);  // sized for the largest trial
+    ctx->ws.clear();
+    const pir_schedule& use = (rc == PIR_OK && top.chunk_elems) ? top : start;
+    ctx->chunk = use.chunk_elems;
+    ctx->qb = use.query_group;
+    ctx->relin_group = use.relin_group;
+    if (rc != PIR_OK) return rc;
+    if (!top.chunk_elems) return fail(PIR_E_NOMEM, "no candidate schedule fits the HBM budget");
+    CW_TRY(ensure_fix(ctx));
+    if (best) *best = top;
+    return (int)nrec;
+}
+
+// ------------------------------------------------------------------------------------------------
+// captured answers (HIP graphs)
+//
+// pir_graph_capture records the whole launch sequence of one pir_answer_batch call into a HIP graph
+// with its own work buffers; pir_graph_launch replays it.  Every launch reads its inputs from
+// device memory at run time, so a replay answers whatever the query buffers hold then.  The path
+// clears its counters and accumulators with kernels, never with memset nodes.
+// ------------------------------------------------------------------------------------------------
+struct pir_graph {
+    pir_ctx* ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::map<std::string, DevBuf> ws;  // the graph's own work buffers
+};
+
+extern "C" void pir_graph_free(pir_graph* g) {
+    if (!g) return;
+    pir_ctx* ctx = g->ctx;
+    std::lock_guard<std::recursive_mutex> lock(ctx->mu);
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    for (auto& kv : g->ws) dev_free(ctx, kv.second.p, kv.second.bytes);
+    --ctx->live_graphs;
+    delete g;
+}
+
+extern "C" int pir_graph_capture(pir_ctx* ctx, uint32_t B, const pir_key* const* keys, const pir_db* const* dbs,
+                                 const uint64_t* const* queries, uint64_t* const* answers, pir_graph** out) {
+    CW_ENTER(ctx);
+    if (!out || B == 0) return fail(PIR_E_INVALID, "need an output handle and B >= 1");
+    *out = nullptr;
+    CW_TRY(check_batch(ctx, B, keys, dbs, queries, answers));
+    CW_HIP(ctx, hipSetDevice(ctx->device));
+    CW_HIP(ctx, hipDeviceSynchronize());
+    pir_graph* g = new pir_graph();
+    g->ctx = ctx;
+    ++ctx->live_graphs;
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) {
+        pir_graph_free(g);
+        ctx->poisoned = true;
+        return fail(PIR_E_DEVICE, "stream creation failed");
+    }
+    const bool prof = ctx->prof;
+    ctx->prof = false;
+    std::swap(ctx->ws, g->ws);
+    // an eager run sizes the graph's work buffers (nothing may be allocated while capturing) and
+    // leaves the current queries' answers in place
+    int rc = answer_dbs(ctx, st, B, keys, dbs, queries, answers);
+    if (rc == PIR_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(PIR_E_DEVICE, "warm-up run failed");
+    if (rc == PIR_OK) {
+        if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            rc = fail(PIR_E_DEVICE, "hipStreamBeginCapture failed");
+        } else {
+            rc = answer_dbs(ctx, st, B, keys, dbs, queries, answers);
+            hipGraph_t graph = nullptr;
+            const hipError_t e = hipStreamEndCapture(st, &graph);
+            g->graph = graph;
+            if (rc == PIR_OK && e != hipSuccess) rc = fail(PIR_E_DEVICE, "hipStreamEndCapture failed");
+            if (rc == PIR_OK && hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0) != hipSuccess)
+                rc = fail(PIR_E_DEVICE, "hipGraphInstantiate failed");
+        }
+    }
+    std::swap(ctx->ws, g->ws);
+    ctx->prof = prof;
+    (void)hipStreamSynchronize(st);
+    (void)hipStreamDestroy(st);
+    if (rc != PIR_OK) {
+        const std::string msg = g_err;
+        if (rc == PIR_E_DEVICE) ctx->poisoned = true;
+        pir_graph_free(g);
+        return fail(rc, msg);
+    }
+    *out = g;
+    return PIR_OK;
+}
+
+extern "C" int pir_graph_launch(pir_graph* g, void* stream) {
+    if (!g) return fail(PIR_E_INVALID, "null graph");
+    pir_ctx* ctx = g->ctx;
+    CW_ENTER(ctx);
+    hipStream_t st = (hipStream_t)stream;
+    CW_TRY(begin_async(ctx, st));
+    CW_HIP(ctx, hipGraphLaunch(g->exec, st));
+    return end_async(ctx, st);
+}
+
+// ------------------------------------------------------------------------------------------------
+// query expansion (Section 3.3.3 "Query Expansion", Algorithm 5)
+//
+// Level a of c turns slots b < 2^a of every packed ciphertext into slots b and b + 2^a:
+//   c0 = Sub_g(cts[b]) with g = N / 2^a + 1;  cts[b] += c0;  cts[b + 2^a] = x^(-2^a) (cts[b] - c0)
+// (the same value as x^(-2^a) cts[b] - x^(-2^a) c0).  Sub_g is the automorphism followed by the key
+// switch of the relinearization path: the three-polynomial input (sigma(c0), 0, sigma(c1)) under
+// the Galois key, transformed back to coefficient form.  All h 2^a substitutions of a level run in
+// one launch per stage.  Ciphertexts live in two ping-pong buffers.
+// ------------------------------------------------------------------------------------------------
+extern "C" int pir_load_galois_key(pir_ctx* ctx, uint32_t galois_elt, const uint64_t* gk, pir_key** out) {
+    CW_ENTER(ctx);
+    if (!out) return fail(PIR_E_INVALID, "null argument");
+    *out = nullptr;
+    if (galois_elt % 2 == 0 || galois_elt >= 2 * ctx->N || galois_elt == 1)
+        return fail(PIR_E_INVALID, "the Galois element must be odd, in (1, 2N)");
+    pir_key* key = nullptr;
+    CW_TRY(pir_load_key(ctx, gk, &key));
+    key->galois = galois_elt;
+    *out = key;
+    return PIR_OK;
+}
+
+static uint32_t inv_mod_2n(uint32_t g, uint32_t twoN) {  // g odd: g^-1 mod 2N by brute force
+    for (uint32_t x = 1; x < twoN; x += 2)
+        if ((uint64_t)g * x % twoN == 1) return x;
+    return 0;
+}
+
+extern "C" int pir_expand(pir_ctx* ctx, const pir_key* const* gkeys, uint32_t c, const uint64_t* packed, uint32_t h,
+                          uint32_t m, uint64_t* query, void* stream) {
+    CW_ENTER(ctx);
+    const uint32_t N = ctx->N, L = ctx->L;
+    if (!packed || !query || (c && !gkeys)) return fail(PIR_E_INVALID, "null argument");
+    if (c > ctx->logN) return fail(PIR_E_INVALID, "c must be at most log2 N");
+    if (m == 0 || h != (m + (1u << c) - 1) >> c) return fail(PIR_E_INVALID, "need m >= 1 and h = ceil(m / 2^c)");
+    for (uint32_t a = 0; a < c; ++a) {
+        if (!gkeys[a] || gkeys[a]->ctx != ctx) return fail(PIR_E_INVALID, "missing Galois key or another context");
+        if (gkeys[a]->galois != N / (1u << a) + 1)
+            return fail(PIR_E_INVALID, "gkeys[a] must switch from x -> x^(N/2^a + 1)");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    const size_t LN = (size_t)L * N, ct = 2 * LN;
+    CW_TRY(begin_async(ctx, st));
+    if (c == 0) {
+        CW_HIP(ctx, hipMemcpyAsync(query, packed, (size_t)m * ct * 8, hipMemcpyDeviceToDevice, st));
+        return end_async(ctx, st);
+    }
+    const size_t slots = (size_t)h << c, Emax = (size_t)h << (c - 1);
+    uint64_t *A, *B, *stage, *sub, *R = nullptr;
+    CW_TRY(ws_get_t(ctx, "exp_a", slots * ct, &A));
+    CW_TRY(ws_get_t(ctx, "exp_b", slots * ct, &B));
+    CW_TRY(ws_get_t(ctx, "exp_stage", Emax * 3 * LN, &stage));
+    CW_TRY(ws_get_t(ctx, "exp_sub", Emax * ct, &sub));
+    if (cw::relin_needs_staging(ctx->logN)) CW_TRY(ws_get_t(ctx, "exp_R", Emax * (L + 2) * LN, &R));
+    Launch lc = make_launch(ctx, st);
+    for (uint32_t j = 0; j < h; ++j)
+        CW_HIP(ctx, hipMemcpyAsync(A + ((size_t)j << c) * ct, packed + (size_t)j * ct, ct * 8, hipMemcpyDeviceToDevice, st));
+    for (uint32_t a = 0; a < c; ++a) {
+        const uint32_t E = h << a, g = N / (1u << a) + 1;
+        {
+            Prof pr(ctx, "expand", st, (double)E * 2 * LN);
+            cw::launch_expand_stage(lc, A, c, a, h, inv_mod_2n(g, 2 * N), stage);
+        }
+        cw::Batch bt{};
+        bt.nq = 1;
+        bt.E = E;
+        bt.rlk[0] = gkeys[a]->d;
+        bt.sel[0] = sub;
+        {
+            Prof pr(ctx, "relin", st, bfly(ctx, (size_t)E * (L + 2) * L));
+            cw::launch_relin(lc, stage, bt, R);
+        }
+        {
+            Prof pr(ctx, "ntt_inv", st, bfly(ctx, (size_t)E * 2 * L));
+            cw::launch_ntt(lc, true, sub, sub, (size_t)E * 2 * L, L, 0);
+        }
+        {
+            Prof pr(ctx, "expand", st, (double)E * 2 * LN);
+            cw::launch_expand_combine(lc, A, sub, c, a, h, B);
+        }
+        std::swap(A, B);
+    }
+    CW_HIP(ctx, hipMemcpyAsync(query, A, (size_t)m * ct * 8, hipMemcpyDeviceToDevice, st));
+    return end_async(ctx, st);
 }

@@ -39,6 +39,8 @@ struct Launch {
                           // need no reduction between passes
     uint32_t N, logN, L, LB, LL;
     uint32_t cus;         // compute units of the device
+    uint32_t relin_group; // key-switch workgroup order: 0 = the L limbs of an element side by side on
+                          // one XCD; G > 0 = blocks of G elements, limb-major inside a block
     uint64_t* fix;        // fixup list for ambiguous conversions (capacity >= coefficients per launch)
     uint32_t* fixcnt;     // its counter; zero between launches
 };
@@ -69,6 +71,16 @@ void launch_gather_leaf(const Launch& lc, const uint32_t* refs, const Batch& bt)
 void launch_accumulate(const Launch& lc, const QueryPtrs& qp, const uint64_t* Ph, uint32_t nq, uint32_t E,
                        uint32_t s);
 void launch_pointwise_pt(const Launch& lc, const uint64_t* ct, const uint64_t* pt, uint64_t* out);
+// Query expansion, level a of c, over E = h 2^a items (packed ciphertext j, slot b), ciphertexts
+// [h 2^c][2][L][N] in coefficient form with slot b of packed ciphertext j at j 2^c + b.
+//   stage:   staging [E][3][L][N] = (sigma_g(c0), 0, sigma_g(c1)) of cts[j 2^c + b], where
+//            sigma_g is x -> x^g and ginv = g^-1 mod 2N
+//   combine: dst[j 2^c + b] = src[..] + sub[e], dst[j 2^c + b + 2^a] = x^(-2^a) (src[..] - sub[e]),
+//            sub [E][2][L][N] in coefficient form; dst != src
+void launch_expand_stage(const Launch& lc, const uint64_t* cts, uint32_t c, uint32_t a, uint32_t h, uint32_t ginv,
+                         uint64_t* staging);
+void launch_expand_combine(const Launch& lc, const uint64_t* src, const uint64_t* sub, uint32_t c, uint32_t a,
+                           uint32_t h, uint64_t* dst);
 // Row gather: dst row e = src row order[e] for e < n, rows of `row` uint16 (a multiple of 8).
 void launch_gather_rows(hipStream_t st, const uint16_t* src, const uint64_t* order, uint64_t n, size_t row,
                         uint16_t* dst);

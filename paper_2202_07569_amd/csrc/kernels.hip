@@ -100,7 +100,14 @@ __device__ __forceinline__ uint32_t elem_index(uint32_t tid, uint32_t u) {
     }
 }
 
-__device__ __forceinline__ uint32_t lds_pad(uint32_t idx) { return idx + (idx >> 4); }
+__host__ __device__ constexpr uint32_t lds_pad(uint32_t idx) { return idx + (idx >> 4); }
+
+// elem_index splits into a thread part and an element part with disjoint bits:
+//   elem_index(tid, u) = elem_index(tid, 0) | elem_index(0, u).
+// Shifts and the LDS padding distribute over such a split: for disjoint a and b,
+// (a | b) >> k = (a >> k) + (b >> k) and lds_pad(a | b) = lds_pad(a) + lds_pad(b).  The transforms
+// therefore form each address as a per-thread base (once per pass or stage) plus a compile-time
+// offset, which the memory instructions take as an immediate.
 
 template <class Sh, int P>
 __device__ __forceinline__ void fwd_pass(uint64_t* a, uint32_t tid, const uint64_t* __restrict__ psi,
@@ -111,12 +118,15 @@ __device__ __forceinline__ void fwd_pass(uint64_t* a, uint32_t tid, const uint64
     for (int sp = 0; sp < G::rp; ++sp) {
         const int s = G::S0 + sp;
         const int pb = G::x + G::rp - 1 - sp;
+        const uint32_t tb = (1u << s) + (elem_index<Sh, P>(tid, 0u) >> (Sh::LOGN - s));
+        const uint64_t* __restrict__ ps = psi + tb;
+        const uint64_t* __restrict__ pq = psiq + tb;
 #pragma unroll
         for (int u0 = 0; u0 < Sh::EPT; ++u0) {
             if (u0 & (1 << pb)) continue;
             const int u1 = u0 | (1 << pb);
-            const uint32_t ti = (1u << s) + (elem_index<Sh, P>(tid, (uint32_t)u0) >> (Sh::LOGN - s));
-            const uint64_t w = psi[ti], wq = psiq[ti];
+            const uint32_t c = elem_index<Sh, P>(0u, (uint32_t)u0) >> (Sh::LOGN - s);
+            const uint64_t w = ps[c], wq = pq[c];
             uint64_t X = a[u0];
             X = X >= p2 ? X - p2 : X;
             const uint64_t T = mul_shoup_lazy(a[u1], w, wq, p);
@@ -135,12 +145,15 @@ __device__ __forceinline__ void inv_pass(uint64_t* a, uint32_t tid, const uint64
     for (int sp = G::rp - 1; sp >= 0; --sp) {
         const int s = G::S0 + sp;
         const int pb = G::x + G::rp - 1 - sp;
+        const uint32_t tb = (1u << s) + (elem_index<Sh, P>(tid, 0u) >> (Sh::LOGN - s));
+        const uint64_t* __restrict__ ps = psi + tb;
+        const uint64_t* __restrict__ pq = psiq + tb;
 #pragma unroll
         for (int u0 = 0; u0 < Sh::EPT; ++u0) {
             if (u0 & (1 << pb)) continue;
             const int u1 = u0 | (1 << pb);
-            const uint32_t ti = (1u << s) + (elem_index<Sh, P>(tid, (uint32_t)u0) >> (Sh::LOGN - s));
-            const uint64_t w = psi[ti], wq = psiq[ti];
+            const uint32_t c = elem_index<Sh, P>(0u, (uint32_t)u0) >> (Sh::LOGN - s);
+            const uint64_t w = ps[c], wq = pq[c];
             const uint64_t X = a[u0], Y = a[u1];
             const uint64_t Sm = X + Y;
             a[u0] = Sm >= p2 ? Sm - p2 : Sm;
@@ -175,7 +188,9 @@ __device__ __forceinline__ double fred(double x, double p, double pinv) {
     return __builtin_fma(-__builtin_rint(x * pinv), p, x);
 }
 
-template <class Sh, int P, bool LAZY = false>
+// TWPAD: the twiddle table is an LDS copy stored with the exchange buffer's padding (lds_pad), which
+// keeps the last stages' per-lane twiddle reads free of bank conflicts.
+template <class Sh, int P, bool LAZY = false, bool TWPAD = false>
 __device__ __forceinline__ void fwd_pass_fp(double* a, uint32_t tid, const double* __restrict__ tw, double p,
                                             double pinv) {
     using G = PassGeo<Sh, P>;
@@ -188,12 +203,14 @@ __device__ __forceinline__ void fwd_pass_fp(double* a, uint32_t tid, const doubl
     for (int sp = 0; sp < G::rp; ++sp) {
         const int s = G::S0 + sp;
         const int pb = G::x + G::rp - 1 - sp;
+        const uint32_t tb = (1u << s) + (elem_index<Sh, P>(tid, 0u) >> (Sh::LOGN - s));
+        const double* __restrict__ ts = tw + (TWPAD ? lds_pad(tb) : tb);
 #pragma unroll
         for (int u0 = 0; u0 < Sh::EPT; ++u0) {
             if (u0 & (1 << pb)) continue;
             const int u1 = u0 | (1 << pb);
-            const uint32_t ti = (1u << s) + (elem_index<Sh, P>(tid, (uint32_t)u0) >> (Sh::LOGN - s));
-            const double T = fmulmod(a[u1], tw[ti], p, pinv);
+            const uint32_t c = elem_index<Sh, P>(0u, (uint32_t)u0) >> (Sh::LOGN - s);
+            const double T = fmulmod(a[u1], ts[TWPAD ? lds_pad(c) : c], p, pinv);
             const double X = a[u0];
             a[u0] = X + T;
             a[u1] = X - T;
@@ -212,14 +229,16 @@ __device__ __forceinline__ void inv_pass_fp(double* a, uint32_t tid, const doubl
     for (int sp = G::rp - 1; sp >= 0; --sp) {
         const int s = G::S0 + sp;
         const int pb = G::x + G::rp - 1 - sp;
+        const uint32_t tb = (1u << s) + (elem_index<Sh, P>(tid, 0u) >> (Sh::LOGN - s));
+        const double* __restrict__ ts = tw + tb;
 #pragma unroll
         for (int u0 = 0; u0 < Sh::EPT; ++u0) {
             if (u0 & (1 << pb)) continue;
             const int u1 = u0 | (1 << pb);
-            const uint32_t ti = (1u << s) + (elem_index<Sh, P>(tid, (uint32_t)u0) >> (Sh::LOGN - s));
+            const uint32_t c = elem_index<Sh, P>(0u, (uint32_t)u0) >> (Sh::LOGN - s);
             const double X = a[u0], Y = a[u1];
             a[u0] = X + Y;
-            a[u1] = fmulmod(X - Y, tw[ti], p, pinv);
+            a[u1] = fmulmod(X - Y, ts[c], p, pinv);
         }
     }
 }
@@ -231,15 +250,57 @@ __device__ __forceinline__ uint64_t fp_to_residue(double x, double p) {
     return (uint64_t)x;
 }
 
-// registers of pass PA -> LDS -> registers of pass PB
-template <class Sh, int PA, int PB, class V>
+// Index bit that bit b of the thread index occupies in pass P (see elem_index).
+template <class Sh, int P>
+__host__ __device__ constexpr int tid_bit_pos(int b) {
+    using G = PassGeo<Sh, P>;
+    if constexpr (G::plo == 0) return b + Sh::R;
+    else return b < G::plo - G::x ? G::x + b : b + G::x + G::rp;
+}
+// An exchange between passes PA and PB stays inside each wavefront when every thread-index bit
+// above the lane bits occupies the same index bit in both passes: a wavefront then reads back
+// exactly the LDS words it wrote.
+template <class Sh, int PA, int PB>
+__host__ __device__ constexpr bool wave_local() {
+    constexpr int TB = Sh::LOGN - Sh::R;
+    for (int b = 6; b < TB; ++b)
+        if (tid_bit_pos<Sh, PA>(b) != tid_bit_pos<Sh, PB>(b)) return false;
+    return true;
+}
+// Whether the exchange that fed pass PA (from the pass before it, in the direction PA -> PB) was
+// wavefront-local.
+template <class Sh, int PA, int PB, bool FIRST>
+__host__ __device__ constexpr bool prev_wave_local() {
+    if constexpr (FIRST) return false;
+    else if constexpr (PA < PB) return wave_local<Sh, PA - 1, PA>();
+    else return wave_local<Sh, PA + 1, PA>();
+}
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+// registers of pass PA -> LDS -> registers of pass PB.  FIRST: the first exchange of a transform.
+// A workgroup-wide exchange starts with a barrier (earlier reads of the buffer by other waves must
+// be done before it is overwritten) and has a second one between its writes and reads.  A
+// wavefront-local exchange needs only wavefront ordering, plus a leading barrier when it follows a
+// workgroup-wide exchange or starts the transform, whose readers may still be reading this
+// wavefront's words.  The transform therefore leaves the buffer with reads possibly pending, and
+// every later user starts with a barrier.
+template <class Sh, int PA, int PB, bool FIRST, class V>
 __device__ __forceinline__ void exchange(V* a, V* sm, uint32_t tid) {
+    constexpr bool WL = wave_local<Sh, PA, PB>();
+    constexpr bool prev_wl = prev_wave_local<Sh, PA, PB, FIRST>();
+    if constexpr (!(WL && prev_wl)) __syncthreads();
+    V* wa = sm + lds_pad(elem_index<Sh, PA>(tid, 0u));
+    V* ra = sm + lds_pad(elem_index<Sh, PB>(tid, 0u));
 #pragma unroll
-    for (int u = 0; u < Sh::EPT; ++u) sm[lds_pad(elem_index<Sh, PA>(tid, u))] = a[u];
-    __syncthreads();
+    for (int u = 0; u < Sh::EPT; ++u) wa[lds_pad(elem_index<Sh, PA>(0u, u))] = a[u];
+    if constexpr (WL) wave_sync();
+    else __syncthreads();
 #pragma unroll
-    for (int u = 0; u < Sh::EPT; ++u) a[u] = sm[lds_pad(elem_index<Sh, PB>(tid, u))];
-    __syncthreads();
+    for (int u = 0; u < Sh::EPT; ++u) a[u] = ra[lds_pad(elem_index<Sh, PB>(0u, u))];
+    if constexpr (WL) wave_sync();
 }
 
 // Twiddle tables of one prime: integer form [4][N] (w, w', w_inv, w_inv') and double form
@@ -249,21 +310,21 @@ struct TwRow {
     const double* f;
 };
 
-template <class Sh, bool FP, int P, bool LAZY = false>
+template <class Sh, bool FP, int P, bool LAZY = false, bool TWPAD = false>
 __device__ __forceinline__ void fwd_passes(void* av, void* smv, uint32_t tid, TwRow tw, const CtxConst* K,
                                            uint32_t pi) {
     if constexpr (FP) {
         double* a = (double*)av;
-        fwd_pass_fp<Sh, P, LAZY>(a, tid, tw.f, K->pd[pi], K->pinv[pi]);
+        fwd_pass_fp<Sh, P, LAZY, TWPAD>(a, tid, tw.f, K->pd[pi], K->pinv[pi]);
         if constexpr (P + 1 < Sh::NP) {
-            exchange<Sh, P, P + 1>(a, (double*)smv, tid);
-            fwd_passes<Sh, FP, P + 1, LAZY>(av, smv, tid, tw, K, pi);
+            exchange<Sh, P, P + 1, P == 0>(a, (double*)smv, tid);
+            fwd_passes<Sh, FP, P + 1, LAZY, TWPAD>(av, smv, tid, tw, K, pi);
         }
     } else {
         uint64_t* a = (uint64_t*)av;
         fwd_pass<Sh, P>(a, tid, tw.i, tw.i + Sh::N, K->p[pi]);
         if constexpr (P + 1 < Sh::NP) {
-            exchange<Sh, P, P + 1>(a, (uint64_t*)smv, tid);
+            exchange<Sh, P, P + 1, P == 0>(a, (uint64_t*)smv, tid);
             fwd_passes<Sh, FP, P + 1>(av, smv, tid, tw, K, pi);
         }
     }
@@ -276,14 +337,14 @@ __device__ __forceinline__ void inv_passes(void* av, void* smv, uint32_t tid, Tw
         double* a = (double*)av;
         inv_pass_fp<Sh, P>(a, tid, tw.f + 2 * Sh::N, K->pd[pi], K->pinv[pi]);
         if constexpr (P > 0) {
-            exchange<Sh, P, P - 1>(a, (double*)smv, tid);
+            exchange<Sh, P, P - 1, P == Sh::NP - 1>(a, (double*)smv, tid);
             inv_passes<Sh, FP, P - 1>(av, smv, tid, tw, K, pi);
         }
     } else {
         uint64_t* a = (uint64_t*)av;
         inv_pass<Sh, P>(a, tid, tw.i + 2 * Sh::N, tw.i + 3 * Sh::N, K->p[pi]);
         if constexpr (P > 0) {
-            exchange<Sh, P, P - 1>(a, (uint64_t*)smv, tid);
+            exchange<Sh, P, P - 1, P == Sh::NP - 1>(a, (uint64_t*)smv, tid);
             inv_passes<Sh, FP, P - 1>(av, smv, tid, tw, K, pi);
         }
     }
@@ -293,11 +354,11 @@ __device__ __forceinline__ void inv_passes(void* av, void* smv, uint32_t tid, Tw
 // transform; any |v| < 2^53 for the inverse, whose passes start by reducing).  On return v[] holds
 // the outputs reduced to [-p/2, p/2]: the forward transform in the transformed layout, the inverse
 // (including N^-1) in the first pass's natural-order pattern.
-template <class Sh, bool LAZY = false>
+template <class Sh, bool LAZY = false, bool TWPAD = false>
 __device__ __forceinline__ void ntt_fwd_f(double* v, uint64_t* sm, uint32_t tid, TwRow tw, const CtxConst* K,
                                           uint32_t pi) {
     static_assert(!LAZY || Sh::LOGN <= 13, "the lazy bound covers at most 13 stages");
-    fwd_passes<Sh, true, 0, LAZY>(v, sm, tid, tw, K, pi);
+    fwd_passes<Sh, true, 0, LAZY, TWPAD>(v, sm, tid, tw, K, pi);
     const double p = K->pd[pi], pinv = K->pinv[pi];
 #pragma unroll
     for (int u = 0; u < Sh::EPT; ++u) v[u] = fred(v[u], p, pinv);
@@ -380,6 +441,22 @@ __device__ __forceinline__ void xcd_split(size_t b, uint32_t per, size_t& group,
     const size_t slot = b / XCDS;
     group = slot / per * XCDS + b % XCDS;
     member = (uint32_t)(slot % per);
+}
+
+// Key-switch workgroup b -> (element-query eq, output limb j).  G = 0: xcd_split, the L limbs of an
+// element on one XCD (they read the same digit rows).  G > 0: blocks of G element-queries, limb-major
+// inside a block, so that workgroups running together read the same key limb.
+__host__ __device__ __forceinline__ size_t relin_grid(size_t nEQ, uint32_t L, uint32_t G) {
+    return G ? (nEQ + G - 1) / G * G * L : xcd_grid(nEQ, L);
+}
+__device__ __forceinline__ void relin_split(size_t b, uint32_t L, uint32_t G, size_t& eq, uint32_t& j) {
+    if (G == 0) {
+        xcd_split(b, L, eq, j);
+        return;
+    }
+    const size_t blk = b / ((size_t)G * L), r = b % ((size_t)G * L);
+    j = (uint32_t)(r / G);
+    eq = blk * G + r % G;
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -612,7 +689,7 @@ __global__ __launch_bounds__(Sh::T) void k_ntt_digits(const CtxConst* __restrict
     ntt_fwd_row<Sh, FP>(K, tw, twf, RowsDigits<Sh>{c3, out, K, K->L});
 }
 template <class Sh, bool FP>
-__global__ __launch_bounds__(Sh::T) void k_ntt_inv_tensor(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
+__global__ __launch_bounds__(Sh::T, Sh::LOGN == 13 ? 8 : 1) void k_ntt_inv_tensor(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
                                                           const double* __restrict__ twf,
                                                           const uint32_t* __restrict__ refs, const Batch bt,
                                                           uint64_t* __restrict__ X, size_t groups) {
@@ -653,16 +730,16 @@ __global__ __launch_bounds__(Sh::T) void k_ntt_inv_tensor(const CtxConst* __rest
 // ---------------------------------------------------------------------------------------------
 
 
-template <class Sh, bool FP, bool LAZY>
+template <class Sh>
 __global__ __launch_bounds__(Sh::T) void k_relin(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
                                                  const double* __restrict__ twf, const uint64_t* __restrict__ c3,
-                                                 const Batch bt) {
+                                                 const Batch bt, uint32_t G) {
     __shared__ uint64_t sm[Sh::LDS_WORDS];
     constexpr int N = Sh::N, T = Sh::T, EPT = Sh::EPT;
     const uint32_t L = K->L, tid = threadIdx.x;
     size_t eq;
     uint32_t j;
-    xcd_split(blockIdx.x, L, eq, j);  // the L workgroups of element e share its digit rows: one XCD
+    relin_split(blockIdx.x, L, G, eq, j);
     if (eq >= (size_t)bt.nq * bt.E) return;
     const uint32_t q = (uint32_t)(eq / bt.E);
     const size_t e = eq % bt.E;
@@ -671,56 +748,7 @@ __global__ __launch_bounds__(Sh::T) void k_relin(const CtxConst* __restrict__ K,
     const uint64_t* base = c3 + eq * 3 * L * N;
     const size_t LN = (size_t)L * N;
     uint64_t* o0 = sel + e * 2 * LN + (size_t)j * N + tid;
-    if constexpr (FP) {
-        // Key in the fp64 operand format; the digits D_i < q_i are exact doubles reduced mod q_j by
-        // fred.  Transformed values and key entries lie in [-p/2, p/2], so each product is below
-        // 0.7 p and each accumulator below (0.7 L + 0.5) p < 2^53.
-        const double* __restrict__ rlk = (const double*)bt.rlk[q];
-        const double p = K->pd[j], pinv = K->pinv[j];
-        double acc0[EPT], acc1[EPT], v[EPT];
-        for (uint32_t i = 0; i < L + 2; ++i) {
-            // The transform's index and twiddle arithmetic does not depend on i; opaque copies of
-            // the thread index and table pointers per iteration keep the compiler from hoisting all
-            // of it out of the loop into registers (which would spill).
-            uint32_t t = tid;
-            TwRow tr = twr;
-            asm volatile("" : "+v"(t), "+v"(tr.i), "+v"(tr.f));
-            const uint64_t* src = i < L ? base + ((size_t)2 * L + i) * N : base + ((size_t)(i - L) * L + j) * N;
-            if (i < L && i != j) {
-#pragma unroll
-                for (int u = 0; u < EPT; ++u) v[u] = fred((double)src[elem_index<Sh, 0>(t, u)], p, pinv);
-            } else {
-#pragma unroll
-                for (int u = 0; u < EPT; ++u) v[u] = (double)src[elem_index<Sh, 0>(t, u)];
-            }
-            ntt_fwd_f<Sh, LAZY>(v, (uint64_t*)sm, t, tr, K, j);
-            asm volatile("" ::: "memory");  // keep the key loads below the transform
-            if (i < L) {
-                const double* bh = rlk + ((size_t)i * 2 + 0) * LN + (size_t)j * N + t;
-                const double* ah = rlk + ((size_t)i * 2 + 1) * LN + (size_t)j * N + t;
-#pragma unroll
-                for (int u = 0; u < EPT; ++u) {
-                    const size_t o = (size_t)u * T;
-                    const double tb = fmulmod(v[u], bh[o], p, pinv);
-                    const double ta = fmulmod(v[u], ah[o], p, pinv);
-                    acc0[u] = i == 0 ? tb : acc0[u] + tb;
-                    acc1[u] = i == 0 ? ta : acc1[u] + ta;
-                }
-            } else {
-#pragma unroll
-                for (int u = 0; u < EPT; ++u) {
-                    if (i == L) acc0[u] = acc0[u] + v[u];
-                    else acc1[u] = acc1[u] + v[u];
-                }
-            }
-            asm volatile("" ::: "memory");
-        }
-#pragma unroll
-        for (int u = 0; u < EPT; ++u) {
-            o0[(size_t)u * T] = fp_to_residue(fred(acc0[u], p, pinv), p);
-            o0[LN + (size_t)u * T] = fp_to_residue(fred(acc1[u], p, pinv), p);
-        }
-    } else {
+    {
         const uint64_t* __restrict__ rlk = bt.rlk[q];
         const uint64_t p = K->p[j], r1 = K->r1[j];
         const size_t half = (size_t)L * 2 * LN;
@@ -770,21 +798,109 @@ __global__ __launch_bounds__(Sh::T) void k_relin(const CtxConst* __restrict__ K,
 // N = 16384 does not fit 16 elements plus two accumulators per thread in the 128 registers that a
 // 1024-thread workgroup allows; there the digits are transformed to `staging` [E][L+2][L][N] and
 // multiplied-accumulated by a second kernel.
+// fp64 key switch (every prime below 2^50).  The key is in the fp64 operand format; the digits
+// D_i < q_i are exact doubles, reduced mod q_j by fred.  Transformed values and key entries lie in
+// [-p/2, p/2], so each product is below 0.7 p and each accumulator below (0.7 L + 0.5) p < 2^53.
+// All L + 2 transforms of the workgroup use prime q_j: its forward twiddles are staged in LDS once,
+// which leaves global memory to the operand rows.  The next operand row is loaded while the
+// current one is transformed (no global load inside the transform waits behind it).
+template <class Sh, bool LAZY>
+__global__ __launch_bounds__(Sh::T) void k_relin_f(const CtxConst* __restrict__ K, const double* __restrict__ twf,
+                                                   const uint64_t* __restrict__ c3, const Batch bt, uint32_t G) {
+    __shared__ uint64_t sm[Sh::LDS_WORDS];
+    __shared__ double twl[Sh::LDS_WORDS];  // padded like the exchange buffer
+    constexpr int N = Sh::N, T = Sh::T, EPT = Sh::EPT;
+    const uint32_t L = K->L, tid = threadIdx.x;
+    size_t eq;
+    uint32_t j;
+    relin_split(blockIdx.x, L, G, eq, j);
+    if (eq >= (size_t)bt.nq * bt.E) return;
+    const uint32_t q = (uint32_t)(eq / bt.E);
+    const size_t e = eq % bt.E;
+    {
+        const double* __restrict__ g = twf + (size_t)j * 4 * N;  // forward twiddles of q_j
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) twl[lds_pad(u * T + tid)] = g[u * T + tid];
+    }
+    const double* __restrict__ rlk = (const double*)bt.rlk[q];
+    uint64_t* __restrict__ sel = bt.sel[q];
+    const uint64_t* base = c3 + eq * 3 * L * N;
+    const size_t LN = (size_t)L * N;
+    const double p = K->pd[j], pinv = K->pinv[j];
+    auto src_row = [&](uint32_t i) {
+        return i < L ? base + ((size_t)2 * L + i) * N : base + ((size_t)(i - L) * L + j) * N;
+    };
+    uint64_t nx[EPT];
+    {
+        const uint64_t* src = src_row(0);
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) nx[u] = src[elem_index<Sh, 0>(tid, u)];
+    }
+    __syncthreads();  // twiddles staged
+    double acc0[EPT], acc1[EPT], v[EPT];
+    for (uint32_t i = 0; i < L + 2; ++i) {
+        // The transform's index arithmetic does not depend on i; an opaque copy of the thread index
+        // per iteration keeps the compiler from hoisting all of it out of the loop into registers.
+        uint32_t t = tid;
+        asm volatile("" : "+v"(t));
+        if (i < L && i != j) {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) v[u] = fred((double)nx[u], p, pinv);
+        } else {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) v[u] = (double)nx[u];
+        }
+        if (i + 1 < L + 2) {
+            const uint64_t* src = src_row(i + 1);
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) nx[u] = src[elem_index<Sh, 0>(t, u)];
+        }
+        ntt_fwd_f<Sh, LAZY, true>(v, sm, t, TwRow{nullptr, twl}, K, j);
+        asm volatile("" ::: "memory");  // keep the key loads below the transform
+        if (i < L) {
+            const double* bh = rlk + ((size_t)i * 2 + 0) * LN + (size_t)j * N + t;
+            const double* ah = rlk + ((size_t)i * 2 + 1) * LN + (size_t)j * N + t;
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                const size_t o = (size_t)u * T;
+                const double tb = fmulmod(v[u], bh[o], p, pinv);
+                const double ta = fmulmod(v[u], ah[o], p, pinv);
+                acc0[u] = i == 0 ? tb : acc0[u] + tb;
+                acc1[u] = i == 0 ? ta : acc1[u] + ta;
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                if (i == L) acc0[u] = acc0[u] + v[u];
+                else acc1[u] = acc1[u] + v[u];
+            }
+        }
+        asm volatile("" ::: "memory");
+    }
+    uint64_t* o0 = sel + e * 2 * LN + (size_t)j * N + tid;
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        o0[(size_t)u * T] = fp_to_residue(fred(acc0[u], p, pinv), p);
+        o0[LN + (size_t)u * T] = fp_to_residue(fred(acc1[u], p, pinv), p);
+    }
+}
+
 void launch_relin(const Launch& lc, const uint64_t* c3, const Batch& bt, uint64_t* staging) {
     if (!bt.E || !bt.nq) return;
-    const unsigned blocks = (unsigned)xcd_grid((size_t)bt.nq * bt.E, lc.L);
-#define CW_RELIN(LG)                                                                                               \
-    {                                                                                                              \
-        using Sh = DefaultShape<LG>::type;                                                                         \
-        if (lc.fp && lc.q_lazy)                                                                                    \
-            hipLaunchKernelGGL((k_relin<Sh, true, true>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,      \
-                               lc.twf, c3, bt);                                                                    \
-        else if (lc.fp)                                                                                            \
-            hipLaunchKernelGGL((k_relin<Sh, true, false>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,     \
-                               lc.twf, c3, bt);                                                                    \
-        else                                                                                                       \
-            hipLaunchKernelGGL((k_relin<Sh, false, false>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,    \
-                               lc.twf, c3, bt);                                                                    \
+    const unsigned blocks = (unsigned)relin_grid((size_t)bt.nq * bt.E, lc.L, lc.relin_group);
+#define CW_RELIN(LG)                                                                                      \
+    {                                                                                                     \
+        using Sh = DefaultShape<LG>::type;                                                                \
+        const uint32_t G = lc.relin_group;                                                                \
+        if (lc.fp && lc.q_lazy)                                                                           \
+            hipLaunchKernelGGL((k_relin_f<Sh, true>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.twf, \
+                               c3, bt, G);                                                                \
+        else if (lc.fp)                                                                                   \
+            hipLaunchKernelGGL((k_relin_f<Sh, false>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K,       \
+                               lc.twf, c3, bt, G);                                                        \
+        else                                                                                              \
+            hipLaunchKernelGGL((k_relin<Sh>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, lc.twf, \
+                               c3, bt, G);                                                                \
     }
     switch (lc.logN) {
         case 12: CW_RELIN(12) break;
@@ -969,9 +1085,11 @@ __device__ __forceinline__ bool scale_coeff(const CtxConst* K, const uint64_t* x
 // of a half is reported as ambiguous and the exact integer form redoes the coefficient.  Partial
 // sums are reduced every four terms so every value stays below 2^53 (see fmulmod).
 #pragma clang fp contract(off)
-template <int NL, int NB>
+// EX: the context has exactly NL ciphertext and NB auxiliary primes (every loop bound is then a
+// compile-time constant).
+template <int NL, int NB, bool EX>
 __device__ __forceinline__ bool scale_coeff_fp(const CtxConst* K, const uint64_t* x, size_t xs, uint64_t* cq) {
-    const uint32_t L = K->L, LB = K->LB;
+    const uint32_t L = EX ? NL : K->L, LB = EX ? NB : K->LB;
     double y[NL];
     double S = 0.0;
 #pragma unroll
@@ -1029,7 +1147,7 @@ __device__ __forceinline__ void scale_store(const CtxConst* K, const uint64_t* c
         if (i < (int)L) o[(size_t)i * N] = cq[i];
 }
 
-template <int NL, int NB, bool FP>
+template <int NL, int NB, bool FP, bool EX = false>
 __global__ void k_scale(const CtxConst* __restrict__ K, const uint64_t* __restrict__ X, uint64_t* __restrict__ out,
                         uint32_t E, uint64_t* fix, uint32_t* fixcnt) {
     const uint32_t N = K->N, LL = K->LL;
@@ -1038,7 +1156,7 @@ __global__ void k_scale(const CtxConst* __restrict__ K, const uint64_t* __restri
     const size_t c = gid % N, er = gid / N;
     uint64_t cq[NL];
     bool amb;
-    if constexpr (FP) amb = scale_coeff_fp<NL, NB>(K, X + er * LL * N + c, N, cq);
+    if constexpr (FP) amb = scale_coeff_fp<NL, NB, EX>(K, X + er * LL * N + c, N, cq);
     else amb = scale_coeff<NL, NB>(K, X + er * LL * N + c, N, cq, false);
     if (amb) fix[atomicAdd(fixcnt, 1u)] = gid;
     scale_store<NL>(K, cq, out, er, c);
@@ -1071,7 +1189,15 @@ void launch_scale(const Launch& lc, const uint64_t* X, uint64_t* out, uint32_t E
         hipLaunchKernelGGL((k_scale<NLV, NBV, false>), dim3(nb), dim3(EW_THREADS), 0, lc.stream, lc.K, X, out, E, \
                            lc.fix, lc.fixcnt);                                                                \
     hipLaunchKernelGGL((k_scale_fix<NLV, NBV>), dim3(1), dim3(256), 0, lc.stream, lc.K, X, out, lc.fix, lc.fixcnt);
-    if (lc.L <= 4 && lc.LB <= 5) {
+    if (lc.fp && lc.L == 5 && lc.LB == 5) {  // the N = 8192 parameter sets
+        hipLaunchKernelGGL((k_scale<5, 5, true, true>), dim3(nb), dim3(EW_THREADS), 0, lc.stream, lc.K, X, out, E,
+                           lc.fix, lc.fixcnt);
+        hipLaunchKernelGGL((k_scale_fix<8, 9>), dim3(1), dim3(256), 0, lc.stream, lc.K, X, out, lc.fix, lc.fixcnt);
+    } else if (lc.fp && lc.L == 3 && lc.LB == 3) {  // N = 4096, three 36-bit primes
+        hipLaunchKernelGGL((k_scale<3, 3, true, true>), dim3(nb), dim3(EW_THREADS), 0, lc.stream, lc.K, X, out, E,
+                           lc.fix, lc.fixcnt);
+        hipLaunchKernelGGL((k_scale_fix<4, 5>), dim3(1), dim3(256), 0, lc.stream, lc.K, X, out, lc.fix, lc.fixcnt);
+    } else if (lc.L <= 4 && lc.LB <= 5) {
         CW_SCALE(4, 5)
     } else if (lc.L <= 8 && lc.LB <= 9) {
         CW_SCALE(8, 9)
@@ -1202,6 +1328,75 @@ void launch_accumulate(const Launch& lc, const QueryPtrs& qp, const uint64_t* Ph
     if (!E || !nq) return;
     hipLaunchKernelGGL(k_accumulate, dim3(blocks_for((size_t)s * 2 * lc.L * lc.N), nq), dim3(EW_THREADS), 0,
                        lc.stream, lc.K, qp, Ph, E, s);
+}
+
+// ---------------------------------------------------------------------------------------------
+// Query expansion (Algorithm 5).  One thread per coefficient of one polynomial limb of one item.
+// The automorphism is written as a gather: output coefficient o of sigma_g(a) is a_i for
+// i = o g^-1 mod 2N when that is below N, else -a_(i - N) (x^N = -1).  The monomial x^(-e) moves
+// coefficient i to i - e, negated when it wraps (x^(-e) = -x^(N - e)).
+// ---------------------------------------------------------------------------------------------
+__global__ void k_expand_stage(const CtxConst* __restrict__ K, const uint64_t* __restrict__ cts, uint32_t c,
+                               uint32_t a, size_t E, uint32_t ginv, uint64_t* __restrict__ staging) {
+    const uint32_t N = K->N, L = K->L;
+    const size_t LN = (size_t)L * N;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= E * 2 * LN) return;
+    const uint32_t o = (uint32_t)(gid % N);
+    const uint32_t l = (uint32_t)((gid / N) % L);
+    const uint32_t poly = (uint32_t)((gid / LN) % 2);
+    const size_t e = gid / (2 * LN);
+    const size_t j = e >> a, b = e & ((1u << a) - 1u);
+    const uint64_t* src = cts + (((j << c) + b) * 2 + poly) * LN + (size_t)l * N;
+    const uint64_t p = K->p[l];
+    const uint32_t i = (uint32_t)((uint64_t)o * ginv % (2ull * N));
+    const uint64_t v = i < N ? src[i] : (src[i - N] ? p - src[i - N] : 0);
+    uint64_t* dst = staging + e * 3 * LN + (size_t)l * N + o;
+    if (poly == 0) {
+        dst[0] = v;
+        dst[LN] = 0;
+    } else {
+        dst[2 * LN] = v;
+    }
+}
+
+__global__ void k_expand_combine(const CtxConst* __restrict__ K, const uint64_t* __restrict__ src,
+                                 const uint64_t* __restrict__ sub, uint32_t c, uint32_t a, size_t E,
+                                 uint64_t* __restrict__ dst) {
+    const uint32_t N = K->N, L = K->L;
+    const size_t LN = (size_t)L * N;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= E * 2 * LN) return;
+    const uint32_t o = (uint32_t)(gid % N);
+    const size_t row = gid / N;  // (e, poly, l)
+    const uint32_t l = (uint32_t)(row % L);
+    const size_t e = gid / (2 * LN);
+    const size_t pl = row % (2 * (size_t)L);  // poly * L + l
+    const size_t j = e >> a, b = e & ((1u << a) - 1u);
+    const uint64_t p = K->p[l];
+    const uint64_t* x = src + (((j << c) + b) * 2) * LN + pl * N;
+    const uint64_t* y = sub + row * N;
+    dst[(((j << c) + b) * 2) * LN + pl * N + o] = add_mod(x[o], y[o], p);
+    const uint32_t sh = 1u << a;
+    const uint32_t i = o + sh;
+    const uint64_t d = i < N ? sub_mod(x[i], y[i], p) : sub_mod(y[i - N], x[i - N], p);
+    dst[(((j << c) + b + sh) * 2) * LN + pl * N + o] = d;
+}
+
+void launch_expand_stage(const Launch& lc, const uint64_t* cts, uint32_t c, uint32_t a, uint32_t h, uint32_t ginv,
+                         uint64_t* staging) {
+    const size_t E = (size_t)h << a;
+    if (!E) return;
+    hipLaunchKernelGGL(k_expand_stage, dim3(blocks_for(E * 2 * lc.L * lc.N)), dim3(EW_THREADS), 0, lc.stream, lc.K,
+                       cts, c, a, E, ginv, staging);
+}
+
+void launch_expand_combine(const Launch& lc, const uint64_t* src, const uint64_t* sub, uint32_t c, uint32_t a,
+                           uint32_t h, uint64_t* dst) {
+    const size_t E = (size_t)h << a;
+    if (!E) return;
+    hipLaunchKernelGGL(k_expand_combine, dim3(blocks_for(E * 2 * lc.L * lc.N)), dim3(EW_THREADS), 0, lc.stream,
+                       lc.K, src, sub, c, a, E, dst);
 }
 
 // dst row e = src row order[e], rows of `row` uint16 (a multiple of 8), copied in 16-byte words.

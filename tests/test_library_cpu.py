@@ -78,3 +78,12 @@ def test_serving_calls_reject_null_server():
     assert L.pir_serve_stats(None, None, None, None, None, None) == binding.PIR_E_INVALID
     assert "null server" in L.pir_last_error().decode()
     L.pir_serve_close(None)  # no-op
+
+
+def test_schedule_calls_reject_null_context():
+    L = binding.lib()
+    s = binding._Schedule(64, 2, 0, 0.0)
+    assert L.pir_get_schedule(None, ctypes.byref(s)) == binding.PIR_E_INVALID
+    assert L.pir_set_schedule(None, ctypes.byref(s)) == binding.PIR_E_INVALID
+    assert L.pir_autotune(None, 1, 2, 1, None, 0, None) == binding.PIR_E_INVALID
+    assert "null context" in L.pir_last_error().decode()
