@@ -57,6 +57,7 @@ def lib():
             "orc_mul_monomial": (None, [vp, P64, u32, u32, P64]),
             "orc_galois_keygen": (None, [vp, P8, u32, P64, P64, P64]),
             "orc_sub": (None, [vp, vp, P64, u32, P64]),
+            "orc_mod_switch": (None, [vp, P64, u32, u32, P64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -241,6 +242,14 @@ class Oracle:
         ct = np.ascontiguousarray(ct, dtype=np.uint64)
         out = np.empty(self.ct_shape(2), dtype=np.uint64)
         lib().orc_sub(self._h, gk._h, _ptr(ct), int(g), _ptr(out))
+        return out
+
+    def mod_switch(self, ct: np.ndarray, keep: int) -> np.ndarray:
+        """Response compression: [npoly][L][N] mod q -> [npoly][keep][N] mod q' = q_0 ... q_{keep-1},
+        each coefficient round(q' x / q) of its centred representative x."""
+        ct = np.ascontiguousarray(ct, dtype=np.uint64)
+        out = np.empty((ct.shape[0], keep, self.N), dtype=np.uint64)
+        lib().orc_mod_switch(self._h, _ptr(ct), ct.shape[0], int(keep), _ptr(out))
         return out
 
     def selector(self, key: Key, query: np.ndarray, positions) -> np.ndarray:

@@ -795,4 +795,27 @@ void orc_sub(const OrcCtx* c, const OrcKey* gk, const uint64_t* ct, uint32_t g, 
     orc_relin(c, gk, three.data(), out);
 }
 
+// ---- response compression (modulus switching; Section 2.2, the SealPIR optimization the paper
+// adopts for responses) --------------------------------------------------------------------------
+// Every coefficient x of every polynomial, lifted to its centred representative modulo q, becomes
+// round(q' x / q) = round(x / r) with q' = q_0 ... q_{keep-1} and r = q / q' (odd, so no ties),
+// stored modulo q'.  in: [npoly][L][N]; out: [npoly][keep][N].
+void orc_mod_switch(const OrcCtx* c, const uint64_t* in, uint32_t npoly, uint32_t keep, uint64_t* out) {
+    const uint32_t N = c->N, L = c->L;
+    Big r = big_u64(1);
+    for (uint32_t j = keep; j < L; ++j) r = mul_u64(r, c->qp[j]);
+    const Big twor = add(r, r);
+    for (uint32_t poly = 0; poly < npoly; ++poly)
+        for (uint32_t i = 0; i < N; ++i) {
+            SInt x = c->Q.lift_centered(in + (size_t)poly * L * N + i, N);
+            Big num = add(add(x.mag, x.mag), r);  // round(|x| / r) = floor((2|x| + r) / (2r))
+            Big y, rem;
+            divmod(num, twor, y, rem);
+            for (uint32_t j = 0; j < keep; ++j) {
+                uint64_t v = mod_u64(y, c->qp[j]);
+                out[((size_t)poly * keep + j) * N + i] = (x.neg && v) ? c->qp[j] - v : v;
+            }
+        }
+}
+
 }  // extern "C"

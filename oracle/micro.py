@@ -150,3 +150,16 @@ class Micro:
         sig = self.automorphism(ct, g)
         zero = np.zeros_like(sig[0])
         return self.relin(gk, np.stack([sig[0], zero, sig[1]]))
+
+    # response compression: round(q' x / q) of the centred lift, in Python integers
+    def mod_switch(self, ct, keep):
+        qk = 1
+        for p in self.primes[:keep]:
+            qk *= p
+        out = []
+        for r in range(ct.shape[0]):
+            xs = [self.centred(v) for v in self.to_int(ct[r])]
+            ys = [(2 * qk * x + self.q) // (2 * self.q) for x in xs]  # floor(q' x / q + 1/2)
+            out.append(np.array([[y % p for y in ys] for p in self.primes[:keep]], dtype=np.uint64))
+        return np.stack(out)
+
