@@ -501,11 +501,12 @@ def summarize_traffic(fetch_csv, write_csv, copy_mib, workload, n, batch, schedu
         return groups
 
     fetch, write = per_dispatch(fetch_csv, "FETCH_SIZE"), per_dispatch(write_csv, "WRITE_SIZE")
-    copies = [max((k for k in fetch if k[0] == "copy"), key=lambda k: k[1])]  # the calibration copies
-    ncopy = sum(len(fetch[k]) for k in copies)
-    copy_kib = copy_mib * 1024 * 3 / ncopy  # three copies of copy_mib MiB in the run
-    f_factor = copy_kib / (sum(sum(fetch[k]) for k in copies) / ncopy)
-    w_factor = copy_kib / (sum(sum(write[k]) for k in copies) / ncopy)
+
+    def calib(groups):  # the run's three copies of copy_mib MiB are its three largest copy dispatches
+        top = sorted((v for k, vs in groups.items() if k[0] == "copy" for v in vs), reverse=True)[:3]
+        return copy_mib * 1024 / (sum(top) / 3)
+
+    f_factor, w_factor, ncopy = calib(fetch), calib(write), 3
     fams = {}
     for fam in sorted({k[0] for k in fetch if k[0] != "copy"}):
         grid = max((k for k in fetch if k[0] == fam), key=lambda k: len(fetch[k]))
