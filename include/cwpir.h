@@ -163,6 +163,14 @@ int pir_load_galois_key(pir_ctx* ctx, uint32_t galois_elt, const uint64_t* gk, p
 int pir_expand(pir_ctx* ctx, const pir_key* const* gkeys, uint32_t c, const uint64_t* packed, uint32_t h, uint32_t m,
                uint64_t* query, void* stream);
 
+/* Response compression (the modulus switching of responses that the paper takes over from SealPIR,
+ * Section 2.2): `count` polynomials in (dev [count][L][N], e.g. an answer [s][2][L][N] as 2s
+ * polynomials) are switched from q to q' = q_0 ... q_{keep-1}: every coefficient's centred
+ * representative x becomes round(q' x / q) (q / q' is odd, so there are no ties), written to out
+ * (dev [count][keep][N]).  The client decrypts with q'.  1 <= keep <= L; in and out must not overlap.
+ * Asynchronous. */
+int pir_mod_switch(pir_ctx* ctx, const uint64_t* in, uint32_t count, uint32_t keep, uint64_t* out, void* stream);
+
 /* Captured answers (HIP graphs), for callers that answer many queries of the same shape, e.g. a
  * serving loop with fixed query and answer slots.  pir_graph_capture runs pir_answer_batch once
  * for the given arguments (the answers for the queries' current contents are written) and records

@@ -22,7 +22,7 @@ EXPORTS = [
     "pir_db_pair_count", "pir_profile_enable", "pir_profile_read", "pir_db_free", "pir_key_free", "pir_free",
     "pir_last_error", "pir_serve_open", "pir_serve_submit", "pir_serve_step", "pir_serve_poll", "pir_serve_stats",
     "pir_serve_close", "pir_get_schedule", "pir_set_schedule", "pir_autotune", "pir_graph_capture",
-    "pir_graph_launch", "pir_graph_free", "pir_load_galois_key", "pir_expand",
+    "pir_graph_launch", "pir_graph_free", "pir_load_galois_key", "pir_expand", "pir_mod_switch",
 ]
 
 
@@ -101,6 +101,7 @@ def lib():
             "pir_graph_free": (None, [vp]),
             "pir_load_galois_key": (i32, [vp, u32, vp, pp]),
             "pir_expand": (i32, [vp, pp, u32, vp, u32, u32, vp, vp]),
+            "pir_mod_switch": (i32, [vp, vp, u32, u32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -263,6 +264,17 @@ class Context:
             out = self.empty(m, 2, self.L, self.N)
         arr = (ctypes.c_void_p * max(1, c))(*([k._h.value for k in gkeys[:c]] or [None]))
         _check(lib().pir_expand(self._h, arr, c, _ptr(packed), h, m, _ptr(out), _stream(stream)))
+        return out
+
+    def mod_switch(self, x, keep: int, out=None, stream=None):
+        """Response compression: [..., L, N] residues mod q -> [..., keep, N] mod q_0 ... q_{keep-1}."""
+        x = _dev_u64(x, self.device)
+        lead = tuple(x.shape[:-2])
+        assert tuple(x.shape[-2:]) == (self.L, self.N)
+        count = int(np.prod(lead)) if lead else 1
+        if out is None:
+            out = self.empty(*lead, keep, self.N)
+        _check(lib().pir_mod_switch(self._h, _ptr(x), count, keep, _ptr(out), _stream(stream)))
         return out
 
     def load_key(self, rlk) -> Key:

@@ -57,6 +57,16 @@ struct CtxConst {
     ConvTable bq;                                // B -> q
 };
 
+// Modulus switching from q = q_0 ... q_{L-1} to q' = q_0 ... q_{keep-1} (response compression):
+// r = q / q'.  For x with residues x_i: [x]_r (centred) from the dropped limbs by the exact
+// conversion T (dropped -> kept), then x' = (x_j - [x]_r) r^{-1} mod q_j = round(x / r).
+struct SwitchConst {
+    uint32_t keep, L;
+    ConvTable T;                                 // {q_keep..q_{L-1}} -> {q_0..q_{keep-1}}
+    uint64_t yc[MAX_L], ycq[MAX_L];              // [(r / q_i)^{-1}]_{q_i} for dropped i (index i - keep)
+    uint64_t rinv[MAX_L], rinvq[MAX_L];          // [r^{-1}]_{q_j} for kept j
+};
+
 // Operand reference of a tree node: a query ciphertext (leaf) or a level-1 product (node).
 constexpr uint32_t REF_NODE = 0x80000000u;
 

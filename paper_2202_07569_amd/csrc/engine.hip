@@ -80,6 +80,7 @@ struct pir_ctx {
     };
     std::map<std::string, ProfAcc> prof_acc;
     std::map<std::pair<uint32_t, uint32_t>, uint64_t*> binom;  // (m, k) -> device table
+    std::map<uint32_t, cw::SwitchConst*> switches;            // keep -> device switch constants
 };
 
 struct pir_key {
@@ -325,6 +326,7 @@ extern "C" void pir_free(pir_ctx* ctx) {
     }
     for (auto& kv : ctx->ws) dev_free(ctx, kv.second.p, kv.second.bytes);
     for (auto& kv : ctx->binom) (void)hipFree(kv.second);
+    for (auto& kv : ctx->switches) dev_free(ctx, kv.second, sizeof(cw::SwitchConst));
     dev_free(ctx, ctx->dK, sizeof(CtxConst));
     dev_free(ctx, ctx->dtw, (size_t)ctx->LL * 4 * ctx->N * 8);
     if (ctx->dtwf) dev_free(ctx, ctx->dtwf, (size_t)ctx->LL * 4 * ctx->N * 8);
@@ -1665,5 +1667,33 @@ extern "C" int pir_expand(pir_ctx* ctx, const pir_key* const* gkeys, uint32_t c,
         std::swap(A, B);
     }
     CW_HIP(ctx, hipMemcpyAsync(query, A, (size_t)m * ct * 8, hipMemcpyDeviceToDevice, st));
+    return end_async(ctx, st);
+}
+
+// ------------------------------------------------------------------------------------------------
+// response compression (modulus switching)
+// ------------------------------------------------------------------------------------------------
+extern "C" int pir_mod_switch(pir_ctx* ctx, const uint64_t* in, uint32_t count, uint32_t keep, uint64_t* out,
+                              void* stream) {
+    CW_ENTER(ctx);
+    if (count && (!in || !out)) return fail(PIR_E_INVALID, "null argument");
+    if (keep < 1 || keep > ctx->L) return fail(PIR_E_INVALID, "keep must be in [1, L]");
+    if (in == out) return fail(PIR_E_INVALID, "in and out must not overlap");
+    hipStream_t st = (hipStream_t)stream;
+    CW_TRY(begin_async(ctx, st));
+    cw::SwitchConst*& dS = ctx->switches[keep];
+    if (!dS) {
+        cw::SwitchConst S;
+        cw::host::build_switch(S, std::vector<uint64_t>(ctx->primes.begin(), ctx->primes.begin() + ctx->L), keep);
+        CW_TRY(dev_alloc(ctx, (void**)&dS, sizeof(S)));
+        CW_HIP(ctx, hipMemcpy(dS, &S, sizeof(S), hipMemcpyHostToDevice));
+    }
+    Launch lc = make_launch(ctx, st);
+    const size_t N = ctx->N, per = std::max<size_t>(1, ctx->fix_cap / N);  // polynomials per launch
+    Prof pr(ctx, "mod_switch", st, (double)count * N);
+    for (size_t p0 = 0; p0 < count; p0 += per) {
+        const size_t n = std::min<size_t>(per, count - p0);
+        cw::launch_mod_switch(lc, dS, keep, in + p0 * ctx->L * N, n, out + p0 * keep * N);
+    }
     return end_async(ctx, st);
 }

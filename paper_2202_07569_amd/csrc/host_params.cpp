@@ -200,6 +200,24 @@ void build_const(CtxConst& K, uint32_t N, const std::vector<uint64_t>& q, const 
     build_conv(K.bq, B, q);
 }
 
+void build_switch(SwitchConst& S, const std::vector<uint64_t>& q, uint32_t keep) {
+    std::memset(&S, 0, sizeof(S));
+    S.keep = keep;
+    S.L = (uint32_t)q.size();
+    const std::vector<uint64_t> kept(q.begin(), q.begin() + keep), dropped(q.begin() + keep, q.end());
+    if (dropped.empty()) return;
+    build_conv(S.T, dropped, kept);
+    for (size_t i = 0; i < dropped.size(); ++i) {
+        S.yc[i] = invmod(mw_mod(mw_prod(dropped, (int)i), dropped[i]), dropped[i]);
+        S.ycq[i] = shoup(S.yc[i], dropped[i]);
+    }
+    const MW r = mw_prod(dropped);
+    for (size_t j = 0; j < kept.size(); ++j) {
+        S.rinv[j] = invmod(mw_mod(r, kept[j]), kept[j]);
+        S.rinvq[j] = shoup(S.rinv[j], kept[j]);
+    }
+}
+
 static uint32_t bitrev(uint32_t x, uint32_t logn) {
     uint32_t r = 0;
     for (uint32_t b = 0; b < logn; ++b)

@@ -29,6 +29,8 @@ void build_twiddles(std::vector<uint64_t>& tw, const std::vector<uint64_t>& prim
 void build_twiddles_fp(std::vector<double>& twf, const std::vector<uint64_t>& tw, const std::vector<uint64_t>& primes,
                        uint32_t N);
 std::vector<uint64_t> binom_table(uint32_t m, uint32_t k);
+// Constants of the switch from q to its first `keep` primes.
+void build_switch(SwitchConst& S, const std::vector<uint64_t>& q, uint32_t keep);
 
 }  // namespace host
 }  // namespace cw

@@ -81,6 +81,10 @@ void launch_expand_stage(const Launch& lc, const uint64_t* cts, uint32_t c, uint
                          uint64_t* staging);
 void launch_expand_combine(const Launch& lc, const uint64_t* src, const uint64_t* sub, uint32_t c, uint32_t a,
                            uint32_t h, uint64_t* dst);
+// Modulus switching of `polys` polynomials [polys][L][N] -> [polys][keep][N] (coefficient form),
+// x' = round(x q' / q) on centred representatives; S is a device copy of the switch constants.
+void launch_mod_switch(const Launch& lc, const SwitchConst* S, uint32_t keep, const uint64_t* in, size_t polys,
+                       uint64_t* out);
 // Row gather: dst row e = src row order[e] for e < n, rows of `row` uint16 (a multiple of 8).
 void launch_gather_rows(hipStream_t st, const uint16_t* src, const uint64_t* order, uint64_t n, size_t row,
                         uint16_t* dst);

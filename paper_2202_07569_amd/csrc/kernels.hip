@@ -1399,6 +1399,76 @@ void launch_expand_combine(const Launch& lc, const uint64_t* src, const uint64_t
                        lc.K, src, sub, c, a, E, dst);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Modulus switching (response compression): one thread per coefficient.  [x]_r centred comes from
+// the dropped limbs by the exact conversion (fast rounding decision, exact fallback in the fixup
+// kernel), then x' = (x_j - [x]_r) r^{-1} mod q_j for every kept limb.
+// ---------------------------------------------------------------------------------------------
+__device__ __forceinline__ bool switch_coeff(const CtxConst* K, const SwitchConst* S, const uint64_t* x,
+                                             uint64_t* y, bool exact, uint64_t* out, size_t os) {
+    const uint32_t N = K->N, keep = S->keep, nd = S->L - keep;
+    for (uint32_t i = 0; i < nd; ++i) {
+        const uint64_t p = K->p[keep + i];
+        y[i] = mul_shoup(x[(size_t)(keep + i) * N], S->yc[i], S->ycq[i], p);
+    }
+    bool amb = false;
+    const uint32_t v = exact ? conv_round_exact(S->T, y) : conv_round_fast<MAX_L>(S->T, y, nd, amb);
+    for (uint32_t j = 0; j < keep; ++j) {
+        const uint64_t p = K->p[j];
+        const uint64_t xr = conv_out<MAX_L>(S->T, y, nd, v, j);  // [x]_r mod q_j
+        out[(size_t)j * os] = mul_shoup(sub_mod(x[(size_t)j * N], xr, p), S->rinv[j], S->rinvq[j], p);
+    }
+    return amb;
+}
+
+__global__ void k_mod_switch(const CtxConst* __restrict__ K, const SwitchConst* __restrict__ S,
+                             const uint64_t* __restrict__ in, size_t polys, uint64_t* __restrict__ out,
+                             uint64_t* fix, uint32_t* fixcnt) {
+    const uint32_t N = K->N, L = K->L, keep = S->keep;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= polys * N) return;
+    const size_t poly = gid / N, c = gid % N;
+    uint64_t y[MAX_L];
+    if (switch_coeff(K, S, in + poly * L * N + c, y, false, out + poly * keep * N + c, N))
+        fix[atomicAdd(fixcnt, 1u)] = gid;
+}
+
+__global__ void k_mod_switch_fix(const CtxConst* __restrict__ K, const SwitchConst* __restrict__ S,
+                                 const uint64_t* __restrict__ in, uint64_t* __restrict__ out, uint64_t* fix,
+                                 uint32_t* fixcnt) {
+    const uint32_t N = K->N, L = K->L, keep = S->keep;
+    const uint32_t n = *fixcnt;
+    for (uint32_t f = threadIdx.x; f < n; f += blockDim.x) {
+        const size_t gid = fix[f];
+        const size_t poly = gid / N, c = gid % N;
+        uint64_t y[MAX_L];
+        switch_coeff(K, S, in + poly * L * N + c, y, true, out + poly * keep * N + c, N);
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *fixcnt = 0;
+}
+
+__global__ void k_copy_limbs(const uint64_t* __restrict__ in, size_t polys, uint32_t L, uint32_t keep, uint32_t N,
+                             uint64_t* __restrict__ out) {
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= polys * keep * N) return;
+    const size_t poly = gid / ((size_t)keep * N), r = gid % ((size_t)keep * N);
+    out[gid] = in[poly * L * N + r];
+}
+
+void launch_mod_switch(const Launch& lc, const SwitchConst* S, uint32_t keep, const uint64_t* in, size_t polys,
+                       uint64_t* out) {
+    if (!polys) return;
+    if (keep == lc.L) {  // nothing dropped: the identity
+        hipLaunchKernelGGL(k_copy_limbs, dim3(blocks_for(polys * keep * lc.N)), dim3(EW_THREADS), 0, lc.stream, in,
+                           polys, lc.L, keep, lc.N, out);
+        return;
+    }
+    hipLaunchKernelGGL(k_mod_switch, dim3(blocks_for(polys * lc.N)), dim3(EW_THREADS), 0, lc.stream, lc.K, S, in, polys,
+                       out, lc.fix, lc.fixcnt);
+    hipLaunchKernelGGL(k_mod_switch_fix, dim3(1), dim3(256), 0, lc.stream, lc.K, S, in, out, lc.fix, lc.fixcnt);
+}
+
 // dst row e = src row order[e], rows of `row` uint16 (a multiple of 8), copied in 16-byte words.
 __global__ void k_gather_rows(const uint16_t* __restrict__ src, const uint64_t* __restrict__ order, uint64_t n,
                               size_t row, uint16_t* __restrict__ dst) {
