@@ -58,6 +58,7 @@ def lib():
             "orc_galois_keygen": (None, [vp, P8, u32, P64, P64, P64]),
             "orc_sub": (None, [vp, vp, P64, u32, P64]),
             "orc_mod_switch": (None, [vp, P64, u32, u32, P64]),
+            "orc_one_minus": (None, [vp, P64, P64]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -242,6 +243,13 @@ class Oracle:
         ct = np.ascontiguousarray(ct, dtype=np.uint64)
         out = np.empty(self.ct_shape(2), dtype=np.uint64)
         lib().orc_sub(self._h, gk._h, _ptr(ct), int(g), _ptr(out))
+        return out
+
+    def one_minus(self, ct: np.ndarray) -> np.ndarray:
+        """The plaintext constant 1 minus the ciphertext: (Delta - c0, -c1) mod q."""
+        ct = np.ascontiguousarray(ct, dtype=np.uint64)
+        out = np.empty_like(ct)
+        lib().orc_one_minus(self._h, _ptr(ct), _ptr(out))
         return out
 
     def mod_switch(self, ct: np.ndarray, keep: int) -> np.ndarray:

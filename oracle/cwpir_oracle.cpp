@@ -818,4 +818,18 @@ void orc_mod_switch(const OrcCtx* c, const uint64_t* in, uint32_t npoly, uint32_
         }
 }
 
+// ---- folklore PIR (Section 2.4, the plain folklore equality operator) ------------------------------
+// 1 - ct: the plaintext constant 1 minus a ciphertext, (Delta - c0, -c1) mod q.  in/out [2][L][N].
+void orc_one_minus(const OrcCtx* c, const uint64_t* ct, uint64_t* out) {
+    const uint32_t N = c->N, L = c->L;
+    for (uint32_t j = 0; j < L; ++j) {
+        const uint64_t p = c->qp[j];
+        for (uint32_t x = 0; x < N; ++x) {
+            const uint64_t c0 = ct[(size_t)j * N + x], c1 = ct[(size_t)(L + j) * N + x];
+            out[(size_t)j * N + x] = subm(x == 0 ? c->delta_r[j] : 0, c0, p);
+            out[(size_t)(L + j) * N + x] = subm(0, c1, p);
+        }
+    }
+}
+
 }  // extern "C"
