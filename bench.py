@@ -212,6 +212,7 @@ def main():
         raise SystemExit("the batched answer of query 0 differs from the plain answer")
 
     expansion = expansion_bench(args, ctx, cfg, torch, stream)
+    folklore = folklore_bench(args, cfg, torch, stream) if args.workload == "mid" else None
 
     fp = cfg.N <= 8192 and all(p < FP_PRIME_BOUND for p in tuple(cfg.primes) + ctx.aux_primes)
     roof = roofline(prof, args.steps, fp, traffic_table(cfg, n, B, ctx.schedule())) if prof else None
@@ -238,6 +239,7 @@ def main():
                         "ms_per_query": t_graph / args.steps * 1e3, **lat(per_graph)},
         "batched": {"value": value, "ms_per_step": ms_step, **lat(per_b)},
         "expansion": expansion,
+        "folklore": folklore,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -335,6 +337,43 @@ def expansion_bench(args, ctx, cfg, torch, stream):
     log(f"expansion c={c} h={h} m={cfg.m}: {np.median(per) * 1e3:.2f} ms")
     return {"c": c, "packed_ciphertexts": h, "m": cfg.m, "substitutions": h * ((1 << c) - 1),
             "ms_median": float(np.median(per) * 1e3), "ms_p99": float(np.percentile(per, 99) * 1e3)}
+
+
+def folklore_bench(args, cfg, torch, stream):
+    """Folklore PIR (plain folklore operator) on the same parameters and database size: the query is
+    the l = ceil(log2 n) index bits, the server forms the 2l leaves (1 - x_i, x_i) and evaluates the
+    depth-ceil(log2 l) product per element with the memoised tree.  One query at a time."""
+    from paper_2202_07569_amd import Context
+    n = cfg.n
+    ell = max(1, (n - 1).bit_length())
+    j = np.arange(n, dtype=np.uint64)[:, None]
+    i = np.arange(ell, dtype=np.uint64)[None, :]
+    cw = (2 * i + ((j >> i) & np.uint64(1))).astype(np.uint32)  # leaf 2i + bit_i(j)
+    ctx = Context(cfg.N, cfg.primes, cfg.t)
+    key = ctx.load_key(datagen.uniform_residues(cfg.primes, (cfg.L, 2), cfg.N, seed=cfg.seed * 100 + 70))
+    db = ctx.encode_db(cw, datagen.payload(cfg, n), 2 * ell)
+    q = torch.from_numpy(datagen.uniform_residues(cfg.primes, (ell, 2), cfg.N, seed=cfg.seed * 100 + 71)).cuda()
+    out = ctx.empty(cfg.s, 2, cfg.L, cfg.N)
+
+    def one():
+        ctx.answer(key, db, ctx.folklore_leaves(q, stream=stream), out=out, stream=stream)
+
+    for _ in range(max(1, args.warmup)):
+        one()
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(max(3, args.steps)):
+        a = time.perf_counter()
+        one()
+        torch.cuda.synchronize()
+        per.append(time.perf_counter() - a)
+    t = float(np.median(per))
+    log(f"folklore l={ell} (k={ell}, {db.pair_count} shared nodes): {t * 1e3:.1f} ms/query -> {n / t:.0f} elements/s")
+    res = {"ell": ell, "shared_nodes": db.pair_count, "ms_per_query": t * 1e3, "elements_per_s": n / t,
+           "p99_ms": float(np.percentile(per, 99) * 1e3)}
+    db.close()
+    key.close()
+    return res
 
 
 # --------------------------------------------------------------------------------------------

@@ -18,8 +18,9 @@
  *   Relin  per-limb digits D_i = [c2]_{q_i} in [0, q_i):  (c0 + sum_i D_i b_i, c1 + sum_i D_i a_i);
  *   PM     plaintext coefficients in [0, t) taken as they are;
  *   selector of element j: product of the query ciphertexts at j's ascending one positions
- *          p_1 < ... < p_k, as the tree ((p1 p2)(p3 p4)) with an odd last factor carried up and a
- *          relinearization after every Mult; k = 1 gives the query ciphertext itself;
+ *          p_1 < ... < p_k, as the tree that pairs neighbours level by level ((p1 p2)(p3 p4)...),
+ *          carries an odd last factor up and relinearizes after every Mult; k = 1 gives the query
+ *          ciphertext itself;
  *   answer_r = sum_j PM(sel_j, P_{j,r}) mod q  for r in [s].
  *
  * Layouts (all little-endian uint64 residues in [0, q_i) unless stated):
@@ -64,7 +65,7 @@ extern "C" {
 #define PIR_E_UNSUPPORTED (-5) /* N not in {4096, 8192, 16384}, L or k out of range             */
 
 #define PIR_MAX_L 12           /* ciphertext primes */
-#define PIR_MAX_K 4            /* Hamming weight of the codewords (tree depth <= 2) */
+#define PIR_MAX_K 16           /* Hamming weight of the codewords (tree depth <= 4) */
 
 typedef struct pir_ctx pir_ctx;
 typedef struct pir_key pir_key;
@@ -79,7 +80,7 @@ typedef struct {
     uint64_t hbm_budget_bytes; /* cap on the library's own device allocations; 0 = no cap         */
     int32_t device;            /* HIP device ordinal                                              */
     uint32_t chunk_elems;      /* elements per processing chunk, 1..4096; 0 = default by N        */
-    uint64_t memo_bytes;       /* cap on HBM for level-1 products shared by a whole database
+    uint64_t memo_bytes;       /* cap on HBM for inner tree nodes shared by a whole database
                                   (k >= 3); above it they are shared within a chunk only;
                                   0 = default (a quarter of the budget, else 8 GiB)               */
 } pir_params;
@@ -94,7 +95,7 @@ int pir_load_key(pir_ctx* ctx, const uint64_t* rlk, pir_key** out);
 
 /* Setup (Section 3.3.1, "Put DB in plaintext format"; codewords precomputed there as well):
  * copy n elements of s plaintexts each, with their weight-k codewords of length m, into the
- * library's device memory and precompute the selection-vector schedule (shared level-1 products
+ * library's device memory and precompute the selection-vector schedule (shared inner tree nodes
  * for k >= 3).  codewords: host [n][k]; payload: host or dev uint16 [n][s][N].  Synchronous. */
 int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, uint32_t k, const uint32_t* codewords,
                   const uint16_t* payload, pir_db** out);
@@ -162,6 +163,13 @@ void pir_serve_close(pir_server* srv);
 int pir_load_galois_key(pir_ctx* ctx, uint32_t galois_elt, const uint64_t* gk, pir_key** out);
 int pir_expand(pir_ctx* ctx, const pir_key* const* gkeys, uint32_t c, const uint64_t* packed, uint32_t h, uint32_t m,
                uint64_t* query, void* stream);
+
+/* Folklore PIR (Section 2.4, the plain folklore equality operator f_PF): the client sends the
+ * l = ceil(log2 n) bits of the target index, one ciphertext per bit (query dev [l][2][L][N]); the
+ * server forms the 2l leaves (out dev [2l][2][L][N]): leaf 2i = 1 - x_i = (Delta - c0, -c1),
+ * Delta = floor(q/t), and leaf 2i + 1 = x_i.  With element j's codeword {2i + bit_i(j)} (weight l,
+ * length 2l) pir_answer then evaluates f_PF as the product tree above.  Asynchronous. */
+int pir_folklore_leaves(pir_ctx* ctx, const uint64_t* query, uint32_t ell, uint64_t* out, void* stream);
 
 /* Response compression (the modulus switching of responses that the paper takes over from SealPIR,
  * Section 2.2): `count` polynomials in (dev [count][L][N], e.g. an answer [s][2][L][N] as 2s
@@ -245,7 +253,7 @@ int pir_autotune(pir_ctx* ctx, uint32_t batch, uint32_t k, uint32_t s, pir_sched
 /* Introspection. */
 uint32_t pir_ctx_aux_primes(const pir_ctx* ctx, uint64_t* out_primes /* may be NULL */);
 uint64_t pir_ctx_device_bytes(const pir_ctx* ctx);       /* bytes the library holds on the device */
-uint64_t pir_db_pair_count(const pir_db* db);            /* distinct level-1 products (k >= 3)    */
+uint64_t pir_db_pair_count(const pir_db* db);            /* distinct inner tree nodes (k >= 3)    */
 
 /* Kernel timing with HIP events on the launching stream.  When enabled, every kernel family's
  * launch is bracketed by events; pir_profile_read synchronises on them and returns, per family,

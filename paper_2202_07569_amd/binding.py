@@ -23,6 +23,7 @@ EXPORTS = [
     "pir_last_error", "pir_serve_open", "pir_serve_submit", "pir_serve_step", "pir_serve_poll", "pir_serve_stats",
     "pir_serve_close", "pir_get_schedule", "pir_set_schedule", "pir_autotune", "pir_graph_capture",
     "pir_graph_launch", "pir_graph_free", "pir_load_galois_key", "pir_expand", "pir_mod_switch",
+    "pir_folklore_leaves",
 ]
 
 
@@ -102,6 +103,7 @@ def lib():
             "pir_load_galois_key": (i32, [vp, u32, vp, pp]),
             "pir_expand": (i32, [vp, pp, u32, vp, u32, u32, vp, vp]),
             "pir_mod_switch": (i32, [vp, vp, u32, u32, vp, vp]),
+            "pir_folklore_leaves": (i32, [vp, vp, u32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -264,6 +266,15 @@ class Context:
             out = self.empty(m, 2, self.L, self.N)
         arr = (ctypes.c_void_p * max(1, c))(*([k._h.value for k in gkeys[:c]] or [None]))
         _check(lib().pir_expand(self._h, arr, c, _ptr(packed), h, m, _ptr(out), _stream(stream)))
+        return out
+
+    def folklore_leaves(self, query, out=None, stream=None):
+        """Folklore PIR: the l query bits [l][2][L][N] -> the 2l leaves (1 - x_i, x_i)."""
+        query = _dev_u64(query, self.device)
+        ell = query.shape[0]
+        if out is None:
+            out = self.empty(2 * ell, 2, self.L, self.N)
+        _check(lib().pir_folklore_leaves(self._h, _ptr(query), ell, _ptr(out), _stream(stream)))
         return out
 
     def mod_switch(self, x, keep: int, out=None, stream=None):

@@ -49,10 +49,14 @@ struct CtxConst {
     double pd[MAX_LL], pinv[MAX_LL];             // p and 1/p as doubles (fp64 transform)
     double ninvd[MAX_LL], ninvdq[MAX_LL];        // N^{-1} mod p and (N^{-1} mod p)/p as doubles
     uint64_t qinv[MAX_L], qinvq[MAX_L];          // [(q/q_i)^{-1}]_{q_i}
+    uint64_t delta[MAX_L];                       // Delta = floor(q/t) mod q_i
     uint64_t tqinv[MAX_L], tqinvq[MAX_L];        // [t (q/q_i)^{-1}]_{q_i}
     uint64_t kb1[MAX_LB], kb1q[MAX_LB];          // [t q^{-1} (B/b_j)^{-1}]_{b_j}
     uint64_t kb2[MAX_LB], kb2q[MAX_LB];          // [q^{-1} (B/b_j)^{-1}]_{b_j}
     double tqinvd[MAX_L], kb1d[MAX_LB], kb2d[MAX_LB];  // the same constants as doubles (fp64 path)
+    // fp64 scale with the key constant folded into the Q -> B conversion:
+    //   z_j = kb1_j x_j + sum_i y_i [-kb2_j (q/q_i)]_{b_j} + v [kb2_j q]_{b_j}   (mod b_j)
+    double fqbd[MAX_L][MAX_LB], fqpd[MAX_LB];
     ConvTable qb;                                // q -> B
     ConvTable bq;                                // B -> q
 };
@@ -67,7 +71,7 @@ struct SwitchConst {
     uint64_t rinv[MAX_L], rinvq[MAX_L];          // [r^{-1}]_{q_j} for kept j
 };
 
-// Operand reference of a tree node: a query ciphertext (leaf) or a level-1 product (node).
+// Operand reference of a tree node: a query ciphertext (leaf) or a memoised inner node.
 constexpr uint32_t REF_NODE = 0x80000000u;
 
 }  // namespace cw

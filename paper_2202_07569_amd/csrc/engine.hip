@@ -3,8 +3,9 @@
 // One answer (Section 3.3.3) runs as:
 //   1. query residency: every query ciphertext is extended exactly from Q to Q u B and
 //      transformed (once per query);
-//   2. per group of elements: the distinct level-1 products of the group (k >= 3) are computed
-//      once — Mult + Relin, then extended and transformed again — and kept in HBM;
+//   2. per group of elements: the distinct inner nodes of the elements' product trees (k >= 3) are
+//      computed once, depth by depth — Mult + Relin, then extended and transformed again — and
+//      kept in HBM;
 //   3. per chunk of E elements: the root Mult + Relin of each element's tree gives its selector
 //      (transformed over Q); the chunk's payload rows are lifted and transformed once and
 //      multiplied into the accumulators of every query scanning this database;
@@ -92,7 +93,8 @@ struct pir_key {
 
 struct Group {
     uint64_t e0 = 0, ne = 0;   // element range
-    uint32_t p0 = 0, np = 0;   // pair range in the pair table
+    uint32_t p0 = 0, np = 0;   // node range in the node table
+    std::vector<uint32_t> level_end;  // end of each depth's nodes, relative to p0
 };
 
 struct pir_db {
@@ -407,44 +409,60 @@ extern "C" void pir_key_free(pir_key* key) {
 // ------------------------------------------------------------------------------------------------
 // database
 // ------------------------------------------------------------------------------------------------
-// Tree of element j (leaves = ascending positions): k=1 leaf; k=2 (p1 p2); k=3 ((p1 p2) p3);
-// k=4 ((p1 p2)(p3 p4)).  Level-1 products depend only on their two positions, so equal pairs
-// are computed once per group.
+// Product tree of one element (leaves = its ascending positions): each level pairs neighbours
+// (0,1), (2,3), ... into Mult+Relin nodes and carries an odd last operand up unchanged, until two
+// operands remain, the root's (k = 1: the leaf itself).  k=2 (p1 p2); k=3 ((p1 p2) p3);
+// k=4 ((p1 p2)(p3 p4)); k=5 (((p1 p2)(p3 p4)) p5); ...  A non-root node depends only on its two
+// operands, so equal nodes are computed once per group.  Nodes are listed by depth (a node's
+// operands are leaves or nodes of smaller depth), and level_end marks where each depth ends.
 struct PlanBuild {
-    std::vector<uint32_t> pairs;  // [np][2]
-    std::vector<uint32_t> refs;   // [ne][2]
+    std::vector<uint32_t> pairs;      // [np][2] operand refs (leaf position, or REF_NODE | node)
+    std::vector<uint32_t> level_end;  // end of each depth's nodes in `pairs`
+    std::vector<uint32_t> refs;       // [ne][2] root operands
 };
 
 static void plan_elements(const uint32_t* cw, uint64_t e0, uint64_t ne, uint32_t k, PlanBuild& pb) {
     std::unordered_map<uint64_t, uint32_t> ids;
-    auto pair_id = [&](uint32_t a, uint32_t b) {
-        uint64_t key = ((uint64_t)a << 32) | b;
+    std::vector<uint32_t> ops, depth, roots;
+    auto dep = [&](uint32_t r) -> uint32_t { return (r & cw::REF_NODE) ? depth[r & ~cw::REF_NODE] : 0u; };
+    auto node = [&](uint32_t a, uint32_t b) -> uint32_t {
+        const uint64_t key = ((uint64_t)a << 32) | b;
         auto it = ids.find(key);
-        if (it != ids.end()) return it->second;
-        uint32_t id = (uint32_t)(pb.pairs.size() / 2);
-        pb.pairs.push_back(a);
-        pb.pairs.push_back(b);
+        if (it != ids.end()) return it->second | cw::REF_NODE;
+        const uint32_t id = (uint32_t)depth.size();
+        ops.push_back(a);
+        ops.push_back(b);
+        depth.push_back(std::max(dep(a), dep(b)) + 1);
         ids.emplace(key, id);
-        return id;
+        return id | cw::REF_NODE;
     };
+    std::vector<uint32_t> lvl, nxt;
+    roots.reserve(2 * ne);
     for (uint64_t e = e0; e < e0 + ne; ++e) {
-        const uint32_t* p = cw + e * k;
-        uint32_t ra = 0, rb = 0;
-        if (k == 1) {
-            ra = p[0];
-        } else if (k == 2) {
-            ra = p[0];
-            rb = p[1];
-        } else if (k == 3) {
-            ra = pair_id(p[0], p[1]) | cw::REF_NODE;
-            rb = p[2];
-        } else {
-            ra = pair_id(p[0], p[1]) | cw::REF_NODE;
-            rb = pair_id(p[2], p[3]) | cw::REF_NODE;
+        lvl.assign(cw + e * k, cw + e * k + k);
+        while (lvl.size() > 2) {
+            nxt.clear();
+            for (size_t i = 0; i + 1 < lvl.size(); i += 2) nxt.push_back(node(lvl[i], lvl[i + 1]));
+            if (lvl.size() % 2) nxt.push_back(lvl.back());
+            lvl.swap(nxt);
         }
-        pb.refs.push_back(ra);
-        pb.refs.push_back(rb);
+        roots.push_back(lvl[0]);
+        roots.push_back(lvl.size() == 2 ? lvl[1] : 0u);
     }
+    // list the nodes by depth and renumber
+    const uint32_t nn = (uint32_t)depth.size();
+    std::vector<uint32_t> order(nn), newid(nn);
+    for (uint32_t i = 0; i < nn; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](uint32_t x, uint32_t y) { return depth[x] < depth[y]; });
+    for (uint32_t r = 0; r < nn; ++r) newid[order[r]] = r;
+    auto remap = [&](uint32_t r) { return (r & cw::REF_NODE) ? (newid[r & ~cw::REF_NODE] | cw::REF_NODE) : r; };
+    pb.pairs.reserve(2 * (size_t)nn);
+    for (uint32_t r = 0; r < nn; ++r) {
+        pb.pairs.push_back(remap(ops[2 * (size_t)order[r]]));
+        pb.pairs.push_back(remap(ops[2 * (size_t)order[r] + 1]));
+        if (r + 1 == nn || depth[order[r + 1]] != depth[order[r]]) pb.level_end.push_back(r + 1);
+    }
+    for (uint32_t r : roots) pb.refs.push_back(remap(r));
 }
 
 static size_t node_bytes(const pir_ctx* ctx) { return (size_t)2 * ctx->LL * ctx->N * 8; }
@@ -489,7 +507,7 @@ extern "C" int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, u
     CW_ENTER(ctx);
     if (!out) return fail(PIR_E_INVALID, "null argument");
     *out = nullptr;
-    if (k < 1 || k > PIR_MAX_K) return fail(PIR_E_UNSUPPORTED, "k must be in [1, 4]");
+    if (k < 1 || k > PIR_MAX_K) return fail(PIR_E_UNSUPPORTED, "k must be in [1, 16]");
     if (s < 1 || m < k || m >= 0x7fffffffu) return fail(PIR_E_INVALID, "bad s or m");
     if (n && (!codewords || !payload)) return fail(PIR_E_INVALID, "null argument");
     if (n > (1ull << 40)) return fail(PIR_E_INVALID, "n too large");
@@ -511,8 +529,8 @@ extern "C" int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, u
     db->cw.assign(codewords, codewords + n * k);
     // Internal element order: ascending codewords.  The answer is a sum over all elements, so the
     // order does not change it; sorted, consecutive elements share their first operand (a query
-    // ciphertext for k = 2, a level-1 product for k = 4), which then stays in cache, and a chunk
-    // touches fewer distinct level-1 products.
+    // ciphertext for k = 2, a tree node for k >= 3), which then stays in cache, and a chunk
+    // touches fewer distinct tree nodes.
     std::vector<uint64_t> order(n);
     for (uint64_t e = 0; e < n; ++e) order[e] = e;
     std::stable_sort(order.begin(), order.end(), [&](uint64_t a, uint64_t b) {
@@ -521,7 +539,7 @@ extern "C" int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, u
     });
     std::vector<uint32_t> scw(n * k);
     for (uint64_t e = 0; e < n; ++e) std::memcpy(&scw[e * k], codewords + order[e] * k, (size_t)k * 4);
-    // schedule: one group sharing all level-1 products when they fit the memo budget, else one
+    // schedule: one group sharing all tree nodes when they fit the memo budget, else one
     // group per chunk of elements
     const uint32_t E = ctx->chunk;
     PlanBuild all;
@@ -535,6 +553,7 @@ extern "C" int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, u
         g.ne = n;
         g.p0 = 0;
         g.np = (uint32_t)np_all;
+        g.level_end = all.level_end;
         db->groups.push_back(g);
         pb = std::move(all);
     } else {
@@ -546,6 +565,7 @@ extern "C" int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, u
             PlanBuild local;
             plan_elements(scw.data(), e0, g.ne, k, local);
             g.np = (uint32_t)(local.pairs.size() / 2);
+            g.level_end = local.level_end;
             pb.pairs.insert(pb.pairs.end(), local.pairs.begin(), local.pairs.end());
             pb.refs.insert(pb.refs.end(), local.refs.begin(), local.refs.end());
             db->groups.push_back(g);
@@ -622,7 +642,7 @@ struct QState {
     const uint64_t* query = nullptr;  // caller's [m][2][L][N]
     uint64_t* answer = nullptr;       // caller's [s][2][L][N]; accumulates in the transformed domain
     uint64_t* QX = nullptr;           // resident query [m][2][LL][N]
-    uint64_t* nodes = nullptr;        // level-1 products [max_pairs][2][LL][N] (k >= 3)
+    uint64_t* nodes = nullptr;        // memoised tree nodes [max_pairs][2][LL][N] (k >= 3)
     uint64_t* sel = nullptr;          // selectors [E][2][L][N]
 };
 
@@ -678,25 +698,30 @@ static cw::Batch one_query(uint32_t E, const uint64_t* leaves, const uint64_t* n
     return bt;
 }
 
-// Level-1 products of pairs[0..np) into nodes (extended, transformed), in chunks of E; `tmp` holds
-// E selectors.
-static void make_nodes(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint32_t* pairs, uint32_t np,
-                       const uint64_t* leaves, const pir_key* key, uint64_t* tmp, uint64_t* nodes, uint32_t E) {
+// Memoised tree nodes pairs[0..np) into nodes (extended, transformed), depth by depth (a node reads
+// nodes of smaller depth only), in chunks of E; `tmp` holds E selectors.
+static void make_nodes(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint32_t* pairs,
+                       const std::vector<uint32_t>& level_end, const uint64_t* leaves, const pir_key* key,
+                       uint64_t* tmp, uint64_t* nodes, uint32_t E) {
     const size_t N = ctx->N, L = ctx->L, LL = ctx->LL;
-    for (uint32_t p0 = 0; p0 < np; p0 += E) {
-        const uint32_t cnt = std::min(E, np - p0);
-        mult_relin(ctx, lc, b, pairs + 2 * (size_t)p0, one_query(cnt, leaves, nullptr, key, tmp));
-        {
-            Prof pr(ctx, "ntt_inv", lc.stream, bfly(ctx, (size_t)cnt * 2 * L));
-            cw::launch_ntt(lc, true, tmp, tmp, (size_t)cnt * 2 * L, L, 0);
+    uint32_t start = 0;
+    for (uint32_t end : level_end) {
+        for (uint32_t p0 = start; p0 < end; p0 += E) {
+            const uint32_t cnt = std::min(E, end - p0);
+            mult_relin(ctx, lc, b, pairs + 2 * (size_t)p0, one_query(cnt, leaves, nodes, key, tmp));
+            {
+                Prof pr(ctx, "ntt_inv", lc.stream, bfly(ctx, (size_t)cnt * 2 * L));
+                cw::launch_ntt(lc, true, tmp, tmp, (size_t)cnt * 2 * L, L, 0);
+            }
+            uint64_t* dst = nodes + (size_t)p0 * 2 * LL * N;
+            {
+                Prof pr(ctx, "extend", lc.stream, (double)2 * cnt * N);
+                cw::launch_extend(lc, tmp, dst, (size_t)2 * cnt);
+            }
+            Prof pr(ctx, "ntt_fwd", lc.stream, bfly(ctx, (size_t)cnt * 2 * LL));
+            cw::launch_ntt_operand(lc, dst, dst, (size_t)cnt * 2 * LL, LL, 0);
         }
-        uint64_t* dst = nodes + (size_t)p0 * 2 * LL * N;
-        {
-            Prof pr(ctx, "extend", lc.stream, (double)2 * cnt * N);
-            cw::launch_extend(lc, tmp, dst, (size_t)2 * cnt);
-        }
-        Prof pr(ctx, "ntt_fwd", lc.stream, bfly(ctx, (size_t)cnt * 2 * LL));
-        cw::launch_ntt_operand(lc, dst, dst, (size_t)cnt * 2 * LL, LL, 0);
+        start = end;
     }
 }
 
@@ -710,7 +735,7 @@ static void roots(pir_ctx* ctx, const Launch& lc, const Bufs& b, uint32_t k, con
     mult_relin(ctx, lc, b, refs, bt);
 }
 
-// Start an answer: resident query, zeroed accumulator and, when the database shares its level-1
+// Start an answer: resident query, zeroed accumulator and, when the database shares its tree
 // products across all elements, those products.
 static int prepare_query(pir_ctx* ctx, const Launch& lc, const Bufs& b, const pir_db* db, QState& qs) {
     CW_TRY(make_leaves(ctx, lc, qs.query, db->m, qs.QX));
@@ -719,7 +744,7 @@ static int prepare_query(pir_ctx* ctx, const Launch& lc, const Bufs& b, const pi
         cw::launch_fill(lc.stream, qs.answer, (size_t)db->s * 2 * ctx->L * ctx->N, 0);
     }
     if (db->groups.size() == 1 && db->groups[0].np)
-        make_nodes(ctx, lc, b, db->dpairs, db->groups[0].np, qs.QX, qs.key, qs.sel, qs.nodes, ctx->chunk);
+        make_nodes(ctx, lc, b, db->dpairs, db->groups[0].level_end, qs.QX, qs.key, qs.sel, qs.nodes, ctx->chunk);
     return check_launch(ctx);
 }
 
@@ -732,9 +757,9 @@ static int chunk_step(pir_ctx* ctx, const Launch& lc, const Bufs& b, const pir_d
     const uint32_t E = ctx->chunk, s = db->s, k = db->k;
     const uint64_t e0 = (uint64_t)c * E;
     const uint32_t cnt = (uint32_t)std::min<uint64_t>(E, db->n - e0);
-    if (db->groups.size() > 1 && db->groups[c].np)  // level-1 products shared within this chunk only
+    if (db->groups.size() > 1 && db->groups[c].np)  // tree nodes shared within this chunk only
         for (uint32_t q = 0; q < nq; ++q)
-            make_nodes(ctx, lc, b, db->dpairs + 2 * (size_t)db->groups[c].p0, db->groups[c].np, qs[q]->QX, qs[q]->key,
+            make_nodes(ctx, lc, b, db->dpairs + 2 * (size_t)db->groups[c].p0, db->groups[c].level_end, qs[q]->QX, qs[q]->key,
                        qs[q]->sel, qs[q]->nodes, E);
     const uint32_t* refs = db->drefs + 2 * e0;
     for (uint32_t q0 = 0; q0 < nq; q0 += ctx->qb) {
@@ -890,7 +915,7 @@ extern "C" int pir_selectors(pir_ctx* ctx, const pir_key* key, const pir_db* db,
         const uint32_t np = (uint32_t)(pb.pairs.size() / 2);
         if (np) {
             CW_TRY(ws_get_t(ctx, "sel_nodes", (size_t)np * 2 * LL * N, &nodes));
-            make_nodes(ctx, lc, b, dpairs, np, QX, key, sel, nodes, E);
+            make_nodes(ctx, lc, b, dpairs, pb.level_end, QX, key, sel, nodes, E);
         }
         roots(ctx, lc, b, k, drefs, one_query(cnt, QX, nodes, key, sel));
         cw::launch_ntt(lc, true, sel, out + (size_t)c0 * 2 * L * N, (size_t)cnt * 2 * L, L, 0);
@@ -1695,5 +1720,18 @@ extern "C" int pir_mod_switch(pir_ctx* ctx, const uint64_t* in, uint32_t count, 
         const size_t n = std::min<size_t>(per, count - p0);
         cw::launch_mod_switch(lc, dS, keep, in + p0 * ctx->L * N, n, out + p0 * keep * N);
     }
+    return end_async(ctx, st);
+}
+
+// ------------------------------------------------------------------------------------------------
+// folklore PIR leaves (Section 2.4, plain folklore operator)
+// ------------------------------------------------------------------------------------------------
+extern "C" int pir_folklore_leaves(pir_ctx* ctx, const uint64_t* query, uint32_t ell, uint64_t* out, void* stream) {
+    CW_ENTER(ctx);
+    if (ell && (!query || !out)) return fail(PIR_E_INVALID, "null argument");
+    if (ell > 64) return fail(PIR_E_INVALID, "ell must be at most 64");
+    hipStream_t st = (hipStream_t)stream;
+    CW_TRY(begin_async(ctx, st));
+    cw::launch_folklore_leaves(make_launch(ctx, st), query, ell, out);
     return end_async(ctx, st);
 }

@@ -176,6 +176,17 @@ void build_const(CtxConst& K, uint32_t N, const std::vector<uint64_t>& q, const 
         K.ninvdq[i] = (double)K.ninv[i] / (double)p;
     }
     MW Q = mw_prod(q), BB = mw_prod(B);
+    {
+        MW delta(Q.size(), 0);  // floor(Q / t) by long division in 64-bit digits
+        u128 rem = 0;
+        for (size_t w = Q.size(); w-- > 0;) {
+            const u128 cur = (rem << 64) | Q[w];
+            delta[w] = (uint64_t)(cur / t);
+            rem = cur % t;
+        }
+        mw_trim(delta);
+        for (uint32_t i = 0; i < K.L; ++i) K.delta[i] = mw_mod(delta, q[i]);
+    }
     for (uint32_t i = 0; i < K.L; ++i) {
         uint64_t p = q[i];
         uint64_t qhat = mw_mod(mw_prod(q, (int)i), p);
@@ -198,6 +209,11 @@ void build_const(CtxConst& K, uint32_t N, const std::vector<uint64_t>& q, const 
     }
     build_conv(K.qb, q, B);
     build_conv(K.bq, B, q);
+    for (uint32_t j = 0; j < K.LB; ++j) {
+        const uint64_t b = B[j];
+        for (uint32_t i = 0; i < K.L; ++i) K.fqbd[i][j] = (double)mulmod(b - K.kb2[j], K.qb.M[i][j], b);
+        K.fqpd[j] = (double)mulmod(K.kb2[j], K.qb.Pm[j], b);
+    }
 }
 
 void build_switch(SwitchConst& S, const std::vector<uint64_t>& q, uint32_t keep) {

@@ -24,7 +24,7 @@ constexpr int MAX_QB = 8;
 struct Batch {
     uint32_t nq, E;
     const uint64_t* leaves[MAX_QB];  // resident query [m][2][LL][N], operand format
-    const uint64_t* nodes[MAX_QB];   // level-1 products [pairs][2][LL][N] (or null), operand format
+    const uint64_t* nodes[MAX_QB];   // memoised tree nodes [pairs][2][LL][N] (or null), operand format
     const uint64_t* rlk[MAX_QB];     // transformed key [L][2][L][N], operand format
     uint64_t* sel[MAX_QB];           // selectors out [E][2][L][N], u64 residues
 };
@@ -85,6 +85,8 @@ void launch_expand_combine(const Launch& lc, const uint64_t* src, const uint64_t
 // x' = round(x q' / q) on centred representatives; S is a device copy of the switch constants.
 void launch_mod_switch(const Launch& lc, const SwitchConst* S, uint32_t keep, const uint64_t* in, size_t polys,
                        uint64_t* out);
+// Folklore leaves: out [2 ell][2][L][N] = (1 - x_i, x_i) for the query bits x_i [ell][2][L][N].
+void launch_folklore_leaves(const Launch& lc, const uint64_t* query, uint32_t ell, uint64_t* out);
 // Row gather: dst row e = src row order[e] for e < n, rows of `row` uint16 (a multiple of 8).
 void launch_gather_rows(hipStream_t st, const uint16_t* src, const uint64_t* order, uint64_t n, size_t row,
                         uint16_t* dst);

@@ -1082,14 +1082,15 @@ __device__ __forceinline__ bool scale_coeff(const CtxConst* K, const uint64_t* x
 
 // fp64 form (every prime below 2^50): the same conversions on signed representatives.  The
 // rounding decisions v, v2 come from double sums whose error is below 2^-45; a sum within 2^-40
-// of a half is reported as ambiguous and the exact integer form redoes the coefficient.  Partial
-// sums are reduced every four terms so every value stays below 2^53 (see fmulmod).
+// of a half is reported as ambiguous and the exact integer form redoes the coefficient.  The key
+// constant kb2 is folded into the Q -> B products (fqbd, fqpd), so z_j is one sum of L + 2 products;
+// every product is below 0.7 b in magnitude, so sums of up to 7 of them stay below 2^53 (b < 2^50)
+// and are reduced once.
 #pragma clang fp contract(off)
-// EX: the context has exactly NL ciphertext and NB auxiliary primes (every loop bound is then a
-// compile-time constant).
 template <int NL, int NB, bool EX>
 __device__ __forceinline__ bool scale_coeff_fp(const CtxConst* K, const uint64_t* x, size_t xs, uint64_t* cq) {
     const uint32_t L = EX ? NL : K->L, LB = EX ? NB : K->LB;
+    static_assert(!EX || (NL + 2 <= 7 && NB + 1 <= 7), "the single-reduction bound covers 7 products");
     double y[NL];
     double S = 0.0;
 #pragma unroll
@@ -1108,15 +1109,14 @@ __device__ __forceinline__ bool scale_coeff_fp(const CtxConst* K, const uint64_t
         if (j < (int)LB) {
             const uint32_t jj = L + j;
             const double b = K->pd[jj], binv = K->pinv[jj];
-            double rb = -fmulmod(v, K->qb.Pmd[j], b, binv);
+            double acc = fmulmod((double)x[jj * xs], K->kb1d[j], b, binv) + fmulmod(v, K->fqpd[j], b, binv);
 #pragma unroll
             for (int i = 0; i < NL; ++i)
                 if (i < (int)L) {
-                    rb += fmulmod(y[i], K->qb.Md[i][j], b, binv);
-                    if ((i & 3) == 3) rb = fred(rb, b, binv);
+                    acc += fmulmod(y[i], K->fqbd[i][j], b, binv);
+                    if (!EX && (i % 5) == 4) acc = fred(acc, b, binv);
                 }
-            const double zz = fmulmod((double)x[jj * xs], K->kb1d[j], b, binv) - fmulmod(rb, K->kb2d[j], b, binv);
-            z[j] = fred(zz, b, binv);
+            z[j] = fred(acc, b, binv);
             S2 += z[j] * binv;
         }
     const double v2 = __builtin_rint(S2);
@@ -1130,7 +1130,7 @@ __device__ __forceinline__ bool scale_coeff_fp(const CtxConst* K, const uint64_t
             for (int j = 0; j < NB; ++j)
                 if (j < (int)LB) {
                     c += fmulmod(z[j], K->bq.Md[j][i], p, pinv);
-                    if ((j & 3) == 3) c = fred(c, p, pinv);
+                    if (!EX && (j % 6) == 5) c = fred(c, p, pinv);
                 }
             cq[i] = fp_to_residue(fred(c, p, pinv), p);
         }
@@ -1315,6 +1315,7 @@ __global__ void k_accumulate(const CtxConst* __restrict__ K, const QueryPtrs qp,
     const uint64_t* sel = qp.sel[blockIdx.y];
     uint64_t* acc = qp.acc[blockIdx.y];
     uint64_t sum = acc[gid];
+#pragma unroll 8
     for (uint32_t e = 0; e < E; ++e) {
         const uint64_t a = sel[((size_t)e * 2 + poly) * LN + cj];
         const uint64_t b = Ph[((size_t)e * s + r) * LN + cj];
@@ -1467,6 +1468,27 @@ void launch_mod_switch(const Launch& lc, const SwitchConst* S, uint32_t keep, co
     hipLaunchKernelGGL(k_mod_switch, dim3(blocks_for(polys * lc.N)), dim3(EW_THREADS), 0, lc.stream, lc.K, S, in, polys,
                        out, lc.fix, lc.fixcnt);
     hipLaunchKernelGGL(k_mod_switch_fix, dim3(1), dim3(256), 0, lc.stream, lc.K, S, in, out, lc.fix, lc.fixcnt);
+}
+
+// Folklore leaves: leaf 2i = 1 - x_i = (Delta - c0, -c1) (Delta in coefficient 0 only), leaf 2i + 1 = x_i.
+__global__ void k_folklore_leaves(const CtxConst* __restrict__ K, const uint64_t* __restrict__ query, uint32_t ell,
+                                  uint64_t* __restrict__ out) {
+    const uint32_t N = K->N, L = K->L;
+    const size_t ct = (size_t)2 * L * N;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)ell * ct) return;
+    const size_t i = gid / ct, w = gid % ct;  // w = (poly * L + j) * N + c
+    const uint32_t c = (uint32_t)(w % N), j = (uint32_t)((w / N) % L), poly = (uint32_t)(w / ((size_t)L * N));
+    const uint64_t p = K->p[j], x = query[gid];
+    const uint64_t d = (poly == 0 && c == 0) ? K->delta[j] : 0;
+    out[(2 * i) * ct + w] = sub_mod(d, x, p);
+    out[(2 * i + 1) * ct + w] = x;
+}
+
+void launch_folklore_leaves(const Launch& lc, const uint64_t* query, uint32_t ell, uint64_t* out) {
+    if (!ell) return;
+    hipLaunchKernelGGL(k_folklore_leaves, dim3(blocks_for((size_t)ell * 2 * lc.L * lc.N)), dim3(EW_THREADS), 0,
+                       lc.stream, lc.K, query, ell, out);
 }
 
 // dst row e = src row order[e], rows of `row` uint16 (a multiple of 8), copied in 16-byte words.
