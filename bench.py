@@ -71,16 +71,19 @@ def parse():
     ap.add_argument("--serve", type=int, default=-1, choices=[-1, 0, 1],
                     help="also replay the batched-serving trace (4 resident databases, Poisson arrivals)")
     ap.add_argument("--serve-queries", type=int, default=256)
-    ap.add_argument("--serve-rates", default="2.0", help="arrival rates as multiples of 1/S (S: mean plain service time)")
+    ap.add_argument("--serve-rates", default="0.8", help="arrival rates as multiples of 1/S (S: mean plain service time)")
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--serve-only", action="store_true", help="skip the mid workload")
     return ap.parse_args()
 
 
+DISTINCT_QUERIES = 8  # larger batches reuse these query ciphertexts (the work does not depend on values)
+
+
 def synthetic_inputs(cfg, n, B):
     rlk = datagen.uniform_residues(cfg.primes, (cfg.L, 2), cfg.N, seed=cfg.seed * 100 + 1)
     queries = [datagen.uniform_residues(cfg.primes, (cfg.m, 2), cfg.N, seed=cfg.seed * 100 + 10 + b)
-               for b in range(B)]
+               for b in range(min(B, DISTINCT_QUERIES))]
     payload = datagen.payload(cfg, n)
     return rlk, queries, payload
 
@@ -153,6 +156,7 @@ def main():
     key, key_plain = ctx.load_key(rlk), ctx_plain.load_key(rlk)
     db, db_plain = ctx.encode_db(codewords, payload, cfg.m), ctx_plain.encode_db(codewords, payload, cfg.m)
     dq = [torch.from_numpy(q).cuda() for q in queries]
+    dq = [dq[b % len(dq)] for b in range(B)]
     outs = [ctx.empty(cfg.s, 2, cfg.L, cfg.N) for _ in range(B)]
     out_plain = ctx.empty(cfg.s, 2, cfg.L, cfg.N)
     stream = torch.cuda.current_stream()
@@ -213,6 +217,7 @@ def main():
 
     expansion = expansion_bench(args, ctx, cfg, torch, stream)
     folklore = folklore_bench(args, cfg, torch, stream) if args.workload == "mid" else None
+    arith = arith_bench(args, ctx, key, cfg, torch, stream) if args.workload == "mid" else None
 
     fp = cfg.N <= 8192 and all(p < FP_PRIME_BOUND for p in tuple(cfg.primes) + ctx.aux_primes)
     roof = roofline(prof, args.steps, fp, traffic_table(cfg, n, B, ctx.schedule())) if prof else None
@@ -240,6 +245,7 @@ def main():
         "batched": {"value": value, "ms_per_step": ms_step, **lat(per_b)},
         "expansion": expansion,
         "folklore": folklore,
+        "arith_equality": arith,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
@@ -337,6 +343,26 @@ def expansion_bench(args, ctx, cfg, torch, stream):
     log(f"expansion c={c} h={h} m={cfg.m}: {np.median(per) * 1e3:.2f} ms")
     return {"c": c, "packed_ciphertexts": h, "m": cfg.m, "substitutions": h * ((1 << c) - 1),
             "ms_median": float(np.median(per) * 1e3), "ms_p99": float(np.percentile(per, 99) * 1e3)}
+
+
+def arith_bench(args, ctx, key, cfg, torch, stream, m=37, k=4):
+    """Arithmetic constant-weight equality (Algorithm 2) on batch-encoded ciphertexts: N comparisons
+    per evaluation, for the paper's n = 2^16, k = 4 row (code length m = 37).  Synthetic uniform
+    residues stand in for the two encrypted codewords."""
+    x = torch.from_numpy(datagen.uniform_residues(cfg.primes, (m, 2), cfg.N, seed=cfg.seed * 100 + 80)).cuda()
+    y = torch.from_numpy(datagen.uniform_residues(cfg.primes, (m, 2), cfg.N, seed=cfg.seed * 100 + 81)).cuda()
+    out = ctx.empty(2, cfg.L, cfg.N)
+    for _ in range(max(1, args.warmup)):
+        ctx.arith_equality(key, x, y, k, out=out, stream=stream)
+    per = []
+    for _ in range(max(3, args.steps)):
+        a = time.perf_counter()
+        ctx.arith_equality(key, x, y, k, out=out, stream=stream)
+        torch.cuda.synchronize()
+        per.append(time.perf_counter() - a)
+    t = float(np.median(per))
+    log(f"arithmetic equality m={m} k={k}: {t * 1e3:.2f} ms per {cfg.N} comparisons")
+    return {"m": m, "k": k, "slots": cfg.N, "ms_per_evaluation": t * 1e3, "comparisons_per_s": cfg.N / t}
 
 
 def folklore_bench(args, cfg, torch, stream):
@@ -446,8 +472,8 @@ def serve_bench(args, torch):
             lat[i] = done - arr[i]
         return lat, done - arr[0]
 
-    def batched(arr):
-        srv = Server(ctx, max_slots=args.serve_slots)
+    def batched(arr, policy=Server.ROUND_ROBIN):
+        srv = Server(ctx, max_slots=args.serve_slots, policy=policy)
         lat = np.zeros(Q)
         live = {}
         i = nd = 0
@@ -488,14 +514,20 @@ def serve_bench(args, torch):
         lp, tp = plain(arr)
         log(f"rate {mult}/S: continuous batching")
         lb, tb, st = batched(arr)
+        log(f"rate {mult}/S: continuous batching, oldest first")
+        lf, tf, stf = batched(arr, Server.OLDEST_FIRST)
         pct = lambda x: {"p50_ms": float(np.percentile(x, 50) * 1e3),  # noqa: E731
                          "p99_ms": float(np.percentile(x, 99) * 1e3), "mean_ms": float(x.mean() * 1e3)}
         entry = {"rate_per_s": rate, "rate_over_S": mult,
                  "plain": {"elements_per_s": elems / tp, "wall_s": tp, **pct(lp)},
-                 "batched": {"elements_per_s": elems / tb, "wall_s": tb, **pct(lb), "rounds": st["rounds"]}}
+                 "batched": {"elements_per_s": elems / tb, "wall_s": tb, **pct(lb), "rounds": st["rounds"]},
+                 "batched_oldest_first": {"elements_per_s": elems / tf, "wall_s": tf, **pct(lf),
+                                          "rounds": stf["rounds"]}}
         log(f"rate {mult}/S: plain {entry['plain']['elements_per_s']:.0f} el/s p50 {entry['plain']['p50_ms']:.0f} "
             f"p99 {entry['plain']['p99_ms']:.0f} ms | batched {entry['batched']['elements_per_s']:.0f} el/s "
-            f"p50 {entry['batched']['p50_ms']:.0f} p99 {entry['batched']['p99_ms']:.0f} ms")
+            f"p50 {entry['batched']['p50_ms']:.0f} p99 {entry['batched']['p99_ms']:.0f} ms | oldest first "
+            f"{entry['batched_oldest_first']['elements_per_s']:.0f} el/s p50 {entry['batched_oldest_first']['p50_ms']:.0f} "
+            f"p99 {entry['batched_oldest_first']['p99_ms']:.0f} ms")
         res["rates"].append(entry)
     return res
 

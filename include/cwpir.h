@@ -137,6 +137,11 @@ int pir_answer_batch(pir_ctx* ctx, uint32_t B, const pir_key* const* keys, const
  *                     released ticket.
  *   pir_serve_stats   counters: rounds run, queries admitted, tickets released; slots in use and
  *                     queries waiting now.  Any output pointer may be NULL.
+ *   pir_serve_set_policy  which databases a round advances: PIR_SERVE_ROUND_ROBIN (default) every
+ *                     database with active queries by one chunk, so queries share the GPU (short
+ *                     queries finish early); PIR_SERVE_OLDEST_FIRST only the database of the oldest
+ *                     active query, whose later queries ride along (first come, first served, with
+ *                     batching).  Answers do not depend on the policy.
  *   pir_serve_close   wait for the server's queued work and release its slots and stream.
  * A server belongs to one context; calls on it are serialised with that context's other calls. */
 int pir_serve_open(pir_ctx* ctx, uint32_t max_slots, pir_server** out);
@@ -144,6 +149,9 @@ int pir_serve_submit(pir_server* srv, const pir_key* key, const pir_db* db, cons
                      uint64_t* answer, uint64_t* ticket);
 int pir_serve_step(pir_server* srv);
 int pir_serve_poll(pir_server* srv, uint64_t ticket);
+#define PIR_SERVE_ROUND_ROBIN 0
+#define PIR_SERVE_OLDEST_FIRST 1
+int pir_serve_set_policy(pir_server* srv, int policy);
 int pir_serve_stats(pir_server* srv, uint64_t* rounds, uint64_t* admitted, uint64_t* completed,
                     uint32_t* active, uint32_t* pending);
 void pir_serve_close(pir_server* srv);
@@ -170,6 +178,16 @@ int pir_expand(pir_ctx* ctx, const pir_key* const* gkeys, uint32_t c, const uint
  * Delta = floor(q/t), and leaf 2i + 1 = x_i.  With element j's codeword {2i + bit_i(j)} (weight l,
  * length 2l) pir_answer then evaluates f_PF as the product tree above.  Asynchronous. */
 int pir_folklore_leaves(pir_ctx* ctx, const uint64_t* query, uint32_t ell, uint64_t* out, void* stream);
+
+/* Arithmetic constant-weight equality (Section 3.1, Algorithm 2) between two encrypted codewords of
+ * CW(m, k): x, y dev [m][2][L][N], bit i of the codeword in ciphertext i (batch-encoded: every slot
+ * holds its own comparison).  out (dev [2][L][N]) encrypts e = (1/k!) prod_{i < k} (k' - i) with
+ * k' = sum_i x_i y_i: the m products (Mult, exact rounding) are summed and relinearized once, the
+ * factors k' - i (the plaintext constant i subtracted) are multiplied by the product tree above,
+ * and the result is multiplied by the plaintext constant (k!)^-1 mod t (k! invertible mod t).
+ * Returns after the result is computed (synchronous). */
+int pir_arith_equality(pir_ctx* ctx, const pir_key* key, const uint64_t* x, const uint64_t* y, uint32_t m, uint32_t k,
+                       uint64_t* out, void* stream);
 
 /* Response compression (the modulus switching of responses that the paper takes over from SealPIR,
  * Section 2.2): `count` polynomials in (dev [count][L][N], e.g. an answer [s][2][L][N] as 2s

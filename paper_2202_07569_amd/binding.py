@@ -23,7 +23,7 @@ EXPORTS = [
     "pir_last_error", "pir_serve_open", "pir_serve_submit", "pir_serve_step", "pir_serve_poll", "pir_serve_stats",
     "pir_serve_close", "pir_get_schedule", "pir_set_schedule", "pir_autotune", "pir_graph_capture",
     "pir_graph_launch", "pir_graph_free", "pir_load_galois_key", "pir_expand", "pir_mod_switch",
-    "pir_folklore_leaves",
+    "pir_folklore_leaves", "pir_arith_equality", "pir_serve_set_policy",
 ]
 
 
@@ -104,6 +104,8 @@ def lib():
             "pir_expand": (i32, [vp, pp, u32, vp, u32, u32, vp, vp]),
             "pir_mod_switch": (i32, [vp, vp, u32, u32, vp, vp]),
             "pir_folklore_leaves": (i32, [vp, vp, u32, vp, vp]),
+            "pir_arith_equality": (i32, [vp, vp, vp, vp, u32, u32, vp, vp]),
+            "pir_serve_set_policy": (i32, [vp, i32]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -266,6 +268,16 @@ class Context:
             out = self.empty(m, 2, self.L, self.N)
         arr = (ctypes.c_void_p * max(1, c))(*([k._h.value for k in gkeys[:c]] or [None]))
         _check(lib().pir_expand(self._h, arr, c, _ptr(packed), h, m, _ptr(out), _stream(stream)))
+        return out
+
+    def arith_equality(self, key: Key, x, y, k: int, out=None, stream=None):
+        """Algorithm 2: encrypted codewords x, y [m][2][L][N] of weight k -> e [2][L][N] (synchronous)."""
+        x, y = _dev_u64(x, self.device), _dev_u64(y, self.device)
+        assert x.shape == y.shape and tuple(x.shape[1:]) == (2, self.L, self.N)
+        if out is None:
+            out = self.empty(2, self.L, self.N)
+        _check(lib().pir_arith_equality(self._h, key._h, _ptr(x), _ptr(y), x.shape[0], k, _ptr(out),
+                                        _stream(stream)))
         return out
 
     def folklore_leaves(self, query, out=None, stream=None):
@@ -471,11 +483,15 @@ class Server:
     back the answer tensor.  The binding keeps each query and answer tensor alive until then.
     """
 
-    def __init__(self, ctx: Context, max_slots: int = 16):
+    ROUND_ROBIN, OLDEST_FIRST = 0, 1
+
+    def __init__(self, ctx: Context, max_slots: int = 16, policy: int = 0):
         self.ctx = ctx
         h = ctypes.c_void_p()
         _check(lib().pir_serve_open(ctx._h, max_slots, ctypes.byref(h)))
         self._h = h
+        if policy:
+            _check(lib().pir_serve_set_policy(h, policy))
         self._live = {}   # ticket -> (query, answer) while queued or running
         self._done = {}   # ticket -> answer once complete
 

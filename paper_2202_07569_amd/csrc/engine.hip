@@ -964,6 +964,7 @@ struct pir_server {
     std::deque<hipEvent_t> rounds;
     uint64_t next_ticket = 1;
     uint64_t n_rounds = 0, n_admitted = 0, n_completed = 0;
+    int policy = PIR_SERVE_ROUND_ROBIN;
 };
 
 extern "C" int pir_serve_open(pir_ctx* ctx, uint32_t max_slots, pir_server** out) {
@@ -1066,10 +1067,18 @@ extern "C" int pir_serve_step(pir_server* srv) {
     Bufs b;
     CW_TRY(get_bufs(ctx, ctx->chunk, ctx->qb, max_s, b));
     CW_TRY(serve_admit(srv, lc, b));
-    // one round: every database with active queries advances by one chunk
+    // one round: every database with active queries advances by one chunk (round robin), or only
+    // the database of the oldest active query (oldest first)
     std::vector<const pir_db*> dbs;
-    for (const ServeSlot& sl : srv->slots)
-        if (sl.used && std::find(dbs.begin(), dbs.end(), sl.db) == dbs.end()) dbs.push_back(sl.db);
+    if (srv->policy == PIR_SERVE_OLDEST_FIRST) {
+        const ServeSlot* oldest = nullptr;
+        for (const ServeSlot& sl : srv->slots)
+            if (sl.used && (!oldest || sl.ticket < oldest->ticket)) oldest = &sl;
+        if (oldest) dbs.push_back(oldest->db);
+    } else {
+        for (const ServeSlot& sl : srv->slots)
+            if (sl.used && std::find(dbs.begin(), dbs.end(), sl.db) == dbs.end()) dbs.push_back(sl.db);
+    }
     for (const pir_db* db : dbs) {
         std::vector<ServeSlot*> active;
         std::vector<QState*> qs;
@@ -1099,6 +1108,15 @@ extern "C" int pir_serve_step(pir_server* srv) {
     uint32_t busy = (uint32_t)srv->pending.size();
     for (const ServeSlot& sl : srv->slots) busy += sl.used ? 1 : 0;
     return (int)busy;
+}
+
+extern "C" int pir_serve_set_policy(pir_server* srv, int policy) {
+    if (!srv) return fail(PIR_E_INVALID, "null server");
+    CW_ENTER(srv->ctx);
+    if (policy != PIR_SERVE_ROUND_ROBIN && policy != PIR_SERVE_OLDEST_FIRST)
+        return fail(PIR_E_INVALID, "unknown serving policy");
+    srv->policy = policy;
+    return PIR_OK;
 }
 
 extern "C" int pir_serve_poll(pir_server* srv, uint64_t ticket) {
@@ -1734,4 +1752,87 @@ extern "C" int pir_folklore_leaves(pir_ctx* ctx, const uint64_t* query, uint32_t
     CW_TRY(begin_async(ctx, st));
     cw::launch_folklore_leaves(make_launch(ctx, st), query, ell, out);
     return end_async(ctx, st);
+}
+
+// ------------------------------------------------------------------------------------------------
+// arithmetic constant-weight equality (Section 3.1, Algorithm 2), on batch-encoded ciphertexts
+//
+// k' = Relin(sum_i Mult(x_i, y_i)): the m products (tensor and exact rounding, in chunks) are summed
+// as three-polynomial ciphertexts and key-switched once; the factors k' - i (i < k) then go through
+// the product tree of the plain operator (memoised nodes, one root); the result is multiplied by
+// the plaintext constant (k!)^-1 mod t.
+// ------------------------------------------------------------------------------------------------
+extern "C" int pir_arith_equality(pir_ctx* ctx, const pir_key* key, const uint64_t* x, const uint64_t* y, uint32_t m,
+                                  uint32_t k, uint64_t* out, void* stream) {
+    CW_ENTER(ctx);
+    if (!key || !x || !y || !out) return fail(PIR_E_INVALID, "null argument");
+    if (key->ctx != ctx || key->galois) return fail(PIR_E_INVALID, "need a relinearization key of this context");
+    if (m < 1 || k < 1 || k > PIR_MAX_K || k > m) return fail(PIR_E_INVALID, "need 1 <= k <= min(m, 16)");
+    uint64_t fact = 1;  // k! mod t, which must be invertible
+    for (uint32_t i = 2; i <= k; ++i) fact = fact * i % ctx->t;
+    if (fact == 0) return fail(PIR_E_INVALID, "k! is not invertible mod t");
+    const uint64_t finv = cw::host::powmod(fact, ctx->t - 2, ctx->t);  // t prime
+    hipStream_t st = (hipStream_t)stream;
+    CW_TRY(begin_async(ctx, st));
+    const size_t N = ctx->N, L = ctx->L, LL = ctx->LL;
+    const uint32_t E = std::min<uint32_t>(m, ctx->chunk);
+    Launch lc = make_launch(ctx, st);
+    Bufs b;
+    CW_TRY(get_bufs(ctx, E, 1, 0, b));
+    uint64_t *QX, *S, *kp, *F, *FX, *sel, *nodes = nullptr;
+    uint32_t* refs;
+    CW_TRY(ws_get_t(ctx, "ae_qx", (size_t)2 * m * 2 * LL * N, &QX));
+    CW_TRY(ws_get_t(ctx, "ae_refs", (size_t)2 * std::max<uint32_t>(E, 1), &refs));
+    CW_TRY(ws_get_t(ctx, "ae_sum", 3 * L * N, &S));
+    CW_TRY(ws_get_t(ctx, "ae_kp", 2 * L * N, &kp));
+    CW_TRY(ws_get_t(ctx, "ae_f", (size_t)k * 2 * L * N, &F));
+    CW_TRY(ws_get_t(ctx, "ae_fx", (size_t)k * 2 * LL * N, &FX));
+    CW_TRY(ws_get_t(ctx, "ae_sel", (size_t)std::max<uint32_t>(E, 1) * 2 * L * N, &sel));
+    // operands: x then y, extended and transformed
+    CW_TRY(make_leaves(ctx, lc, x, m, QX));
+    CW_TRY(make_leaves(ctx, lc, y, m, QX + (size_t)m * 2 * LL * N));
+    // k' = Relin(sum of the m products)
+    for (uint32_t i0 = 0; i0 < m; i0 += E) {
+        const uint32_t cnt = std::min(E, m - i0);
+        cw::launch_pair_refs(st, refs, cnt, i0, m + i0);
+        cw::Batch bt = one_query(cnt, QX, nullptr, key, sel);
+        {
+            Prof pr(ctx, "ntt_inv_tensor", st, bfly(ctx, (size_t)cnt * 3 * LL));
+            cw::launch_ntt_inv_tensor(lc, refs, bt, b.X);
+        }
+        {
+            Prof pr(ctx, "scale", st, (double)cnt * 3 * N);
+            cw::launch_scale(lc, b.X, b.C, cnt);
+        }
+        cw::launch_sum_rows(lc, b.C, cnt, (uint32_t)(3 * L), i0 == 0, S);
+    }
+    {
+        Prof pr(ctx, "relin", st, bfly(ctx, (L + 2) * L));
+        cw::launch_relin(lc, S, one_query(1, QX, nullptr, key, kp), b.R);
+    }
+    cw::launch_ntt(lc, true, kp, kp, 2 * L, (uint32_t)L, 0);
+    // prod_{i < k} (k' - i) by the plain operator's tree
+    cw::launch_sub_consts(lc, kp, k, F);
+    CW_TRY(make_leaves(ctx, lc, F, k, FX));
+    std::vector<uint32_t> pos(k);
+    for (uint32_t i = 0; i < k; ++i) pos[i] = i;
+    PlanBuild pb;
+    plan_elements(pos.data(), 0, 1, k, pb);
+    const uint32_t np = (uint32_t)(pb.pairs.size() / 2);
+    uint32_t *dpairs, *droot;
+    CW_TRY(ws_get_t(ctx, "ae_pairs", std::max<size_t>(2, pb.pairs.size()), &dpairs));
+    CW_TRY(ws_get_t(ctx, "ae_root", 2, &droot));
+    if (np) {
+        CW_TRY(ws_get_t(ctx, "ae_nodes", (size_t)np * 2 * LL * N, &nodes));
+        CW_HIP(ctx, hipMemcpyAsync(dpairs, pb.pairs.data(), pb.pairs.size() * 4, hipMemcpyHostToDevice, st));
+    }
+    CW_HIP(ctx, hipMemcpyAsync(droot, pb.refs.data(), 8, hipMemcpyHostToDevice, st));
+    if (np) make_nodes(ctx, lc, b, dpairs, pb.level_end, FX, key, sel, nodes, E);
+    roots(ctx, lc, b, k, droot, one_query(1, FX, nodes, key, sel));
+    cw::launch_ntt(lc, true, sel, sel, 2 * L, (uint32_t)L, 0);
+    // times the plaintext constant (k!)^-1
+    cw::launch_scalar_mul(lc, sel, 2, finv, out);
+    CW_TRY(end_async(ctx, st));
+    CW_HIP(ctx, hipStreamSynchronize(st));  // the tree plan was copied from pageable host memory
+    return PIR_OK;
 }

@@ -85,6 +85,16 @@ void launch_expand_combine(const Launch& lc, const uint64_t* src, const uint64_t
 // x' = round(x q' / q) on centred representatives; S is a device copy of the switch constants.
 void launch_mod_switch(const Launch& lc, const SwitchConst* S, uint32_t keep, const uint64_t* in, size_t polys,
                        uint64_t* out);
+// Arithmetic equality helpers.
+//   pair_refs:  refs[2i] = a0 + i, refs[2i + 1] = b0 + i for i < n
+//   sum_rows:   S [rows][N] (+)= sum over e < cnt of C[e][rows][N] (mod the row's prime, row r uses
+//               prime r mod L); overwrites S when `first`
+//   sub_consts: F[i] = ct - i (the plaintext constant i: Delta i off coefficient 0 of c0), i < k
+//   scalar_mul: out = ct * c (mod q_j), ct [count][L][N], c < every q_j
+void launch_pair_refs(hipStream_t st, uint32_t* refs, uint32_t n, uint32_t a0, uint32_t b0);
+void launch_sum_rows(const Launch& lc, const uint64_t* C, uint32_t cnt, uint32_t rows, bool first, uint64_t* S);
+void launch_sub_consts(const Launch& lc, const uint64_t* ct, uint32_t k, uint64_t* F);
+void launch_scalar_mul(const Launch& lc, const uint64_t* ct, uint32_t count, uint64_t c, uint64_t* out);
 // Folklore leaves: out [2 ell][2][L][N] = (1 - x_i, x_i) for the query bits x_i [ell][2][L][N].
 void launch_folklore_leaves(const Launch& lc, const uint64_t* query, uint32_t ell, uint64_t* out);
 // Row gather: dst row e = src row order[e] for e < n, rows of `row` uint16 (a multiple of 8).

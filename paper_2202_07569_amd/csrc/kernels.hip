@@ -1470,6 +1470,72 @@ void launch_mod_switch(const Launch& lc, const SwitchConst* S, uint32_t keep, co
     hipLaunchKernelGGL(k_mod_switch_fix, dim3(1), dim3(256), 0, lc.stream, lc.K, S, in, out, lc.fix, lc.fixcnt);
 }
 
+// ---------------------------------------------------------------------------------------------
+// Arithmetic equality helpers (element-wise, one thread per coefficient).
+// ---------------------------------------------------------------------------------------------
+__global__ void k_pair_refs(uint32_t* refs, uint32_t n, uint32_t a0, uint32_t b0) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    refs[2 * i] = a0 + i;
+    refs[2 * i + 1] = b0 + i;
+}
+
+__global__ void k_sum_rows(const CtxConst* __restrict__ K, const uint64_t* __restrict__ C, uint32_t cnt,
+                           uint32_t rows, bool first, uint64_t* __restrict__ S) {
+    const uint32_t N = K->N, L = K->L;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t per = (size_t)rows * N;
+    if (gid >= per) return;
+    const uint64_t p = K->p[(gid / N) % L];
+    uint64_t acc = first ? 0 : S[gid];
+    for (uint32_t e = 0; e < cnt; ++e) acc = add_mod(acc, C[(size_t)e * per + gid], p);
+    S[gid] = acc;
+}
+
+__global__ void k_sub_consts(const CtxConst* __restrict__ K, const uint64_t* __restrict__ ct, uint32_t k,
+                             uint64_t* __restrict__ F) {
+    const uint32_t N = K->N, L = K->L;
+    const size_t c2 = (size_t)2 * L * N;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)k * c2) return;
+    const uint32_t i = (uint32_t)(gid / c2);
+    const size_t w = gid % c2;  // (poly * L + j) * N + c
+    const uint32_t c = (uint32_t)(w % N), j = (uint32_t)((w / N) % L);
+    const uint64_t p = K->p[j];
+    uint64_t v = ct[w];
+    if (w < (size_t)L * N && c == 0) v = sub_mod(v, mul_barrett(K->delta[j], i, p, K->bar_mu[j], K->bar_s[j]), p);
+    F[gid] = v;
+}
+
+__global__ void k_scalar_mul(const CtxConst* __restrict__ K, const uint64_t* __restrict__ ct, size_t total,
+                             uint64_t c, uint64_t* __restrict__ out) {
+    const uint32_t N = K->N, L = K->L;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= total) return;
+    const uint32_t j = (uint32_t)((gid / N) % L);
+    out[gid] = mul_barrett(ct[gid], c, K->p[j], K->bar_mu[j], K->bar_s[j]);
+}
+
+void launch_pair_refs(hipStream_t st, uint32_t* refs, uint32_t n, uint32_t a0, uint32_t b0) {
+    if (!n) return;
+    hipLaunchKernelGGL(k_pair_refs, dim3(blocks_for(n)), dim3(EW_THREADS), 0, st, refs, n, a0, b0);
+}
+void launch_sum_rows(const Launch& lc, const uint64_t* C, uint32_t cnt, uint32_t rows, bool first, uint64_t* S) {
+    hipLaunchKernelGGL(k_sum_rows, dim3(blocks_for((size_t)rows * lc.N)), dim3(EW_THREADS), 0, lc.stream, lc.K, C,
+                       cnt, rows, first, S);
+}
+void launch_sub_consts(const Launch& lc, const uint64_t* ct, uint32_t k, uint64_t* F) {
+    if (!k) return;
+    hipLaunchKernelGGL(k_sub_consts, dim3(blocks_for((size_t)k * 2 * lc.L * lc.N)), dim3(EW_THREADS), 0, lc.stream,
+                       lc.K, ct, k, F);
+}
+void launch_scalar_mul(const Launch& lc, const uint64_t* ct, uint32_t count, uint64_t c, uint64_t* out) {
+    const size_t total = (size_t)count * lc.L * lc.N;
+    if (!total) return;
+    hipLaunchKernelGGL(k_scalar_mul, dim3(blocks_for(total)), dim3(EW_THREADS), 0, lc.stream, lc.K, ct, total, c,
+                       out);
+}
+
 // Folklore leaves: leaf 2i = 1 - x_i = (Delta - c0, -c1) (Delta in coefficient 0 only), leaf 2i + 1 = x_i.
 __global__ void k_folklore_leaves(const CtxConst* __restrict__ K, const uint64_t* __restrict__ query, uint32_t ell,
                                   uint64_t* __restrict__ out) {
