@@ -74,6 +74,10 @@ def parse():
     ap.add_argument("--serve-rates", default="0.8", help="arrival rates as multiples of 1/S (S: mean plain service time)")
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--serve-only", action="store_true", help="skip the mid workload")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="time only the batched step (no plain loop, graph replay, expansion, folklore or "
+                         "arithmetic timings): the launches a counter pass attributes to each kernel family "
+                         "are then the batched step's")
     return ap.parse_args()
 
 
@@ -200,24 +204,27 @@ def main():
         log(f"copy calibration: 3 copies of {args.copy_calibration_mib} MiB")
         del src, dst
 
-    log("plain loop")
-    t_plain, per_plain, _ = timed(step_plain, args.steps, args.warmup, False)
-    log(f"plain {t_plain / args.steps * 1e3:.1f} ms/query")
-    graph = ctx_plain.capture([key_plain], [db_plain], [dq[0]], outs=[out_plain])
-    t_graph, per_graph, _ = timed(lambda: graph.launch(stream=stream), args.steps, args.warmup, False)
-    log(f"plain, captured graph {t_graph / args.steps * 1e3:.1f} ms/query")
+    graph = None
+    if not args.batched_only:
+        log("plain loop")
+        t_plain, per_plain, _ = timed(step_plain, args.steps, args.warmup, False)
+        log(f"plain {t_plain / args.steps * 1e3:.1f} ms/query")
+        graph = ctx_plain.capture([key_plain], [db_plain], [dq[0]], outs=[out_plain])
+        t_graph, per_graph, _ = timed(lambda: graph.launch(stream=stream), args.steps, args.warmup, False)
+        log(f"plain, captured graph {t_graph / args.steps * 1e3:.1f} ms/query")
     log(f"batched B={B}")
     t_b, per_b, prof = timed(step_batch, args.steps, args.warmup, not args.no_profile)
     ms_step = t_b / args.steps * 1e3
     value = B * n * args.steps / t_b
     log(f"batched {ms_step:.1f} ms/step -> {value:.0f} elements/s")
     torch.cuda.synchronize()
-    if not np.array_equal(out_plain.cpu().numpy(), outs[0].cpu().numpy()):
+    extras = not args.batched_only
+    if extras and not np.array_equal(out_plain.cpu().numpy(), outs[0].cpu().numpy()):
         raise SystemExit("the batched answer of query 0 differs from the plain answer")
 
-    expansion = expansion_bench(args, ctx, cfg, torch, stream)
-    folklore = folklore_bench(args, cfg, torch, stream) if args.workload == "mid" else None
-    arith = arith_bench(args, ctx, key, cfg, torch, stream) if args.workload == "mid" else None
+    expansion = expansion_bench(args, ctx, cfg, torch, stream) if extras else None
+    folklore = folklore_bench(args, cfg, torch, stream) if extras and args.workload == "mid" else None
+    arith = arith_bench(args, ctx, key, cfg, torch, stream) if extras and args.workload == "mid" else None
 
     fp = cfg.N <= 8192 and all(p < FP_PRIME_BOUND for p in tuple(cfg.primes) + ctx.aux_primes)
     roof = roofline(prof, args.steps, fp, traffic_table(cfg, n, B, ctx.schedule())) if prof else None
@@ -239,9 +246,9 @@ def main():
         "schedule": {"batched": ctx.schedule(), "plain": ctx_plain.schedule(),
                      "source": {"batched": tune, "plain": tune_plain}},
         "plain": {"value": n * args.steps / t_plain, "unit": "elements/s", "ms_per_query": t_plain / args.steps * 1e3,
-                  **lat(per_plain)},
+                  **lat(per_plain)} if extras else None,
         "plain_graph": {"value": n * args.steps / t_graph, "unit": "elements/s",
-                        "ms_per_query": t_graph / args.steps * 1e3, **lat(per_graph)},
+                        "ms_per_query": t_graph / args.steps * 1e3, **lat(per_graph)} if extras else None,
         "batched": {"value": value, "ms_per_step": ms_step, **lat(per_b)},
         "expansion": expansion,
         "folklore": folklore,
@@ -249,8 +256,9 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
-    graph.close()
-    if serve:
+    if graph is not None:
+        graph.close()
+    if serve and extras:
         del graph, db, dq, outs, key, ctx, db_plain, key_plain, ctx_plain, out_plain
         torch.cuda.empty_cache()
         out["serving"] = serve_bench(args, torch)

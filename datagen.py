@@ -12,7 +12,7 @@ z0 = mix(mix(seed) XOR stream_id).
 
 Stream ids: 1 secret key, 2 relinearization key, 3 query encryption, 4 payload, 5 identifier
 permutation, 6 target, 7 keywords, 8 lossy-map hash seed, 9 arrivals, 10 database choice,
-11 synthetic ciphertexts.
+11 synthetic ciphertexts, 12 Galois keys, 13 packed query encryptions, 14 seeded query errors.
 
 Workloads follow the paper's evaluation: random synthetic databases of n elements, each element s
 FV plaintexts of N coefficients (Section 5.1 and the keyword-PIR application in Section 5.3); the
@@ -29,7 +29,7 @@ GAMMA = 0x9E3779B97F4A7C15
 MASK64 = (1 << 64) - 1
 
 S_SECRET, S_RLK, S_QUERY, S_PAYLOAD, S_PERM, S_TARGET, S_KEYWORDS, S_HASH, S_ARRIVALS, \
-    S_DBCHOICE, S_SYNTH, S_GALOIS, S_PACKED = range(1, 14)
+    S_DBCHOICE, S_SYNTH, S_GALOIS, S_PACKED, S_SEEDED = range(1, 15)
 
 
 def mix64(z: int) -> int:
