@@ -223,6 +223,7 @@ def main():
         raise SystemExit("the batched answer of query 0 differs from the plain answer")
 
     expansion = expansion_bench(args, ctx, cfg, torch, stream) if extras else None
+    seeded = seeded_bench(args, ctx, cfg, torch, stream) if extras else None
     folklore = folklore_bench(args, cfg, torch, stream) if extras and args.workload == "mid" else None
     arith = arith_bench(args, ctx, key, cfg, torch, stream) if extras and args.workload == "mid" else None
 
@@ -251,6 +252,7 @@ def main():
                         "ms_per_query": t_graph / args.steps * 1e3, **lat(per_graph)} if extras else None,
         "batched": {"value": value, "ms_per_step": ms_step, **lat(per_b)},
         "expansion": expansion,
+        "seeded_query": seeded,
         "folklore": folklore,
         "arith_equality": arith,
         "roofline": roof,
@@ -351,6 +353,29 @@ def expansion_bench(args, ctx, cfg, torch, stream):
     log(f"expansion c={c} h={h} m={cfg.m}: {np.median(per) * 1e3:.2f} ms")
     return {"c": c, "packed_ciphertexts": h, "m": cfg.m, "substitutions": h * ((1 << c) - 1),
             "ms_median": float(np.median(per) * 1e3), "ms_p99": float(np.percentile(per, 99) * 1e3)}
+
+
+def seeded_bench(args, ctx, cfg, torch, stream):
+    """Rebuild of a seeded c = 0 query (m ciphertexts: c0 uploaded, a regenerated from the seed)
+    and the upload sizes of the query forms (64-bit residues; a seed is 8 bytes)."""
+    c0 = torch.from_numpy(datagen.uniform_residues(cfg.primes, (cfg.m,), cfg.N, seed=cfg.seed * 100 + 70)).cuda()
+    out = ctx.empty(cfg.m, 2, cfg.L, cfg.N)
+    for _ in range(max(1, args.warmup)):
+        ctx.seeded_query(c0, 12345, out=out, stream=stream)
+    torch.cuda.synchronize()
+    per = []
+    for _ in range(max(3, args.steps)):
+        a = time.perf_counter()
+        ctx.seeded_query(c0, 12345, out=out, stream=stream)
+        torch.cuda.synchronize()
+        per.append(time.perf_counter() - a)
+    poly = cfg.L * cfg.N * 8
+    c = min(5, max(0, (cfg.m - 1).bit_length()))
+    h = -(-cfg.m // (1 << c))
+    log(f"seeded query rebuild m={cfg.m}: {np.median(per) * 1e3:.3f} ms")
+    return {"m": cfg.m, "ms_median": float(np.median(per) * 1e3),
+            "upload_bytes": {"query": cfg.m * 2 * poly, "seeded_query": cfg.m * poly + 8,
+                             f"packed_c{c}": h * 2 * poly, f"seeded_packed_c{c}": h * poly + 8}}
 
 
 def arith_bench(args, ctx, key, cfg, torch, stream, m=37, k=4):

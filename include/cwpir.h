@@ -197,6 +197,18 @@ int pir_arith_equality(pir_ctx* ctx, const pir_key* key, const uint64_t* x, cons
  * Asynchronous. */
 int pir_mod_switch(pir_ctx* ctx, const uint64_t* in, uint32_t count, uint32_t keep, uint64_t* out, void* stream);
 
+/* Seeded query ciphertexts (the compressed upload of secret-key encryption that the paper lists
+ * among SealPIR's optimisations, Section 2; the upload column of the communication-cost table).
+ * A secret-key ciphertext ([-a s + e + Delta m]_q, a) has a uniform a that the client need not
+ * send: it sends c0 and a 64-bit seed.  The server rebuilds the full ciphertexts:
+ *   c0   dev [count][L][N], residues in [0, q_j) (copied as they are)
+ *   out  dev [count][2][L][N]: out[i][0] = c0[i], out[i][1][j][c] = (W(2u) 2^64 + W(2u + 1)) mod q_j
+ *        with u = (i L + j) N + c and W(v) = SplitMix64 output number v + 1 from state `seed`,
+ *        i.e. mix(seed + (v + 1) 0x9E3779B97F4A7C15 mod 2^64) (Steele, Lea and Flood 2014).
+ * The result is a c = 0 query for pir_answer, or packed ciphertexts for pir_expand.  c0 and out
+ * must not overlap; count * L * N must stay below 2^38.  count = 0 does nothing.  Asynchronous. */
+int pir_seeded_query(pir_ctx* ctx, const uint64_t* c0, uint32_t count, uint64_t seed, uint64_t* out, void* stream);
+
 /* Captured answers (HIP graphs), for callers that answer many queries of the same shape, e.g. a
  * serving loop with fixed query and answer slots.  pir_graph_capture runs pir_answer_batch once
  * for the given arguments (the answers for the queries' current contents are written) and records

@@ -46,24 +46,34 @@ def packed_count(m: int, c: int) -> int:
     return -(-m // (1 << c))
 
 
-def pack_query(orc: Oracle, sk: np.ndarray, bits, c: int, seed: int, draw: int = 0, prescale: bool = True):
-    """Algorithm 4 (lines 2-7): h packed ciphertexts [h][2][L][N].  With prescale=False the
-    plaintext coefficients are the bits themselves (the input of Algorithm 1)."""
+def pack_messages(bits, c: int, N: int, t: int, prescale: bool = True) -> np.ndarray:
+    """Algorithm 4, packing: the h plaintexts [h][N]; plaintext i holds 2^-c (mod t) times bit
+    i 2^c + j in coefficient j.  With prescale=False the coefficients are the bits themselves (the
+    input of Algorithm 1)."""
     bits = [int(b) for b in bits]
-    m, N, t = len(bits), orc.N, orc.t
+    m = len(bits)
     if (1 << c) > N:
         raise ValueError("2^c must not exceed N")
     h = packed_count(m, c)
     inv = pow(2, -c, t) if prescale else 1
-    per = orc.rnd_words_encrypt()
-    out = np.empty((h, 2, orc.L, N), dtype=np.uint64)
+    msgs = np.zeros((h, N), dtype=np.uint64)
     for i in range(h):
-        msg = np.zeros(N, dtype=np.uint64)
         for j in range(1 << c):
             if i * (1 << c) + j < m:
-                msg[j] = (inv * bits[i * (1 << c) + j]) % t
+                msgs[i, j] = (inv * bits[i * (1 << c) + j]) % t
+    return msgs
+
+
+def pack_query(orc: Oracle, sk: np.ndarray, bits, c: int, seed: int, draw: int = 0, prescale: bool = True):
+    """Algorithm 4, packing and encryption: h packed ciphertexts [h][2][L][N], the encryptions of
+    pack_messages."""
+    msgs = pack_messages(bits, c, orc.N, orc.t, prescale)
+    h = len(msgs)
+    per = orc.rnd_words_encrypt()
+    out = np.empty((h, 2, orc.L, orc.N), dtype=np.uint64)
+    for i in range(h):
         rnd = datagen.words(seed, datagen.S_PACKED, per, offset=(draw * h + i) * per)
-        out[i] = orc.encrypt(sk, msg, rnd)
+        out[i] = orc.encrypt(sk, msgs[i], rnd)
     return out
 
 

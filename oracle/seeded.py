@@ -84,3 +84,9 @@ def seeded_query(orc: Oracle, sk: np.ndarray, positions, m: int, seed: int, err_
     msgs = np.zeros((m, orc.N), dtype=np.uint64)
     msgs[:, 0] = codeword_bits(positions, m)
     return encrypt_seeded(orc, sk, msgs, seed, err_seed)
+
+
+def seeded_pack(orc: Oracle, sk: np.ndarray, bits, c: int, seed: int, err_seed: int) -> np.ndarray:
+    """A packed query (Algorithm 4) encrypted with seeded a polynomials: [h][2][L][N]."""
+    from .expand import pack_messages
+    return encrypt_seeded(orc, sk, pack_messages(bits, c, orc.N, orc.t), seed, err_seed)

@@ -23,7 +23,7 @@ EXPORTS = [
     "pir_last_error", "pir_serve_open", "pir_serve_submit", "pir_serve_step", "pir_serve_poll", "pir_serve_stats",
     "pir_serve_close", "pir_get_schedule", "pir_set_schedule", "pir_autotune", "pir_graph_capture",
     "pir_graph_launch", "pir_graph_free", "pir_load_galois_key", "pir_expand", "pir_mod_switch",
-    "pir_folklore_leaves", "pir_arith_equality", "pir_serve_set_policy",
+    "pir_folklore_leaves", "pir_arith_equality", "pir_serve_set_policy", "pir_seeded_query",
 ]
 
 
@@ -106,6 +106,7 @@ def lib():
             "pir_folklore_leaves": (i32, [vp, vp, u32, vp, vp]),
             "pir_arith_equality": (i32, [vp, vp, vp, vp, u32, u32, vp, vp]),
             "pir_serve_set_policy": (i32, [vp, i32]),
+            "pir_seeded_query": (i32, [vp, vp, u32, ctypes.c_uint64, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -298,6 +299,18 @@ class Context:
         if out is None:
             out = self.empty(*lead, keep, self.N)
         _check(lib().pir_mod_switch(self._h, _ptr(x), count, keep, _ptr(out), _stream(stream)))
+        return out
+
+    def seeded_query(self, c0, seed: int, out=None, stream=None):
+        """Seeded query ciphertexts: c0 [count, L, N] plus the client's 64-bit seed -> the full
+        ciphertexts [count, 2, L, N], whose a polynomials the library regenerates from the seed."""
+        c0 = _dev_u64(c0, self.device)
+        assert c0.dim() == 3 and tuple(c0.shape[1:]) == (self.L, self.N)
+        count = int(c0.shape[0])
+        if out is None:
+            out = self.empty(count, 2, self.L, self.N)
+        _check(lib().pir_seeded_query(self._h, _ptr(c0), count, int(seed) & (2**64 - 1), _ptr(out),
+                                      _stream(stream)))
         return out
 
     def load_key(self, rlk) -> Key:

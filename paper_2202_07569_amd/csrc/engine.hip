@@ -1742,6 +1742,25 @@ extern "C" int pir_mod_switch(pir_ctx* ctx, const uint64_t* in, uint32_t count, 
 }
 
 // ------------------------------------------------------------------------------------------------
+// seeded query ciphertexts (Section 2, secret-key encryption compresses the upload)
+// ------------------------------------------------------------------------------------------------
+extern "C" int pir_seeded_query(pir_ctx* ctx, const uint64_t* c0, uint32_t count, uint64_t seed, uint64_t* out,
+                                void* stream) {
+    CW_ENTER(ctx);
+    if (!count) return PIR_OK;
+    if (!c0 || !out) return fail(PIR_E_INVALID, "null argument");
+    const size_t total = (size_t)count * ctx->L * ctx->N;
+    if (total >= (1ull << 38)) return fail(PIR_E_INVALID, "count * L * N must stay below 2^38");
+    const uintptr_t a0 = (uintptr_t)c0, a1 = a0 + total * 8, b0 = (uintptr_t)out, b1 = b0 + 2 * total * 8;
+    if (a0 < b1 && b0 < a1) return fail(PIR_E_INVALID, "c0 and out must not overlap");
+    hipStream_t st = (hipStream_t)stream;
+    CW_TRY(begin_async(ctx, st));
+    Prof pr(ctx, "seeded_query", st, (double)total);
+    cw::launch_seeded_query(make_launch(ctx, st), c0, count, seed, out);
+    return end_async(ctx, st);
+}
+
+// ------------------------------------------------------------------------------------------------
 // folklore PIR leaves (Section 2.4, plain folklore operator)
 // ------------------------------------------------------------------------------------------------
 extern "C" int pir_folklore_leaves(pir_ctx* ctx, const uint64_t* query, uint32_t ell, uint64_t* out, void* stream) {

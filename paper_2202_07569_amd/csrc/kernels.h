@@ -97,6 +97,9 @@ void launch_sub_consts(const Launch& lc, const uint64_t* ct, uint32_t k, uint64_
 void launch_scalar_mul(const Launch& lc, const uint64_t* ct, uint32_t count, uint64_t c, uint64_t* out);
 // Folklore leaves: out [2 ell][2][L][N] = (1 - x_i, x_i) for the query bits x_i [ell][2][L][N].
 void launch_folklore_leaves(const Launch& lc, const uint64_t* query, uint32_t ell, uint64_t* out);
+// Seeded query ciphertexts (seeded.hip): out [count][2][L][N] with out[i][0] = c0[i] ([count][L][N])
+// and out[i][1] the uniform polynomial regenerated from `seed`.
+void launch_seeded_query(const Launch& lc, const uint64_t* c0, uint32_t count, uint64_t seed, uint64_t* out);
 // Row gather: dst row e = src row order[e] for e < n, rows of `row` uint16 (a multiple of 8).
 void launch_gather_rows(hipStream_t st, const uint16_t* src, const uint64_t* order, uint64_t n, size_t row,
                         uint16_t* dst);

@@ -87,3 +87,9 @@ def test_schedule_calls_reject_null_context():
     assert L.pir_set_schedule(None, ctypes.byref(s)) == binding.PIR_E_INVALID
     assert L.pir_autotune(None, 1, 2, 1, None, 0, None) == binding.PIR_E_INVALID
     assert "null context" in L.pir_last_error().decode()
+
+
+def test_seeded_query_rejects_null_context():
+    L = binding.lib()
+    assert L.pir_seeded_query(None, None, 1, 7, None, None) == binding.PIR_E_INVALID
+    assert "null context" in L.pir_last_error().decode()
