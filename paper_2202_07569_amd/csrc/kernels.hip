@@ -1298,37 +1298,90 @@ void launch_gather_leaf(const Launch& lc, const uint32_t* refs, const Batch& bt)
 
 // ---------------------------------------------------------------------------------------------
 // Inner product with the database (Eq. (1)): acc_b[r] += sum_e sel_b[e] * P[e][r], transformed
-// over Q.  Grid y indexes the B queries that scan the same payload chunk.
+// over Q.  Grid y indexes groups of the B queries that scan the same payload chunk.
 // ---------------------------------------------------------------------------------------------
-__global__ void k_accumulate(const CtxConst* __restrict__ K, const QueryPtrs qp, const uint64_t* __restrict__ Ph,
-                             uint32_t E, uint32_t s) {
+// acc_q[r][poly] += sum_e sel_q[e][poly] * Ph[e][r] (mod q_j) for a group of up to QG queries.
+// A workgroup is ACC_SLICES wavefronts over the same 64 coefficients: wavefront w takes the w-th
+// contiguous slice of the E elements, and the slices are summed through LDS at the end, so that
+// enough waves are in flight to cover HBM latency (the loop is a stream of loads with a Barrett
+// product each).  Each thread keeps both polynomials of its coefficient for every query of the
+// group, so a transformed payload row is read once per group rather than once per query and
+// polynomial.  Modular sums do not depend on the order of their terms.
+constexpr int ACC_SLICES = 8;
+template <int QG>
+__global__ __launch_bounds__(64 * ACC_SLICES) void k_accumulate(const CtxConst* __restrict__ K,
+                                                                const QueryPtrs qp, const uint64_t* __restrict__ Ph,
+                                                                uint32_t nq, uint32_t E, uint32_t s) {
+    __shared__ uint64_t red[ACC_SLICES - 1][2 * QG][64];
     const uint32_t N = K->N, L = K->L;
-    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t LN = (size_t)L * N;
-    if (gid >= (size_t)s * 2 * LN) return;
-    const size_t cj = gid % LN;  // j * N + c
+    const uint32_t lane = threadIdx.x & 63u, w = threadIdx.x >> 6;
+    const size_t gid = (size_t)blockIdx.x * 64 + lane;  // (r, j, c) over s L N
+    const bool valid = gid < (size_t)s * LN;
+    const size_t cj = gid % LN;
+    const uint32_t r = (uint32_t)(gid / LN);
     const uint32_t j = (uint32_t)(cj / N);
-    const size_t rp = gid / LN;
-    const uint32_t poly = (uint32_t)(rp % 2), r = (uint32_t)(rp / 2);
     const uint64_t p = K->p[j], mu = K->bar_mu[j];
     const uint32_t sb = K->bar_s[j];
-    const uint64_t* sel = qp.sel[blockIdx.y];
-    uint64_t* acc = qp.acc[blockIdx.y];
-    uint64_t sum = acc[gid];
-#pragma unroll 8
-    for (uint32_t e = 0; e < E; ++e) {
-        const uint64_t a = sel[((size_t)e * 2 + poly) * LN + cj];
-        const uint64_t b = Ph[((size_t)e * s + r) * LN + cj];
-        sum = add_mod(sum, mul_barrett(a, b, p, mu, sb), p);
+    const uint32_t q0 = blockIdx.y * QG;
+    const uint32_t nqg = nq - q0 < (uint32_t)QG ? nq - q0 : (uint32_t)QG;
+    uint64_t s0[QG], s1[QG];
+#pragma unroll
+    for (int q = 0; q < QG; ++q) s0[q] = s1[q] = 0;
+    const uint32_t e_lo = (uint32_t)((uint64_t)E * w / ACC_SLICES);
+    const uint32_t e_hi = (uint32_t)((uint64_t)E * (w + 1) / ACC_SLICES);
+    if (valid) {
+#pragma unroll 2
+        for (uint32_t e = e_lo; e < e_hi; ++e) {
+            const uint64_t b = Ph[((size_t)e * s + r) * LN + cj];
+            const size_t o = (size_t)e * 2 * LN + cj;
+#pragma unroll
+            for (int q = 0; q < QG; ++q) {
+                if ((uint32_t)q < nqg) {
+                    const uint64_t* sel = qp.sel[q0 + q];
+                    s0[q] = add_mod(s0[q], mul_barrett(sel[o], b, p, mu, sb), p);
+                    s1[q] = add_mod(s1[q], mul_barrett(sel[o + LN], b, p, mu, sb), p);
+                }
+            }
+        }
     }
-    acc[gid] = sum;
+    if (w > 0) {
+#pragma unroll
+        for (int q = 0; q < QG; ++q) {
+            red[w - 1][2 * q][lane] = s0[q];
+            red[w - 1][2 * q + 1][lane] = s1[q];
+        }
+    }
+    __syncthreads();
+    if (w == 0 && valid) {
+#pragma unroll
+        for (int q = 0; q < QG; ++q) {
+            if ((uint32_t)q < nqg) {
+                uint64_t a0 = s0[q], a1 = s1[q];
+#pragma unroll
+                for (int v = 0; v < ACC_SLICES - 1; ++v) {
+                    a0 = add_mod(a0, red[v][2 * q][lane], p);
+                    a1 = add_mod(a1, red[v][2 * q + 1][lane], p);
+                }
+                uint64_t* acc = qp.acc[q0 + q] + (size_t)r * 2 * LN + cj;
+                acc[0] = add_mod(acc[0], a0, p);
+                acc[LN] = add_mod(acc[LN], a1, p);
+            }
+        }
+    }
 }
 
 void launch_accumulate(const Launch& lc, const QueryPtrs& qp, const uint64_t* Ph, uint32_t nq, uint32_t E,
                        uint32_t s) {
     if (!E || !nq) return;
-    hipLaunchKernelGGL(k_accumulate, dim3(blocks_for((size_t)s * 2 * lc.L * lc.N), nq), dim3(EW_THREADS), 0,
-                       lc.stream, lc.K, qp, Ph, E, s);
+    const unsigned bx = (unsigned)(((size_t)s * lc.L * lc.N + 63) / 64);
+#define CW_ACC(QG)                                                                                          \
+    hipLaunchKernelGGL(k_accumulate<QG>, dim3(bx, (nq + QG - 1) / QG), dim3(64 * ACC_SLICES), 0, lc.stream, \
+                       lc.K, qp, Ph, nq, E, s)
+    if (nq == 1) CW_ACC(1);
+    else if (nq == 2) CW_ACC(2);
+    else CW_ACC(4);
+#undef CW_ACC
 }
 
 // ---------------------------------------------------------------------------------------------
