@@ -95,8 +95,9 @@ def synthetic_inputs(cfg, n, B):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding by database rows is "
-                                   "described in the design notes but not built", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "the library runs on one GPU; sharding the database rows over several "
+                                   "GPUs is described in the design notes but not implemented",
+                          "n_gpus": args.gpus}))
         sys.exit(2)
     import torch
 
