@@ -186,8 +186,15 @@ static Launch make_launch(pir_ctx* ctx, hipStream_t st) {
     lc.tw = ctx->dtw;
     lc.twf = ctx->dtwf;
     lc.fp = ctx->fp;
+    // the lazy key switch needs every ciphertext prime below 2^48 and its accumulators, below
+    // (2.4 L + 15) max q_i, below 2^53
+    double maxq = 0.0;
     lc.q_lazy = ctx->fp;
-    for (uint32_t i = 0; i < ctx->L; ++i) lc.q_lazy = lc.q_lazy && ctx->primes[i] < cw::FP_LAZY_BOUND;
+    for (uint32_t i = 0; i < ctx->L; ++i) {
+        lc.q_lazy = lc.q_lazy && ctx->primes[i] < cw::FP_LAZY_BOUND;
+        maxq = std::max(maxq, (double)ctx->primes[i]);
+    }
+    lc.q_lazy = lc.q_lazy && (2.4 * ctx->L + 16.0) * maxq < 9007199254740992.0;
     lc.N = ctx->N;
     lc.logN = ctx->logN;
     lc.L = ctx->L;

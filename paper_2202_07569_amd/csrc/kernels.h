@@ -35,8 +35,9 @@ struct Launch {
     const uint64_t* tw;   // device twiddles [LL][4][N]
     const double* twf;    // the same as doubles (fp64 transform), or null
     bool fp;              // transforms run on the fp64 pipe (every prime below 2^50, N <= 8192)
-    bool q_lazy;          // fp and every ciphertext prime below 2^48: forward transforms modulo q_j
-                          // need no reduction between passes
+    bool q_lazy;          // fp, every ciphertext prime below 2^48 and (2.4 L + 16) max q_i < 2^53: the
+                          // key switch's transforms modulo q_j need no reduction between passes or
+                          // of their outputs
     uint32_t N, logN, L, LB, LL;
     uint32_t cus;         // compute units of the device
     uint32_t relin_group; // key-switch workgroup order: 0 = the L limbs of an element side by side on

@@ -244,6 +244,11 @@ __device__ __forceinline__ void inv_pass_fp(double* a, uint32_t tid, const doubl
 }
 #pragma clang fp contract(on)
 
+// x < 2^52 -> the double x, exactly: 2^52 + x has the bits 0x433 (exponent) and x (mantissa).
+__device__ __forceinline__ double u52_to_double(uint64_t x) {
+    return __longlong_as_double((long long)(x | 0x4330000000000000ull)) - 4503599627370496.0;
+}
+
 // integer-valued double in (-p, p) -> residue in [0, p)
 __device__ __forceinline__ uint64_t fp_to_residue(double x, double p) {
     x = x < 0.0 ? x + p : x;
@@ -354,14 +359,19 @@ __device__ __forceinline__ void inv_passes(void* av, void* smv, uint32_t tid, Tw
 // transform; any |v| < 2^53 for the inverse, whose passes start by reducing).  On return v[] holds
 // the outputs reduced to [-p/2, p/2]: the forward transform in the transformed layout, the inverse
 // (including N^-1) in the first pass's natural-order pattern.
-template <class Sh, bool LAZY = false, bool TWPAD = false>
+// REDUCE = false (lazy transforms only) leaves the outputs unreduced, below (b (35/32)^13 + 11.8) p
+// for inputs below b p; the caller reduces them later.
+template <class Sh, bool LAZY = false, bool TWPAD = false, bool REDUCE = true>
 __device__ __forceinline__ void ntt_fwd_f(double* v, uint64_t* sm, uint32_t tid, TwRow tw, const CtxConst* K,
                                           uint32_t pi) {
     static_assert(!LAZY || Sh::LOGN <= 13, "the lazy bound covers at most 13 stages");
+    static_assert(REDUCE || LAZY, "only the lazy transform may skip its final reduction");
     fwd_passes<Sh, true, 0, LAZY, TWPAD>(v, sm, tid, tw, K, pi);
-    const double p = K->pd[pi], pinv = K->pinv[pi];
+    if constexpr (REDUCE) {
+        const double p = K->pd[pi], pinv = K->pinv[pi];
 #pragma unroll
-    for (int u = 0; u < Sh::EPT; ++u) v[u] = fred(v[u], p, pinv);
+        for (int u = 0; u < Sh::EPT; ++u) v[u] = fred(v[u], p, pinv);
+    }
 }
 template <class Sh>
 __device__ __forceinline__ void ntt_inv_f(double* v, uint64_t* sm, uint32_t tid, TwRow tw, const CtxConst* K,
@@ -798,9 +808,15 @@ __global__ __launch_bounds__(Sh::T) void k_relin(const CtxConst* __restrict__ K,
 // N = 16384 does not fit 16 elements plus two accumulators per thread in the 128 registers that a
 // 1024-thread workgroup allows; there the digits are transformed to `staging` [E][L+2][L][N] and
 // multiplied-accumulated by a second kernel.
-// fp64 key switch (every prime below 2^50).  The key is in the fp64 operand format; the digits
-// D_i < q_i are exact doubles, reduced mod q_j by fred.  Transformed values and key entries lie in
-// [-p/2, p/2], so each product is below 0.7 p and each accumulator below (0.7 L + 0.5) p < 2^53.
+// fp64 key switch (every prime below 2^50).  The key is in the fp64 operand format (entries in
+// [-p/2, p/2]); the digits D_i < q_i are exact doubles.  Without LAZY every digit is reduced mod q_j
+// by fred and every transform output to [-p/2, p/2], so each product is below 0.7 p and each
+// accumulator below (0.7 L + 0.5) p < 2^53.  LAZY (every ciphertext prime below 2^48, and
+// (2.4 L + 16) max q_i < 2^53, checked by the host): a digit with q_i <= 2.5 q_j enters the
+// transform as it is (else it is reduced first) and no transform output is reduced.  Outputs stay
+// below 19.8 q_j (the stage bound below, from 2.5 q_j), each product below (1/2 + 3 * 19.8 / 32) q_j
+// < 2.4 q_j, the c0 and c1 transforms below 15 q_j, so each accumulator stays below (2.4 L + 15) q_j:
+// every sum is exact, and the final fred brings it to [-p/2, p/2].
 // All L + 2 transforms of the workgroup use prime q_j: its forward twiddles are staged in LDS once,
 // which leaves global memory to the operand rows.  The next operand row is loaded while the
 // current one is transformed (no global load inside the transform waits behind it).
@@ -838,24 +854,29 @@ __global__ __launch_bounds__(Sh::T) void k_relin_f(const CtxConst* __restrict__ 
     }
     __syncthreads();  // twiddles staged
     double acc0[EPT], acc1[EPT], v[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) acc0[u] = acc1[u] = 0.0;
     for (uint32_t i = 0; i < L + 2; ++i) {
         // The transform's index arithmetic does not depend on i; an opaque copy of the thread index
         // per iteration keeps the compiler from hoisting all of it out of the loop into registers.
         uint32_t t = tid;
         asm volatile("" : "+v"(t));
-        if (i < L && i != j) {
+        // Lazy transforms start from the digit as it is when q_i <= 2.5 q_j (the outputs then stay
+        // below 19.8 q_j); otherwise the digit is first reduced mod q_j.
+        const bool reduce = !LAZY || (i < L && i != j && K->pd[i] > 2.5 * p);
+        if (reduce) {
 #pragma unroll
-            for (int u = 0; u < EPT; ++u) v[u] = fred((double)nx[u], p, pinv);
+            for (int u = 0; u < EPT; ++u) v[u] = fred(LAZY ? u52_to_double(nx[u]) : (double)nx[u], p, pinv);
         } else {
 #pragma unroll
-            for (int u = 0; u < EPT; ++u) v[u] = (double)nx[u];
+            for (int u = 0; u < EPT; ++u) v[u] = LAZY ? u52_to_double(nx[u]) : (double)nx[u];
         }
         if (i + 1 < L + 2) {
             const uint64_t* src = src_row(i + 1);
 #pragma unroll
             for (int u = 0; u < EPT; ++u) nx[u] = src[elem_index<Sh, 0>(t, u)];
         }
-        ntt_fwd_f<Sh, LAZY, true>(v, sm, t, TwRow{nullptr, twl}, K, j);
+        ntt_fwd_f<Sh, LAZY, true, !LAZY>(v, sm, t, TwRow{nullptr, twl}, K, j);
         asm volatile("" ::: "memory");  // keep the key loads below the transform
         if (i < L) {
             const double* bh = rlk + ((size_t)i * 2 + 0) * LN + (size_t)j * N + t;
@@ -863,10 +884,8 @@ __global__ __launch_bounds__(Sh::T) void k_relin_f(const CtxConst* __restrict__ 
 #pragma unroll
             for (int u = 0; u < EPT; ++u) {
                 const size_t o = (size_t)u * T;
-                const double tb = fmulmod(v[u], bh[o], p, pinv);
-                const double ta = fmulmod(v[u], ah[o], p, pinv);
-                acc0[u] = i == 0 ? tb : acc0[u] + tb;
-                acc1[u] = i == 0 ? ta : acc1[u] + ta;
+                acc0[u] += fmulmod(v[u], bh[o], p, pinv);
+                acc1[u] += fmulmod(v[u], ah[o], p, pinv);
             }
         } else {
 #pragma unroll
