@@ -249,10 +249,10 @@ __device__ __forceinline__ double u52_to_double(uint64_t x) {
     return __longlong_as_double((long long)(x | 0x4330000000000000ull)) - 4503599627370496.0;
 }
 
-// integer-valued double in (-p, p) -> residue in [0, p)
+// integer-valued double in (-p, p) -> residue in [0, p) (p < 2^52): the mantissa of 2^52 + x.
 __device__ __forceinline__ uint64_t fp_to_residue(double x, double p) {
     x = x < 0.0 ? x + p : x;
-    return (uint64_t)x;
+    return (uint64_t)__double_as_longlong(x + 4503599627370496.0) & 0xFFFFFFFFFFFFFull;
 }
 
 // Index bit that bit b of the thread index occupies in pass P (see elem_index).
@@ -390,7 +390,7 @@ __device__ __forceinline__ void ntt_fwd_regs(uint64_t* a, uint64_t* sm, uint32_t
     if constexpr (FP) {
         double v[Sh::EPT];
 #pragma unroll
-        for (int u = 0; u < Sh::EPT; ++u) v[u] = (double)a[u];
+        for (int u = 0; u < Sh::EPT; ++u) v[u] = u52_to_double(a[u]);
         ntt_fwd_f<Sh>(v, sm, tid, tw, K, pi);
         const double p = K->pd[pi];
 #pragma unroll
@@ -415,7 +415,7 @@ __device__ __forceinline__ void ntt_inv_regs(uint64_t* a, uint64_t* sm, uint32_t
     if constexpr (FP) {
         double v[Sh::EPT];
 #pragma unroll
-        for (int u = 0; u < Sh::EPT; ++u) v[u] = (double)a[u];
+        for (int u = 0; u < Sh::EPT; ++u) v[u] = u52_to_double(a[u]);
         ntt_inv_f<Sh>(v, sm, tid, tw, K, pi);
         const double p = K->pd[pi];
 #pragma unroll
@@ -668,7 +668,7 @@ __global__ __launch_bounds__(Sh::T) void k_ntt_fwd_operand(const CtxConst* __res
     const uint32_t pi = pbase + (uint32_t)(g % nl);
     double v[Sh::EPT];
 #pragma unroll
-    for (int u = 0; u < Sh::EPT; ++u) v[u] = (double)in[natural_pos<Sh>(g, tid, u)];
+    for (int u = 0; u < Sh::EPT; ++u) v[u] = u52_to_double(in[natural_pos<Sh>(g, tid, u)]);
     ntt_fwd_f<Sh>(v, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
 #pragma unroll
     for (int u = 0; u < Sh::EPT; ++u) out[transformed_pos<Sh>(g, tid, u)] = v[u];
@@ -866,10 +866,10 @@ __global__ __launch_bounds__(Sh::T) void k_relin_f(const CtxConst* __restrict__ 
         const bool reduce = !LAZY || (i < L && i != j && K->pd[i] > 2.5 * p);
         if (reduce) {
 #pragma unroll
-            for (int u = 0; u < EPT; ++u) v[u] = fred(LAZY ? u52_to_double(nx[u]) : (double)nx[u], p, pinv);
+            for (int u = 0; u < EPT; ++u) v[u] = fred(u52_to_double(nx[u]), p, pinv);
         } else {
 #pragma unroll
-            for (int u = 0; u < EPT; ++u) v[u] = LAZY ? u52_to_double(nx[u]) : (double)nx[u];
+            for (int u = 0; u < EPT; ++u) v[u] = u52_to_double(nx[u]);
         }
         if (i + 1 < L + 2) {
             const uint64_t* src = src_row(i + 1);
@@ -1116,7 +1116,7 @@ __device__ __forceinline__ bool scale_coeff_fp(const CtxConst* K, const uint64_t
     for (int i = 0; i < NL; ++i)
         if (i < (int)L) {
             const double p = K->pd[i], pinv = K->pinv[i];
-            y[i] = fmulmod((double)x[i * xs], K->tqinvd[i], p, pinv);
+            y[i] = fmulmod(u52_to_double(x[i * xs]), K->tqinvd[i], p, pinv);
             S += y[i] * pinv;
         }
     const double v = __builtin_rint(S);
@@ -1128,7 +1128,8 @@ __device__ __forceinline__ bool scale_coeff_fp(const CtxConst* K, const uint64_t
         if (j < (int)LB) {
             const uint32_t jj = L + j;
             const double b = K->pd[jj], binv = K->pinv[jj];
-            double acc = fmulmod((double)x[jj * xs], K->kb1d[j], b, binv) + fmulmod(v, K->fqpd[j], b, binv);
+            double acc = fmulmod(u52_to_double(x[jj * xs]), K->kb1d[j], b, binv) +
+                         fmulmod(v, K->fqpd[j], b, binv);
 #pragma unroll
             for (int i = 0; i < NL; ++i)
                 if (i < (int)L) {
