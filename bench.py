@@ -314,8 +314,20 @@ def roofline(prof, steps, fp, traffic):
     return out
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(cfg, rlk, query, codewords, payload):
-    """The CPU oracle (plain textbook FV, OpenMP over elements) on a bounded sample."""
+    """The CPU oracle (plain textbook FV, OpenMP over elements) on a bounded sample, on all host
+    threads and, over a smaller sample, on one thread."""
     from oracle.core import Oracle
     orc = Oracle(cfg.N, cfg.primes, cfg.t)
     key = orc.load_key(rlk)
@@ -324,8 +336,16 @@ def cpu_baseline(cfg, rlk, query, codewords, payload):
     t0 = time.perf_counter()
     orc.answer(key, query, codewords, payload, threads=threads)
     dt = time.perf_counter() - t0
+    one = max(1, len(codewords) // 16)
+    log(f"cpu oracle: {one} elements on one thread")
+    t1 = time.perf_counter()
+    orc.answer(key, query, codewords[:one], payload[:one], threads=1)
+    dt1 = time.perf_counter() - t1
     return {"value": len(codewords) / dt, "unit": "elements/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(codewords)} of {cfg.n} elements of the same workload, one query, {dt:.1f} s"}
+            "sample": f"{len(codewords)} of {cfg.n} elements of the same workload, one query, {dt:.1f} s",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "one_thread": {"value": one / dt1, "unit": "elements/s",
+                           "sample": f"{one} elements of the same workload, one query, {dt1:.1f} s"}}
 
 
 def expansion_bench(args, ctx, cfg, torch, stream):
