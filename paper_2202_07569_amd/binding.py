@@ -126,13 +126,23 @@ def _torch():
     return torch
 
 
-def _stream(stream):
+def _stream(stream, *tensors):
+    """HIP stream handle for an asynchronous call on `stream` (default: torch's current stream of
+    the tensors' device).  Inputs the binding copied to the device and outputs it allocated belong
+    to torch's current stream; on another stream the call first waits for the current stream's
+    queued work, and the tensors are marked as used by that stream, so that torch's caching
+    allocator does not hand their memory to other work before the call has run."""
     torch = _torch()
+    dev = tensors[0].device if tensors else None
+    cur = torch.cuda.current_stream(dev)
     if stream is None:
-        return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
-    if isinstance(stream, int):
-        return ctypes.c_void_p(stream)
-    return ctypes.c_void_p(stream.cuda_stream)
+        return ctypes.c_void_p(cur.cuda_stream)
+    s = torch.cuda.ExternalStream(stream, device=dev) if isinstance(stream, int) else stream
+    if s.cuda_stream != cur.cuda_stream:
+        s.wait_stream(cur)
+        for t in tensors:
+            t.record_stream(s)
+    return ctypes.c_void_p(s.cuda_stream)
 
 
 def _dev_u64(x, device):
@@ -268,7 +278,7 @@ class Context:
         if out is None:
             out = self.empty(m, 2, self.L, self.N)
         arr = (ctypes.c_void_p * max(1, c))(*([k._h.value for k in gkeys[:c]] or [None]))
-        _check(lib().pir_expand(self._h, arr, c, _ptr(packed), h, m, _ptr(out), _stream(stream)))
+        _check(lib().pir_expand(self._h, arr, c, _ptr(packed), h, m, _ptr(out), _stream(stream, packed, out)))
         return out
 
     def arith_equality(self, key: Key, x, y, k: int, out=None, stream=None):
@@ -278,7 +288,7 @@ class Context:
         if out is None:
             out = self.empty(2, self.L, self.N)
         _check(lib().pir_arith_equality(self._h, key._h, _ptr(x), _ptr(y), x.shape[0], k, _ptr(out),
-                                        _stream(stream)))
+                                        _stream(stream, x, y, out)))
         return out
 
     def folklore_leaves(self, query, out=None, stream=None):
@@ -287,7 +297,7 @@ class Context:
         ell = query.shape[0]
         if out is None:
             out = self.empty(2 * ell, 2, self.L, self.N)
-        _check(lib().pir_folklore_leaves(self._h, _ptr(query), ell, _ptr(out), _stream(stream)))
+        _check(lib().pir_folklore_leaves(self._h, _ptr(query), ell, _ptr(out), _stream(stream, query, out)))
         return out
 
     def mod_switch(self, x, keep: int, out=None, stream=None):
@@ -298,7 +308,7 @@ class Context:
         count = int(np.prod(lead)) if lead else 1
         if out is None:
             out = self.empty(*lead, keep, self.N)
-        _check(lib().pir_mod_switch(self._h, _ptr(x), count, keep, _ptr(out), _stream(stream)))
+        _check(lib().pir_mod_switch(self._h, _ptr(x), count, keep, _ptr(out), _stream(stream, x, out)))
         return out
 
     def seeded_query(self, c0, seed: int, out=None, stream=None):
@@ -310,7 +320,7 @@ class Context:
         if out is None:
             out = self.empty(count, 2, self.L, self.N)
         _check(lib().pir_seeded_query(self._h, _ptr(c0), count, int(seed) & (2**64 - 1), _ptr(out),
-                                      _stream(stream)))
+                                      _stream(stream, c0, out)))
         return out
 
     def load_key(self, rlk) -> Key:
@@ -340,7 +350,7 @@ class Context:
         assert tuple(query.shape) == (db.m, 2, self.L, self.N)
         if out is None:
             out = self.empty(db.s, 2, self.L, self.N)
-        _check(lib().pir_answer(self._h, key._h, db._h, _ptr(query), _ptr(out), _stream(stream)))
+        _check(lib().pir_answer(self._h, key._h, db._h, _ptr(query), _ptr(out), _stream(stream, query, out)))
         return out
 
     def answer_batch(self, keys, dbs, queries, outs=None, stream=None):
@@ -351,7 +361,7 @@ class Context:
         arr = lambda xs: (ctypes.c_void_p * B)(*xs)  # noqa: E731
         _check(lib().pir_answer_batch(self._h, B, arr([k._h.value for k in keys]), arr([d._h.value for d in dbs]),
                                       arr([q.data_ptr() for q in queries]), arr([o.data_ptr() for o in outs]),
-                                      _stream(stream)))
+                                      _stream(stream, *queries, *outs)))
         return outs
 
     def capture(self, keys, dbs, queries, outs=None) -> "Graph":
@@ -376,19 +386,19 @@ class Context:
         if out is None:
             out = self.empty(len(el), 2, self.L, self.N)
         _check(lib().pir_selectors(self._h, key._h, db._h, _ptr(query), el.ctypes.data_as(ctypes.c_void_p), len(el),
-                                   _ptr(out), _stream(stream)))
+                                   _ptr(out), _stream(stream, query, out)))
         return out
 
     def mult(self, a, b, stream=None):
         a, b = _dev_u64(a, self.device), _dev_u64(b, self.device)
         out = self.empty(3, self.L, self.N)
-        _check(lib().pir_mult(self._h, _ptr(a), _ptr(b), _ptr(out), _stream(stream)))
+        _check(lib().pir_mult(self._h, _ptr(a), _ptr(b), _ptr(out), _stream(stream, a, b, out)))
         return out
 
     def relin(self, key: Key, c3, stream=None):
         c3 = _dev_u64(c3, self.device)
         out = self.empty(2, self.L, self.N)
-        _check(lib().pir_relin(self._h, key._h, _ptr(c3), _ptr(out), _stream(stream)))
+        _check(lib().pir_relin(self._h, key._h, _ptr(c3), _ptr(out), _stream(stream, c3, out)))
         return out
 
     def pm(self, ct, pt, stream=None):
@@ -398,7 +408,7 @@ class Context:
             pt = torch.from_numpy(np.ascontiguousarray(pt, dtype=np.uint16))
         pt = pt.to(self.device).contiguous()
         out = self.empty(2, self.L, self.N)
-        _check(lib().pir_pm(self._h, _ptr(ct), _ptr(pt), _ptr(out), _stream(stream)))
+        _check(lib().pir_pm(self._h, _ptr(ct), _ptr(pt), _ptr(out), _stream(stream, ct, pt, out)))
         return out
 
     # ---- codeword tables ----
@@ -406,14 +416,14 @@ class Context:
         torch = _torch()
         ids = _dev_u64(np.asarray(ids, dtype=np.uint64), self.device)
         out = torch.empty((ids.shape[0], k), dtype=torch.uint32, device=self.device)
-        _check(lib().pir_map_perfect(self._h, _ptr(ids), ids.shape[0], m, k, _ptr(out), _stream(stream)))
+        _check(lib().pir_map_perfect(self._h, _ptr(ids), ids.shape[0], m, k, _ptr(out), _stream(stream, ids, out)))
         return out
 
     def map_lossy(self, keywords, m: int, k: int, seed: int, stream=None):
         torch = _torch()
         kw = _dev_u64(np.asarray(keywords, dtype=np.uint64), self.device)
         out = torch.empty((kw.shape[0], k), dtype=torch.uint32, device=self.device)
-        _check(lib().pir_map_lossy(self._h, _ptr(kw), kw.shape[0], m, k, seed, _ptr(out), _stream(stream)))
+        _check(lib().pir_map_lossy(self._h, _ptr(kw), kw.shape[0], m, k, seed, _ptr(out), _stream(stream, kw, out)))
         return out
 
     # ---- profiling ----
@@ -473,7 +483,7 @@ class Graph:
         self.queries, self.outs = queries, outs
 
     def launch(self, stream=None):
-        _check(lib().pir_graph_launch(self._h, _stream(stream)))
+        _check(lib().pir_graph_launch(self._h, _stream(stream, *self.queries, *self.outs)))
         return self.outs
 
     def close(self):

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import datagen
+from conftest import cached_instance
 from oracle.client import build_instance
 from oracle.core import Oracle
 from oracle.mapping import lossy_map, perfect_map
@@ -284,3 +285,22 @@ def test_encode_db_rejects_bad_codewords():
     for cw in (np.array([[3, 3], [0, 1]]), np.array([[4, 2], [0, 1]]), np.array([[0, 24], [0, 1]])):
         with pytest.raises(PirError):
             ctx.encode_db(cw.astype(np.uint32), pay, 24)
+
+
+def test_answer_and_seeded_rebuild_on_a_side_stream_with_host_inputs():
+    """Host arrays are copied to the device on torch's current stream; a call on another stream
+    must wait for that copy and keep the copies alive until it has run."""
+    import torch
+    from oracle import seeded as S
+    cfg = PARAMS["tiny"].with_n(40)
+    ins = cached_instance(cfg)
+    ctx = ctx_for(cfg)
+    key, db = ctx.load_key(ins.rlk), ctx.encode_db(ins.codewords, ins.payload, cfg.m)
+    side = torch.cuda.Stream()  # default priority
+    _say("answer tiny n=40 on a side stream, host query")
+    got = ctx.answer(key, db, ins.query, stream=side)
+    c0 = datagen.uniform_residues(cfg.primes, (3,), cfg.N, seed=17)
+    full = ctx.seeded_query(c0, 99, stream=side)
+    side.synchronize()
+    assert np.array_equal(got.cpu().numpy(), ins.orc.answer(ins.key, ins.query, ins.codewords, ins.payload))
+    assert np.array_equal(full.cpu().numpy(), S.unseed(cfg.primes, cfg.N, c0, 99))
