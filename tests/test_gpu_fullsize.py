@@ -3,7 +3,9 @@
 The oracle cannot compute a whole answer over tens of thousands of elements in seconds, so at
 full size the checks use what holds at any size: the decrypted answer is the queried payload (zero
 for an absent keyword), sampled selectors equal the oracle's bit for bit, the answer is linear over
-a split of the database, and a batch equals the single answers.
+a split of the database, and a batch equals the single answers.  Contexts take the launch
+schedules the benchmark uses (the package's tuning cache): the plain loop's for single answers and,
+at the mid size, the batch-of-8 schedule for the benchmark's batched step.
 """
 import numpy as np
 import pytest
@@ -32,9 +34,19 @@ def _say(msg):
     print(f"[gpu-full] {msg}", flush=True)
 
 
-def _check(cfg, ins, samples, absent=False, split=None):
+def _context(cfg, batch=1):
+    """A context with the launch schedule the benchmark uses for `batch` queries per call (the
+    package's tuning cache), or the library default when the cache has none."""
     from paper_2202_07569_amd import Context
     ctx = Context(cfg.N, cfg.primes, cfg.t)
+    sched = ctx.cached_schedule(batch, cfg.k, cfg.s)
+    if sched is not None:
+        ctx.set_schedule(sched["chunk_elems"], min(sched["query_group"], batch), sched["relin_group"])
+    return ctx
+
+
+def _check(cfg, ins, samples, absent=False, split=None):
+    ctx = _context(cfg)
     key = ctx.load_key(ins.rlk)
     db = ctx.encode_db(ins.codewords, ins.payload, cfg.m)
     _say(f"{cfg.name}: answer over n={cfg.n}")
@@ -64,14 +76,19 @@ def test_mid_full_size():
     ins = build_instance(cfg)
     ctx, key, db, ans = _check(cfg, ins, [ins.target, 0, cfg.n - 1], split=9001)
     assert db.pair_count <= 351
-    # a batch of two queries on the database (the second for another element) equals the singles
-    other = (ins.target + 777) % cfg.n
-    q2 = encrypt_query(ins.orc, ins.sk, [int(v) for v in ins.codewords[other]], cfg.m, cfg.seed, draw=5)
-    _say("mid: batch of two")
-    outs = ctx.answer_batch([key, key], [db, db], [_dev(ins.query), _dev(q2)])
+    # the benchmark's batched step: 8 queries for 8 elements under the batch-8 schedule; query 0
+    # equals the plain answer bit for bit and every answer decrypts to its element's payload
+    ctx8 = _context(cfg, batch=8)
+    key8, db8 = ctx8.load_key(ins.rlk), ctx8.encode_db(ins.codewords, ins.payload, cfg.m)
+    others = [(ins.target + 777 * b) % cfg.n for b in range(1, 8)]
+    qs = [ins.query] + [encrypt_query(ins.orc, ins.sk, [int(v) for v in ins.codewords[o]], cfg.m, cfg.seed,
+                                      draw=4 + b) for b, o in enumerate(others)]
+    _say(f"mid: batch of 8 under schedule {ctx8.schedule()}")
+    outs = ctx8.answer_batch([key8] * 8, [db8] * 8, [_dev(q) for q in qs])
     assert np.array_equal(_host(outs[0]), ans)
-    msg, _ = ins.orc.decrypt(ins.sk, _host(outs[1])[0])
-    assert np.array_equal(msg, ins.payload[other][0].astype(np.uint64))
+    for o, out in zip(others, outs[1:]):
+        msg, _ = ins.orc.decrypt(ins.sk, _host(out)[0])
+        assert np.array_equal(msg, ins.payload[o][0].astype(np.uint64)), o
 
 
 def test_large_full_size():
