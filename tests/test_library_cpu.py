@@ -93,3 +93,31 @@ def test_seeded_query_rejects_null_context():
     L = binding.lib()
     assert L.pir_seeded_query(None, None, 1, 7, None, None) == binding.PIR_E_INVALID
     assert "null context" in L.pir_last_error().decode()
+
+
+def test_schedule_cache_round_trip(tmp_path):
+    from paper_2202_07569_amd.binding import lookup_schedule, record_schedule
+    path = str(tmp_path / "cache.json")
+    primes = (0x7fffffd8001, 0x7fffffc8001)
+    assert lookup_schedule(8192, primes, 8, 4, 1, path=path) is None
+    a = {"chunk_elems": 512, "query_group": 1, "relin_group": 0}
+    b = {"chunk_elems": 256, "query_group": 2, "relin_group": 32}
+    record_schedule(8192, primes, 8, 4, 1, a, "first", path=path)
+    record_schedule(8192, primes, 1, 4, 1, b, "batch 1", path=path)
+    assert lookup_schedule(8192, primes, 8, 4, 1, path=path) == a
+    assert lookup_schedule(8192, primes, 1, 4, 1, path=path) == b
+    assert lookup_schedule(8192, primes, 8, 2, 1, path=path) is None        # other k
+    assert lookup_schedule(8192, primes[::-1], 8, 4, 1, path=path) is None  # other prime order
+    record_schedule(8192, primes, 8, 4, 1, b, "replaced", path=path)        # replaces, no duplicate
+    assert lookup_schedule(8192, primes, 8, 4, 1, path=path) == b
+    import json
+    assert len(json.load(open(path))["entries"]) == 2
+
+
+def test_package_tuning_cache_is_well_formed():
+    import json
+    from paper_2202_07569_amd.binding import SCHEDULE_CACHE
+    for e in json.load(open(SCHEDULE_CACHE))["entries"]:
+        sch = e["schedule"]
+        assert 1 <= sch["chunk_elems"] <= 4096 and 1 <= sch["query_group"] <= 8 and sch["relin_group"] >= 0
+        assert all(p % (2 * e["N"]) == 1 for p in e["primes"])
