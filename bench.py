@@ -464,7 +464,8 @@ QUERY_POOL = 4  # distinct synthetic query ciphertexts per database, reused roun
 
 def serve_bench(args, torch):
     """Replay one seeded arrival trace through (i) the plain loop, which answers one query at a time
-    in arrival order with pir_answer, and (ii) the continuous-batching server (pir_serve_*).
+    in arrival order with pir_answer, and (ii) the continuous-batching server (pir_serve_*) under
+    its three policies (round robin, oldest first, size aged).
 
     Latency runs from a query's arrival (host clock; its ciphertexts are already resident) to its
     answer being complete on the device.  Elements/s = sum of the queried databases' sizes / time
@@ -510,6 +511,8 @@ def serve_bench(args, torch):
         svc.append(float(np.median(reps)))
     S = float(np.mean(svc))
     log(f"plain service times {[round(x * 1e3, 1) for x in svc]} ms, S = {S * 1e3:.1f} ms")
+    # size-aged order: priority = arrival + aging * elements, aging twice the plain cost per element
+    aging = 2.0 * float(np.mean([svc[d] / cfgs[d].n for d in range(len(cfgs))])) * 1e9
 
     def plain(arr):
         lat = np.zeros(Q)
@@ -526,8 +529,8 @@ def serve_bench(args, torch):
             lat[i] = done - arr[i]
         return lat, done - arr[0]
 
-    def batched(arr, policy=Server.ROUND_ROBIN):
-        srv = Server(ctx, max_slots=args.serve_slots, policy=policy)
+    def batched(arr, policy=Server.ROUND_ROBIN, aging=0.0):
+        srv = Server(ctx, max_slots=args.serve_slots, policy=policy, aging_ns_per_element=aging)
         lat = np.zeros(Q)
         live = {}
         i = nd = 0
@@ -570,18 +573,23 @@ def serve_bench(args, torch):
         lb, tb, st = batched(arr)
         log(f"rate {mult}/S: continuous batching, oldest first")
         lf, tf, stf = batched(arr, Server.OLDEST_FIRST)
+        log(f"rate {mult}/S: size-aged order, aging {aging:.0f} ns per element")
+        lg, tg, stg = batched(arr, Server.SIZE_AGED, aging)
         pct = lambda x: {"p50_ms": float(np.percentile(x, 50) * 1e3),  # noqa: E731
                          "p99_ms": float(np.percentile(x, 99) * 1e3), "mean_ms": float(x.mean() * 1e3)}
         entry = {"rate_per_s": rate, "rate_over_S": mult,
                  "plain": {"elements_per_s": elems / tp, "wall_s": tp, **pct(lp)},
                  "batched": {"elements_per_s": elems / tb, "wall_s": tb, **pct(lb), "rounds": st["rounds"]},
                  "batched_oldest_first": {"elements_per_s": elems / tf, "wall_s": tf, **pct(lf),
-                                          "rounds": stf["rounds"]}}
+                                          "rounds": stf["rounds"]},
+                 "size_aged": {"elements_per_s": elems / tg, "wall_s": tg, **pct(lg), "rounds": stg["rounds"],
+                               "aging_ns_per_element": aging}}
         log(f"rate {mult}/S: plain {entry['plain']['elements_per_s']:.0f} el/s p50 {entry['plain']['p50_ms']:.0f} "
             f"p99 {entry['plain']['p99_ms']:.0f} ms | batched {entry['batched']['elements_per_s']:.0f} el/s "
             f"p50 {entry['batched']['p50_ms']:.0f} p99 {entry['batched']['p99_ms']:.0f} ms | oldest first "
             f"{entry['batched_oldest_first']['elements_per_s']:.0f} el/s p50 {entry['batched_oldest_first']['p50_ms']:.0f} "
-            f"p99 {entry['batched_oldest_first']['p99_ms']:.0f} ms")
+            f"p99 {entry['batched_oldest_first']['p99_ms']:.0f} ms | size aged {entry['size_aged']['elements_per_s']:.0f} "
+            f"el/s p50 {entry['size_aged']['p50_ms']:.0f} p99 {entry['size_aged']['p99_ms']:.0f} ms")
         res["rates"].append(entry)
     return res
 

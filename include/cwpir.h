@@ -61,7 +61,7 @@ extern "C" {
 #define PIR_E_INVALID (-1)     /* bad shape or parameter, residue >= q_i, bad codeword          */
 #define PIR_E_NOMEM (-2)       /* allocation failed or the HBM budget is exceeded               */
 #define PIR_E_DEVICE (-3)      /* HIP runtime error; the context is poisoned                    */
-#define PIR_E_BUSY (-4)        /* reserved                                                      */
+#define PIR_E_BUSY (-4)        /* the server is not idle (pir_serve_set_policy)                 */
 #define PIR_E_UNSUPPORTED (-5) /* N not in {4096, 8192, 16384}, L or k out of range             */
 
 #define PIR_MAX_L 12           /* ciphertext primes */
@@ -141,7 +141,15 @@ int pir_answer_batch(pir_ctx* ctx, uint32_t B, const pir_key* const* keys, const
  *                     database with active queries by one chunk, so queries share the GPU (short
  *                     queries finish early); PIR_SERVE_OLDEST_FIRST only the database of the oldest
  *                     active query, whose later queries ride along (first come, first served, with
- *                     batching).  Answers do not depend on the policy.
+ *                     batching); PIR_SERVE_SIZE_AGED only the active query with the smallest
+ *                     priority submit time + aging * (elements of its database), one chunk per
+ *                     round and no ride-along (a size-aware ordering that keeps the tail of first
+ *                     come, first served; see pir_serve_set_aging).  Answers do not depend on the
+ *                     policy.  Only an idle server (nothing queued or active) changes its policy:
+ *                     PIR_E_BUSY otherwise.
+ *   pir_serve_set_aging  the weight of PIR_SERVE_SIZE_AGED, in nanoseconds per database element
+ *                     (>= 0, finite; default 0, which orders by submission).  Applies to queries
+ *                     admitted afterwards.
  *   pir_serve_close   wait for the server's queued work and release its slots and stream.
  * A server belongs to one context; calls on it are serialised with that context's other calls. */
 int pir_serve_open(pir_ctx* ctx, uint32_t max_slots, pir_server** out);
@@ -151,7 +159,9 @@ int pir_serve_step(pir_server* srv);
 int pir_serve_poll(pir_server* srv, uint64_t ticket);
 #define PIR_SERVE_ROUND_ROBIN 0
 #define PIR_SERVE_OLDEST_FIRST 1
+#define PIR_SERVE_SIZE_AGED 2
 int pir_serve_set_policy(pir_server* srv, int policy);
+int pir_serve_set_aging(pir_server* srv, double ns_per_element);
 int pir_serve_stats(pir_server* srv, uint64_t* rounds, uint64_t* admitted, uint64_t* completed,
                     uint32_t* active, uint32_t* pending);
 void pir_serve_close(pir_server* srv);

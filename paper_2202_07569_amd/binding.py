@@ -24,6 +24,7 @@ EXPORTS = [
     "pir_serve_close", "pir_get_schedule", "pir_set_schedule", "pir_autotune", "pir_graph_capture",
     "pir_graph_launch", "pir_graph_free", "pir_load_galois_key", "pir_expand", "pir_mod_switch",
     "pir_folklore_leaves", "pir_arith_equality", "pir_serve_set_policy", "pir_seeded_query",
+    "pir_serve_set_aging",
 ]
 
 
@@ -107,6 +108,7 @@ def lib():
             "pir_arith_equality": (i32, [vp, vp, vp, vp, u32, u32, vp, vp]),
             "pir_serve_set_policy": (i32, [vp, i32]),
             "pir_seeded_query": (i32, [vp, vp, u32, ctypes.c_uint64, vp, vp]),
+            "pir_serve_set_aging": (i32, [vp, ctypes.c_double]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -506,13 +508,15 @@ class Server:
     back the answer tensor.  The binding keeps each query and answer tensor alive until then.
     """
 
-    ROUND_ROBIN, OLDEST_FIRST = 0, 1
+    ROUND_ROBIN, OLDEST_FIRST, SIZE_AGED = 0, 1, 2
 
-    def __init__(self, ctx: Context, max_slots: int = 16, policy: int = 0):
+    def __init__(self, ctx: Context, max_slots: int = 16, policy: int = 0, aging_ns_per_element: float = 0.0):
         self.ctx = ctx
         h = ctypes.c_void_p()
         _check(lib().pir_serve_open(ctx._h, max_slots, ctypes.byref(h)))
         self._h = h
+        if aging_ns_per_element:
+            _check(lib().pir_serve_set_aging(h, float(aging_ns_per_element)))
         if policy:
             _check(lib().pir_serve_set_policy(h, policy))
         self._live = {}   # ticket -> (query, answer) while queued or running

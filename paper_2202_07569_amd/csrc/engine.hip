@@ -14,6 +14,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
+#include <cmath>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -940,7 +942,9 @@ extern "C" int pir_selectors(pir_ctx* ctx, const pir_key* key, const pir_db* db,
 // that same chunk together (one selector launch per stage for up to MAX_QB queries, one payload
 // transform, one multiply-accumulate).  A database's chunk cursor keeps rotating, so a query that
 // joins mid-scan starts at the current chunk and leaves after one full cycle: the answer is a sum
-// over all chunks and does not depend on their order.  At most two rounds are in flight.
+// over all chunks and does not depend on their order.  Under the size-aged policy a round instead
+// advances the one active query with the smallest priority along its own cursor.  At most two
+// rounds are in flight.
 // ------------------------------------------------------------------------------------------------
 struct ServeReq {
     const pir_key* key;
@@ -948,6 +952,7 @@ struct ServeReq {
     const uint64_t* query;
     uint64_t* answer;
     uint64_t ticket;
+    uint64_t submit_ns;  // host steady clock at submission
 };
 
 struct ServeSlot {
@@ -955,6 +960,8 @@ struct ServeSlot {
     const pir_db* db = nullptr;
     uint64_t ticket = 0;
     uint32_t chunks_left = 0;
+    uint32_t next = 0;   // PIR_SERVE_SIZE_AGED: the query's own next chunk
+    double key = 0.0;    // PIR_SERVE_SIZE_AGED: priority (smaller first)
     QState qs;
     uint64_t* buf = nullptr;  // QX, nodes and sel of this slot
     size_t buf_words = 0;
@@ -972,6 +979,7 @@ struct pir_server {
     uint64_t next_ticket = 1;
     uint64_t n_rounds = 0, n_admitted = 0, n_completed = 0;
     int policy = PIR_SERVE_ROUND_ROBIN;
+    double aging_ns = 0.0;  // PIR_SERVE_SIZE_AGED weight per database element
 };
 
 extern "C" int pir_serve_open(pir_ctx* ctx, uint32_t max_slots, pir_server** out) {
@@ -998,7 +1006,10 @@ extern "C" int pir_serve_submit(pir_server* srv, const pir_key* key, const pir_d
     if (!key || !db || !query || !answer || !ticket) return fail(PIR_E_INVALID, "null argument");
     if (key->ctx != ctx || db->ctx != ctx) return fail(PIR_E_INVALID, "handle from another context");
     *ticket = srv->next_ticket++;
-    srv->pending.push_back({key, db, query, answer, *ticket});
+    const uint64_t now = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+                             std::chrono::steady_clock::now().time_since_epoch())
+                             .count();
+    srv->pending.push_back({key, db, query, answer, *ticket, now});
     srv->in_flight.insert(*ticket);
     return PIR_OK;
 }
@@ -1031,6 +1042,8 @@ static int serve_admit(pir_server* srv, const Launch& lc, const Bufs& b) {
         sl.db = r.db;
         sl.ticket = r.ticket;
         sl.chunks_left = num_chunks(ctx, r.db);
+        sl.next = 0;
+        sl.key = (double)r.submit_ns + srv->aging_ns * (double)r.db->n;
         sl.qs = QState{};
         sl.qs.key = r.key;
         sl.qs.query = r.query;
@@ -1074,15 +1087,31 @@ extern "C" int pir_serve_step(pir_server* srv) {
     Bufs b;
     CW_TRY(get_bufs(ctx, ctx->chunk, ctx->qb, max_s, b));
     CW_TRY(serve_admit(srv, lc, b));
-    // one round: every database with active queries advances by one chunk (round robin), or only
-    // the database of the oldest active query (oldest first)
+    if (srv->policy == PIR_SERVE_SIZE_AGED) {  // one chunk of the query with the smallest priority
+        ServeSlot* best = nullptr;
+        for (ServeSlot& sl : srv->slots)
+            if (sl.used && (!best || sl.key < best->key || (sl.key == best->key && sl.ticket < best->ticket)))
+                best = &sl;
+        if (best) {
+            const uint32_t nc = num_chunks(ctx, best->db);
+            if (nc) {
+                QState* q = &best->qs;
+                CW_TRY(chunk_step(ctx, lc, b, best->db, best->next, &q, 1));
+                best->next = (best->next + 1) % nc;
+            }
+            if (best->chunks_left) --best->chunks_left;
+            if (!best->chunks_left) CW_TRY(serve_finish(srv, lc, *best));
+        }
+    }
+    // otherwise one round: every database with active queries advances by one chunk (round robin),
+    // or only the database of the oldest active query (oldest first)
     std::vector<const pir_db*> dbs;
     if (srv->policy == PIR_SERVE_OLDEST_FIRST) {
         const ServeSlot* oldest = nullptr;
         for (const ServeSlot& sl : srv->slots)
             if (sl.used && (!oldest || sl.ticket < oldest->ticket)) oldest = &sl;
         if (oldest) dbs.push_back(oldest->db);
-    } else {
+    } else if (srv->policy == PIR_SERVE_ROUND_ROBIN) {
         for (const ServeSlot& sl : srv->slots)
             if (sl.used && std::find(dbs.begin(), dbs.end(), sl.db) == dbs.end()) dbs.push_back(sl.db);
     }
@@ -1120,9 +1149,21 @@ extern "C" int pir_serve_step(pir_server* srv) {
 extern "C" int pir_serve_set_policy(pir_server* srv, int policy) {
     if (!srv) return fail(PIR_E_INVALID, "null server");
     CW_ENTER(srv->ctx);
-    if (policy != PIR_SERVE_ROUND_ROBIN && policy != PIR_SERVE_OLDEST_FIRST)
+    if (policy != PIR_SERVE_ROUND_ROBIN && policy != PIR_SERVE_OLDEST_FIRST && policy != PIR_SERVE_SIZE_AGED)
         return fail(PIR_E_INVALID, "unknown serving policy");
+    bool busy = !srv->pending.empty();
+    for (const ServeSlot& sl : srv->slots) busy = busy || sl.used;
+    if (busy && policy != srv->policy) return fail(PIR_E_BUSY, "the policy changes only on an idle server");
     srv->policy = policy;
+    return PIR_OK;
+}
+
+extern "C" int pir_serve_set_aging(pir_server* srv, double ns_per_element) {
+    if (!srv) return fail(PIR_E_INVALID, "null server");
+    CW_ENTER(srv->ctx);
+    if (!(ns_per_element >= 0.0) || !std::isfinite(ns_per_element))
+        return fail(PIR_E_INVALID, "aging must be finite and non-negative");
+    srv->aging_ns = ns_per_element;
     return PIR_OK;
 }
 

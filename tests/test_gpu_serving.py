@@ -51,14 +51,14 @@ def _query(insts, ki, di, target, draw):
     return encrypt_query(ci.orc, ci.sk, pos, db.cfg.m, ci.cfg.seed, draw=draw)
 
 
-@pytest.mark.parametrize("policy", [0, 1], ids=["round_robin", "oldest_first"])
+@pytest.mark.parametrize("policy", [0, 1, 2], ids=["round_robin", "oldest_first", "size_aged"])
 def test_serving_mix_equals_single_answers(mix, policy):
     from paper_2202_07569_amd import PirError, Server
     insts, ctx, keys, dbs = mix
     # (client key, database, element)
     plan = [(0, 0, 17), (1, 1, 119), (2, 0, 199), (0, 2, 45), (1, 0, 0), (2, 2, 89), (0, 1, 64), (1, 2, 3)]
     qs = [_query(insts, ki, di, j, draw=10 + n) for n, (ki, di, j) in enumerate(plan)]
-    srv = Server(ctx, max_slots=4, policy=policy)
+    srv = Server(ctx, max_slots=4, policy=policy, aging_ns_per_element=1e6 if policy == 2 else 0.0)
     tickets = []
     _say("submit 2, step 2")
     for n in range(2):
@@ -144,4 +144,36 @@ def test_oldest_first_runs_one_database_at_a_time(mix):
     srv.drain([tb])
     assert np.array_equal(_host(srv.result(ta)), _host(ctx.answer(keys[0], dbs[2], _dev(qa))))
     assert np.array_equal(_host(srv.result(tb)), _host(ctx.answer(keys[1], dbs[0], _dev(qb))))
+    srv.close()
+
+
+@pytest.mark.parametrize("aging", [0.0, 1e9])
+def test_size_aged_order(mix, aging):
+    """Size aged: one query per round along its own chunk cursor.  With no aging the first query
+    submitted runs first; with a large aging the query on the smaller database (90 elements, 3
+    chunks) overtakes the one on the larger (200 elements, 7 chunks).  Answers equal the singles."""
+    import torch
+    from paper_2202_07569_amd import Server
+    from paper_2202_07569_amd.binding import PIR_E_BUSY, lib
+    insts, ctx, keys, dbs = mix
+    qa, qb = _query(insts, 0, 0, 33, draw=60), _query(insts, 1, 2, 7, draw=61)
+    srv = Server(ctx, max_slots=2, policy=Server.SIZE_AGED, aging_ns_per_element=aging)
+    ta = srv.submit(keys[0], dbs[0], _dev(qa))  # 200 elements: 7 chunks of 32
+    tb = srv.submit(keys[1], dbs[2], _dev(qb))  # 90 elements: 3 chunks
+    assert lib().pir_serve_set_policy(srv._h, Server.ROUND_ROBIN) == PIR_E_BUSY
+    first, n_first = (tb, 3) if aging else (ta, 7)
+    second, n_second = (ta, 7) if aging else (tb, 3)
+    _say(f"size aged, aging {aging}: {n_first} rounds for the first query")
+    for _ in range(n_first):
+        srv.step()
+    torch.cuda.synchronize()
+    assert srv.poll(first) and not srv.poll(second)
+    steps = 0
+    while srv.step() > 0:  # the other query has not advanced: all of its rounds remain
+        steps += 1
+        assert steps <= n_second
+    assert steps + 1 == n_second
+    srv.drain([second])
+    assert np.array_equal(_host(srv.result(ta)), _host(ctx.answer(keys[0], dbs[0], _dev(qa))))
+    assert np.array_equal(_host(srv.result(tb)), _host(ctx.answer(keys[1], dbs[2], _dev(qb))))
     srv.close()

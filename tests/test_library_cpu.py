@@ -121,3 +121,9 @@ def test_package_tuning_cache_is_well_formed():
         sch = e["schedule"]
         assert 1 <= sch["chunk_elems"] <= 4096 and 1 <= sch["query_group"] <= 8 and sch["relin_group"] >= 0
         assert all(p % (2 * e["N"]) == 1 for p in e["primes"])
+
+
+def test_serving_aging_rejects_null_server():
+    L = binding.lib()
+    assert L.pir_serve_set_aging(None, 1.0) == binding.PIR_E_INVALID
+    assert "null server" in L.pir_last_error().decode()
