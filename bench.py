@@ -109,7 +109,7 @@ def main():
         first = res["rates"][0]["batched"]
         print(json.dumps({"metric": "DB elements answered/sec + p50/p99 query latency, batched serving vs plain",
                           "value": first["elements_per_s"], "unit": "elements/s", "n_gpus": 1,
-                          "higher_is_better": True, "dtype": "u64", "data": "synthetic",
+                          "higher_is_better": True, "dtype": "f64", "data": "synthetic",
                           "config": {"workload": res["workload"]}, "serving": res}), flush=True)
         return
 
@@ -241,7 +241,7 @@ def main():
         "metric": "DB elements answered/sec (N=8192, k=4) + p50/p99 query latency, batched vs plain",
         "value": value, "unit": "elements/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "u64", "data": "synthetic",
+        "dtype": "f64" if fp else "u64", "data": "synthetic",
         "config": {"workload": f"index PIR {cfg.name}: N={cfg.N}, {cfg.L} primes ({math.prod(cfg.primes).bit_length()}"
                                f" bits), t={cfg.t}, k={cfg.k}, m={cfg.m}, n={n}, s={cfg.s}",
                    "batch_queries": B},
