@@ -31,6 +31,7 @@ sys.path.insert(0, ROOT)
 import datagen  # noqa: E402
 
 MI355X_HBM_GBPS = 8000.0
+MI355X_CUS, MI355X_CLOCK_HZ = 256, 2.4e9
 # Integer ALU roof: 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz = 78.6 T lane-ops/s for
 # full-rate 32-bit operations; the 32-bit multipliers (v_mul_lo_u32, v_mul_hi_u32,
 # v_mad_u64_u32) run at half that rate, 39.3 T/s (measured 31-33 T/s with an ALU-only probe).
@@ -74,6 +75,8 @@ def parse():
     ap.add_argument("--serve-rates", default="0.8", help="arrival rates as multiples of 1/S (S: mean plain service time)")
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--serve-only", action="store_true", help="skip the mid workload")
+    ap.add_argument("--probe", action="store_true",
+                    help="only the fp64 issue-rate probe (pir_probe_fp64): wave-instructions per CU per clock")
     ap.add_argument("--batched-only", action="store_true",
                     help="time only the batched step (no plain loop, graph replay, expansion, folklore or "
                          "arithmetic timings): the launches a counter pass attributes to each kernel family "
@@ -102,6 +105,18 @@ def main():
     import torch
 
     from paper_2202_07569_amd import Context
+
+    if args.probe:
+        cfg = datagen.CONFIGS[args.workload]
+        ctx = Context(cfg.N, cfg.primes, cfg.t)
+        rows = []
+        for op, name in enumerate(Context.PROBE_OPS):
+            ms, wi = ctx.probe_fp64(op)
+            rate = wi / (ms * 1e-3) / (MI355X_CUS * MI355X_CLOCK_HZ)
+            log(f"probe {name}: {ms:.3f} ms, {rate:.3f} wave-instructions per CU per clock at 2.4 GHz")
+            rows.append({"op": name, "ms": ms, "wave_instructions": wi, "per_cu_per_clock": rate})
+        print(json.dumps({"probe_fp64": rows, "cus": MI355X_CUS, "clock_hz": MI355X_CLOCK_HZ}), flush=True)
+        return
 
     serve = args.serve == 1 or (args.serve == -1 and args.workload == "mid")
     if args.serve_only:

@@ -305,6 +305,16 @@ int pir_profile_enable(pir_ctx* ctx, int on);
 int pir_profile_read(pir_ctx* ctx, uint32_t max, const char** names, double* total_ms, uint64_t* launches,
                      double* work, int reset);
 
+/* Diagnostics: issue rate of the fp64 instructions the transforms are built from.  Runs `blocks`
+ * workgroups of 256 threads, each thread `iters` steps of one operation on 8 independent chains
+ * (op 0 v_fma_f64, 1 v_mul_f64, 2 v_add_f64, 3 v_rndne_f64 followed by v_add_f64), once to warm up
+ * and once timed with HIP events on `stream`; *ms receives the timed launch's duration and
+ * *wave_instr the wave-instructions it issued of the timed operation(s).  1 <= blocks <= 2^20,
+ * 1 <= iters <= 2^20.  Synchronous.  The rate (wave_instr / time) per CU and clock is the
+ * reference for what the kernels' SQ_INSTS_VALU / SQ_BUSY_CU_CYCLES counters can reach. */
+int pir_probe_fp64(pir_ctx* ctx, int op, uint32_t blocks, uint32_t iters, double* ms, double* wave_instr,
+                   void* stream);
+
 void pir_db_free(pir_db* db);
 void pir_key_free(pir_key* key);
 void pir_free(pir_ctx* ctx);

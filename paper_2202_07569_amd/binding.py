@@ -24,7 +24,7 @@ EXPORTS = [
     "pir_serve_close", "pir_get_schedule", "pir_set_schedule", "pir_autotune", "pir_graph_capture",
     "pir_graph_launch", "pir_graph_free", "pir_load_galois_key", "pir_expand", "pir_mod_switch",
     "pir_folklore_leaves", "pir_arith_equality", "pir_serve_set_policy", "pir_seeded_query",
-    "pir_serve_set_aging",
+    "pir_serve_set_aging", "pir_probe_fp64",
 ]
 
 
@@ -109,6 +109,8 @@ def lib():
             "pir_serve_set_policy": (i32, [vp, i32]),
             "pir_seeded_query": (i32, [vp, vp, u32, ctypes.c_uint64, vp, vp]),
             "pir_serve_set_aging": (i32, [vp, ctypes.c_double]),
+            "pir_probe_fp64": (i32, [vp, i32, u32, u32, ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double), vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -429,6 +431,15 @@ class Context:
         return out
 
     # ---- profiling ----
+    PROBE_OPS = ("v_fma_f64", "v_mul_f64", "v_add_f64", "v_rndne_f64 + v_add_f64")
+
+    def probe_fp64(self, op: int, blocks: int = 4096, iters: int = 4096, stream=None):
+        """Issue-rate probe (pir_probe_fp64): (milliseconds, wave-instructions) of one timed launch."""
+        ms, wi = ctypes.c_double(), ctypes.c_double()
+        _check(lib().pir_probe_fp64(self._h, op, blocks, iters, ctypes.byref(ms), ctypes.byref(wi),
+                                    _stream(stream)))
+        return ms.value, wi.value
+
     def profile(self, on: bool = True):
         _check(lib().pir_profile_enable(self._h, 1 if on else 0))
 

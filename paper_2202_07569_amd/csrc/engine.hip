@@ -1317,6 +1317,37 @@ extern "C" int pir_map_lossy(pir_ctx* ctx, const uint64_t* keywords, uint64_t n,
 // ------------------------------------------------------------------------------------------------
 // profiling
 // ------------------------------------------------------------------------------------------------
+extern "C" int pir_probe_fp64(pir_ctx* ctx, int op, uint32_t blocks, uint32_t iters, double* ms,
+                              double* wave_instr, void* stream) {
+    CW_ENTER(ctx);
+    if (!ms || !wave_instr) return fail(PIR_E_INVALID, "null argument");
+    if (op < 0 || op > 3) return fail(PIR_E_INVALID, "op must be 0 (fma), 1 (mul), 2 (add) or 3 (rint + add)");
+    if (blocks < 1 || blocks > (1u << 20) || iters < 1 || iters > (1u << 20))
+        return fail(PIR_E_INVALID, "blocks and iters must lie in [1, 2^20]");
+    hipStream_t st = (hipStream_t)stream;
+    CW_TRY(begin_async(ctx, st));
+    double* out;
+    CW_TRY(ws_get_t(ctx, "probe", (size_t)blocks * cw::probe_threads(), &out));
+    hipEvent_t e0, e1;
+    CW_HIP(ctx, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(PIR_E_DEVICE, "event creation failed");
+    }
+    cw::launch_probe_fp64(st, op, blocks, iters, out);  // warm-up
+    (void)hipEventRecord(e0, st);
+    const double wi = cw::launch_probe_fp64(st, op, blocks, iters, out);
+    (void)hipEventRecord(e1, st);
+    float t = 0.f;
+    const bool ok = hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t, e0, e1) == hipSuccess;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (!ok) return fail(PIR_E_DEVICE, "probe timing failed");
+    *ms = t;
+    *wave_instr = wi;
+    return end_async(ctx, st);
+}
+
 extern "C" int pir_profile_enable(pir_ctx* ctx, int on) {
     CW_ENTER(ctx);
     ctx->prof = on != 0;

@@ -101,6 +101,11 @@ void launch_folklore_leaves(const Launch& lc, const uint64_t* query, uint32_t el
 // Seeded query ciphertexts (seeded.hip): out [count][2][L][N] with out[i][0] = c0[i] ([count][L][N])
 // and out[i][1] the uniform polynomial regenerated from `seed`.
 void launch_seeded_query(const Launch& lc, const uint64_t* c0, uint32_t count, uint64_t seed, uint64_t* out);
+// fp64 issue-rate probe (probe.hip): `blocks` workgroups of probe_threads() threads run `iters`
+// steps of operation op (0 fma, 1 mul, 2 add, 3 rint + add) on 8 independent chains each, writing
+// one double per thread to out; returns the wave-instructions of the timed operation(s).
+uint32_t probe_threads();
+double launch_probe_fp64(hipStream_t st, int op, uint32_t blocks, uint32_t iters, double* out);
 // Row gather: dst row e = src row order[e] for e < n, rows of `row` uint16 (a multiple of 8).
 void launch_gather_rows(hipStream_t st, const uint16_t* src, const uint64_t* order, uint64_t n, size_t row,
                         uint16_t* dst);
