@@ -127,3 +127,9 @@ def test_serving_aging_rejects_null_server():
     L = binding.lib()
     assert L.pir_serve_set_aging(None, 1.0) == binding.PIR_E_INVALID
     assert "null server" in L.pir_last_error().decode()
+
+
+def test_probe_rejects_null_context():
+    L = binding.lib()
+    ms, wi = ctypes.c_double(), ctypes.c_double()
+    assert L.pir_probe_fp64(None, 0, 1, 1, ctypes.byref(ms), ctypes.byref(wi), None) == binding.PIR_E_INVALID
