@@ -1,12 +1,20 @@
 """Full-size checks of the HIP path in the configuration the benchmark times.
 
-The oracle cannot compute a whole answer over tens of thousands of elements in seconds, so at
-full size the checks use what holds at any size: the decrypted answer is the queried payload (zero
-for an absent keyword), sampled selectors equal the oracle's bit for bit, the answer is linear over
-a split of the database, and a batch equals the single answers.  Contexts take the launch
-schedules the benchmark uses (the package's tuning cache): the plain loop's for single answers and,
-at the mid size, the batch-of-8 schedule for the benchmark's batched step.
+At the mid size (the workload the benchmark times) the GPU answer is compared element by element
+with the oracle's full answer, which a committed script computes from `oracle/` alone
+(`tests/golden/make_mid_answer.py`, stored in `tests/golden/mid_answer.npz`): under the plain
+loop's schedule and as query 0 of the benchmark's batch of 8.  The oracle cannot compute a whole
+answer over the large and keyword databases in seconds, so there the checks use what holds at any
+size: the decrypted answer is the queried payload (zero for an absent keyword), sampled selectors
+equal the oracle's bit for bit, the answer is linear over a split of the database, and a batch
+equals the single answers (their parameters are compared with the oracle's whole answer on small
+databases in `test_gpu_params_parity.py`).  Contexts take the launch schedules the benchmark uses
+(the package's tuning cache): the plain loop's for single answers and, at the mid size, the
+batch-of-8 schedule for the benchmark's batched step.
 """
+import hashlib
+import os
+
 import numpy as np
 import pytest
 
@@ -71,11 +79,32 @@ def _check(cfg, ins, samples, absent=False, split=None):
     return ctx, key, db, ans
 
 
+GOLDEN_MID = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "mid_answer.npz")
+
+
+def _golden_mid(target):
+    """The oracle's full mid answer from the committed golden file (checked against its digest)."""
+    with np.load(GOLDEN_MID, allow_pickle=False) as z:
+        want, digest, tgt = z["answer"], str(z["sha256"]), int(z["target"])
+    assert hashlib.sha256(np.ascontiguousarray(want).tobytes()).hexdigest() == digest
+    assert tgt == target
+    return want
+
+
+def _diff(got, want):
+    bad = np.argwhere(got != want)
+    return f"{len(bad)} residues differ, first at {tuple(bad[0]) if len(bad) else None}"
+
+
 def test_mid_full_size():
     cfg = datagen.CONFIGS["mid"]
     ins = build_instance(cfg)
     ctx, key, db, ans = _check(cfg, ins, [ins.target, 0, cfg.n - 1], split=9001)
     assert db.pair_count <= 351
+    _say(f"mid: plain answer under schedule {ctx.schedule()} against the oracle's full answer")
+    want = _golden_mid(ins.target)
+    assert ans.shape == want.shape
+    assert np.array_equal(ans, want), _diff(ans, want)
     # the benchmark's batched step: 8 queries for 8 elements under the batch-8 schedule; query 0
     # equals the plain answer bit for bit and every answer decrypts to its element's payload
     ctx8 = _context(cfg, batch=8)
@@ -85,7 +114,8 @@ def test_mid_full_size():
                                       draw=4 + b) for b, o in enumerate(others)]
     _say(f"mid: batch of 8 under schedule {ctx8.schedule()}")
     outs = ctx8.answer_batch([key8] * 8, [db8] * 8, [_dev(q) for q in qs])
-    assert np.array_equal(_host(outs[0]), ans)
+    got0 = _host(outs[0])
+    assert np.array_equal(got0, want), _diff(got0, want)
     for o, out in zip(others, outs[1:]):
         msg, _ = ins.orc.decrypt(ins.sk, _host(out)[0])
         assert np.array_equal(msg, ins.payload[o][0].astype(np.uint64)), o
