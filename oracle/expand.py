@@ -77,22 +77,37 @@ def pack_query(orc: Oracle, sk: np.ndarray, bits, c: int, seed: int, draw: int =
     return out
 
 
+def split_level(orc: Oracle, key, ct: np.ndarray, a: int) -> tuple:
+    """What level a of Algorithm 5 does to one ciphertext, derived from its effect on the plaintext.
+
+    Before level a the plaintext has terms only at exponents that are multiples of 2^a, say
+    u_j x^{j 2^a}.  The substitution with g = N / 2^a + 1 sends x^{j 2^a} to x^{j 2^a g} =
+    x^{j N} x^{j 2^a} = (-1)^j x^{j 2^a}: even j are fixed, odd j negated.  So ct + Sub_g(ct) keeps
+    the even-j terms (doubled) and ct - Sub_g(ct) the odd-j terms (doubled), which the monomial
+    x^{-2^a} moves down to multiples of 2^{a+1}.  Returns (ct + Sub_g(ct), x^{-2^a} (ct - Sub_g(ct)))."""
+    N = orc.N
+    g = N // (1 << a) + 1
+    s = orc.sub(key, ct, g)
+    even = orc.add(ct, s)
+    odd = orc.mul_monomial(_sub(orc, ct, s), 2 * N - (1 << a))   # x^{-2^a} = x^{2N - 2^a}
+    return even, odd
+
+
 def expand(orc: Oracle, gkeys: dict, packed: np.ndarray, m: int, c: int) -> np.ndarray:
-    """Algorithm 5: [h][2][L][N] -> the first m of the h 2^c expanded ciphertexts, [m][2][L][N]."""
+    """Algorithm 5: [h][2][L][N] -> the first m of the h 2^c expanded ciphertexts, [m][2][L][N].
+
+    Each packed ciphertext goes through c levels of split_level; at level a the 2^a ciphertexts
+    b < 2^a become 2^{a+1}, the even part staying at b and the odd part going to b + 2^a, so that
+    after the last level ciphertext b carries plaintext coefficient b (times 2^c, which the client's
+    2^-c pre-scale cancels)."""
     N = orc.N
     keys = {g: orc.load_key(gk) if isinstance(gk, np.ndarray) else gk for g, gk in gkeys.items()}
     out = []
     for ct in packed:
-        cts = [np.array(ct, dtype=np.uint64)] + [None] * ((1 << c) - 1)
+        cts = [np.array(ct, dtype=np.uint64)]
         for a in range(c):
-            g = N // (1 << a) + 1
-            shift = 2 * N - (1 << a)                     # x^{-2^a}
-            for b in range(1 << a):
-                c0 = orc.sub(keys[g], cts[b], g)         # Sub_{N/2^a+1}(cts[b])
-                c1 = orc.mul_monomial(c0, shift)
-                cts[b + (1 << a)] = orc.mul_monomial(cts[b], shift)
-                cts[b] = orc.add(cts[b], c0)
-                cts[b + (1 << a)] = _sub(orc, cts[b + (1 << a)], c1)
+            halves = [split_level(orc, keys[N // (1 << a) + 1], x, a) for x in cts]
+            cts = [e for e, _ in halves] + [o for _, o in halves]
         out.extend(cts)
     return np.stack(out[:m])
 

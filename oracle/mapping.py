@@ -26,21 +26,30 @@ def code_length(n: int, k: int) -> int:
 
 
 def perfect_map(x: int, m: int, k: int) -> list:
-    """Perfect mapping (Algorithm 3): x in [C(m,k)] -> one positions of the x-th codeword in
-    sorted (colexicographic) order.  Scans m' = m-1 down to 0 and takes position m' whenever the
-    remaining rank is at least C(m', h), h being the number of ones still to place."""
+    """Perfect mapping (Algorithm 3): identifier x in [C(m,k)] -> the one positions of the x-th
+    codeword of CW(m, k) in colexicographic order.
+
+    Written as the inverse of the colex rank that Algorithm 7 computes, x = sum_h C(p_h, h) over
+    the ascending positions p_1 < ... < p_k (the combinatorial number system): the top position
+    p_k is the largest p with C(p, k) <= x, since the codewords whose top one is below p number
+    C(p, k); the rest x - C(p_k, k) is the rank of the remaining k - 1 positions below p_k, so the
+    same rule gives p_{k-1}, and so on down to p_1."""
     if not 0 <= x < binom(m, k):
         raise ValueError("identifier outside the code")
-    r, h = x, k
     ones = []
-    for mp in range(m - 1, -1, -1):
-        c = binom(mp, h)
-        if r >= c:
-            ones.append(mp)
-            r -= c
-            h -= 1
-        if h == 0:
-            break
+    r, hi = x, m - 1                       # p_h lies in [h - 1, hi]
+    for h in range(k, 0, -1):
+        lo = h - 1                          # C(h - 1, h) = 0 <= r, so lo always qualifies
+        while lo < hi:                      # largest p in [lo, hi] with C(p, h) <= r
+            mid = (lo + hi + 1) // 2
+            if binom(mid, h) <= r:
+                lo = mid
+            else:
+                hi = mid - 1
+        ones.append(lo)
+        r -= binom(lo, h)
+        hi = lo - 1
+    assert r == 0
     return sorted(ones)
 
 
