@@ -207,6 +207,19 @@ int pir_arith_equality(pir_ctx* ctx, const pir_key* key, const uint64_t* x, cons
  * Asynchronous. */
 int pir_mod_switch(pir_ctx* ctx, const uint64_t* in, uint32_t count, uint32_t keep, uint64_t* out, void* stream);
 
+/* Response compression for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same switch as
+ * pir_mod_switch, bit for bit, with arguments, layouts and overlap rule as there.  It allocates
+ * nothing and does not synchronise: its only scratch (the counter and list of coefficients whose
+ * rounding takes the exact fallback) lives in a fixed array of 4 MiB + 256 bytes per GPU, which the
+ * library holds from the first pir_setup on that GPU until the process ends.  Limit: count * N <=
+ * 2^19 coefficients per call (e.g. 32 polynomials at N = 16384, 128 at N = 4096); larger requests
+ * return PIR_E_INVALID and enqueue nothing, so split them into several calls.  Every call on one GPU
+ * shares that GPU's array (across contexts too): calls whose work overlaps on the device race, so
+ * order them on one stream or with events.  Asynchronous. */
+int pir_mod_switch_noalloc(pir_ctx* ctx, const uint64_t* in, uint32_t count, uint32_t keep, uint64_t* out,
+                           void* stream);
+
 /* Seeded query ciphertexts (the compressed upload of secret-key encryption that the paper lists
  * among SealPIR's optimisations, Section 2; the upload column of the communication-cost table).
  * A secret-key ciphertext ([-a s + e + Delta m]_q, a) has a uniform a that the client need not

@@ -24,7 +24,7 @@ EXPORTS = [
     "pir_serve_close", "pir_get_schedule", "pir_set_schedule", "pir_autotune", "pir_graph_capture",
     "pir_graph_launch", "pir_graph_free", "pir_load_galois_key", "pir_expand", "pir_mod_switch",
     "pir_folklore_leaves", "pir_arith_equality", "pir_serve_set_policy", "pir_seeded_query",
-    "pir_serve_set_aging", "pir_probe_fp64",
+    "pir_serve_set_aging", "pir_probe_fp64", "pir_mod_switch_noalloc",
 ]
 
 
@@ -104,6 +104,7 @@ def lib():
             "pir_load_galois_key": (i32, [vp, u32, vp, pp]),
             "pir_expand": (i32, [vp, pp, u32, vp, u32, u32, vp, vp]),
             "pir_mod_switch": (i32, [vp, vp, u32, u32, vp, vp]),
+            "pir_mod_switch_noalloc": (i32, [vp, vp, u32, u32, vp, vp]),
             "pir_folklore_leaves": (i32, [vp, vp, u32, vp, vp]),
             "pir_arith_equality": (i32, [vp, vp, vp, vp, u32, u32, vp, vp]),
             "pir_serve_set_policy": (i32, [vp, i32]),
@@ -313,6 +314,18 @@ class Context:
         if out is None:
             out = self.empty(*lead, keep, self.N)
         _check(lib().pir_mod_switch(self._h, _ptr(x), count, keep, _ptr(out), _stream(stream, x, out)))
+        return out
+
+    def mod_switch_noalloc(self, x, keep: int, out=None, stream=None):
+        """mod_switch through the entry point that allocates no device memory (at most 2^19
+        coefficients per call); `out` may be preallocated so that nothing is allocated at all."""
+        x = _dev_u64(x, self.device)
+        lead = tuple(x.shape[:-2])
+        assert tuple(x.shape[-2:]) == (self.L, self.N)
+        count = int(np.prod(lead)) if lead else 1
+        if out is None:
+            out = self.empty(*lead, keep, self.N)
+        _check(lib().pir_mod_switch_noalloc(self._h, _ptr(x), count, keep, _ptr(out), _stream(stream, x, out)))
         return out
 
     def seeded_query(self, c0, seed: int, out=None, stream=None):

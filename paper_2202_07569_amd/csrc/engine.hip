@@ -84,6 +84,8 @@ struct pir_ctx {
     std::map<std::string, ProfAcc> prof_acc;
     std::map<std::pair<uint32_t, uint32_t>, uint64_t*> binom;  // (m, k) -> device table
     std::map<uint32_t, cw::SwitchConst*> switches;            // keep -> device switch constants
+    void* scratch = nullptr;  // this device's copy of the no-allocation scratch array (device address)
+    std::string scratch_err;  // why it is missing, if it is
 };
 
 struct pir_key {
@@ -252,6 +254,63 @@ static int end_async(pir_ctx* ctx, hipStream_t st) {
 }
 
 // ------------------------------------------------------------------------------------------------
+// no-allocation scratch
+//
+// pir_mod_switch_noalloc keeps its fixup counter and fixup list in this file-scope array instead of
+// the context's buffers: bytes [0, 256) hold the counter, the rest the list (one 64-bit coefficient
+// index per entry, NOALLOC_MAX_COEFFS entries).  Every GPU the library runs on holds its own copy
+// until the process ends.  In host code the array's name is a host-side stand-in; kernels get the
+// device address, looked up once per device (pir_setup, with the device current) and kept below.
+// ------------------------------------------------------------------------------------------------
+constexpr size_t NOALLOC_MAX_COEFFS = size_t(1) << 19;
+constexpr size_t NOALLOC_SCRATCH_BYTES = 256 + NOALLOC_MAX_COEFFS * 8;
+// External linkage on purpose: the HIP runtime resolves a registered device variable through the
+// code object's dynamic symbol table, which holds global symbols only (a `static` array stays a
+// local symbol there, and looking it up is fatal).
+__device__ __align__(256) uint64_t cwpir_noalloc_scratch[NOALLOC_SCRATCH_BYTES / 8];
+constexpr int NOALLOC_MAX_DEVICES = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[NOALLOC_MAX_DEVICES];        // device address of the array, per device ordinal
+static std::string g_scratch_err[NOALLOC_MAX_DEVICES];  // why the lookup failed, if it did
+
+// Called with `device` current.  A failed lookup leaves *out null: only pir_mod_switch_noalloc
+// depends on it, and it then reports the lookup's error.
+static void scratch_address(int device, void** out, std::string* why) {
+    *out = nullptr;
+    if (device < 0 || device >= NOALLOC_MAX_DEVICES) {
+        *why = "device ordinal beyond the scratch table";
+        return;
+    }
+    std::lock_guard<std::mutex> g(g_scratch_mu);
+    if (!g_scratch_ptr[device] && g_scratch_err[device].empty()) {
+        void* p = nullptr;
+        hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(cwpir_noalloc_scratch));
+        if (e == hipSuccess && p) {
+            g_scratch_ptr[device] = p;
+        } else {
+            (void)hipGetLastError();
+            g_scratch_err[device] =
+                std::string("hipGetSymbolAddress(cwpir_noalloc_scratch) failed: ") + hipGetErrorString(e);
+        }
+    }
+    *out = g_scratch_ptr[device];
+    *why = g_scratch_err[device];
+}
+
+// Device constants of the modulus switch to q_0 ... q_{keep-1} (built once per keep).
+static int switch_const(pir_ctx* ctx, uint32_t keep, cw::SwitchConst** out) {
+    cw::SwitchConst*& dS = ctx->switches[keep];
+    if (!dS) {
+        cw::SwitchConst S;
+        cw::host::build_switch(S, std::vector<uint64_t>(ctx->primes.begin(), ctx->primes.begin() + ctx->L), keep);
+        CW_TRY(dev_alloc(ctx, (void**)&dS, sizeof(S)));
+        CW_HIP(ctx, hipMemcpy(dS, &S, sizeof(S), hipMemcpyHostToDevice));
+    }
+    *out = dS;
+    return PIR_OK;
+}
+
+// ------------------------------------------------------------------------------------------------
 // setup
 // ------------------------------------------------------------------------------------------------
 extern "C" int pir_setup(const pir_params* params, pir_ctx** out) {
@@ -323,6 +382,12 @@ extern "C" int pir_setup(const pir_params* params, pir_ctx** out) {
         hipMemset(ctx->dfixcnt, 0, 256) != hipSuccess || hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess)
         return cleanup(fail(PIR_E_DEVICE, "device initialisation failed"));
+    // switch constants for every keep, so that response compression never allocates later
+    for (uint32_t keep = 1; keep <= ctx->L; ++keep) {
+        cw::SwitchConst* dS = nullptr;
+        if ((rc = switch_const(ctx, keep, &dS)) != PIR_OK) return cleanup(rc);
+    }
+    scratch_address(ctx->device, &ctx->scratch, &ctx->scratch_err);
     *out = ctx;
     return PIR_OK;
 }
@@ -1795,21 +1860,22 @@ extern "C" int pir_expand(pir_ctx* ctx, const pir_key* const* gkeys, uint32_t c,
 // ------------------------------------------------------------------------------------------------
 // response compression (modulus switching)
 // ------------------------------------------------------------------------------------------------
+static bool switch_overlap(const pir_ctx* ctx, const uint64_t* in, uint32_t count, uint32_t keep, const uint64_t* out) {
+    const uintptr_t a0 = (uintptr_t)in, a1 = a0 + (size_t)count * ctx->L * ctx->N * 8;
+    const uintptr_t b0 = (uintptr_t)out, b1 = b0 + (size_t)count * keep * ctx->N * 8;
+    return count && a0 < b1 && b0 < a1;
+}
+
 extern "C" int pir_mod_switch(pir_ctx* ctx, const uint64_t* in, uint32_t count, uint32_t keep, uint64_t* out,
                               void* stream) {
     CW_ENTER(ctx);
     if (count && (!in || !out)) return fail(PIR_E_INVALID, "null argument");
     if (keep < 1 || keep > ctx->L) return fail(PIR_E_INVALID, "keep must be in [1, L]");
-    if (in == out) return fail(PIR_E_INVALID, "in and out must not overlap");
+    if (switch_overlap(ctx, in, count, keep, out)) return fail(PIR_E_INVALID, "in and out must not overlap");
     hipStream_t st = (hipStream_t)stream;
     CW_TRY(begin_async(ctx, st));
-    cw::SwitchConst*& dS = ctx->switches[keep];
-    if (!dS) {
-        cw::SwitchConst S;
-        cw::host::build_switch(S, std::vector<uint64_t>(ctx->primes.begin(), ctx->primes.begin() + ctx->L), keep);
-        CW_TRY(dev_alloc(ctx, (void**)&dS, sizeof(S)));
-        CW_HIP(ctx, hipMemcpy(dS, &S, sizeof(S), hipMemcpyHostToDevice));
-    }
+    cw::SwitchConst* dS = nullptr;
+    CW_TRY(switch_const(ctx, keep, &dS));
     Launch lc = make_launch(ctx, st);
     const size_t N = ctx->N, per = std::max<size_t>(1, ctx->fix_cap / N);  // polynomials per launch
     Prof pr(ctx, "mod_switch", st, (double)count * N);
@@ -1817,6 +1883,30 @@ extern "C" int pir_mod_switch(pir_ctx* ctx, const uint64_t* in, uint32_t count, 
         const size_t n = std::min<size_t>(per, count - p0);
         cw::launch_mod_switch(lc, dS, keep, in + p0 * ctx->L * N, n, out + p0 * keep * N);
     }
+    return end_async(ctx, st);
+}
+
+// The same switch with the fixup counter and list in the per-device scratch array: no allocation,
+// no host synchronisation, one fill kernel (the counter starts at zero) and the two switch kernels.
+extern "C" int pir_mod_switch_noalloc(pir_ctx* ctx, const uint64_t* in, uint32_t count, uint32_t keep, uint64_t* out,
+                                      void* stream) {
+    CW_ENTER(ctx);
+    if (count && (!in || !out)) return fail(PIR_E_INVALID, "null argument");
+    if (keep < 1 || keep > ctx->L) return fail(PIR_E_INVALID, "keep must be in [1, L]");
+    if ((uint64_t)count * ctx->N > NOALLOC_MAX_COEFFS)
+        return fail(PIR_E_INVALID, "count * N exceeds the no-allocation limit of 2^19 coefficients per call");
+    if (switch_overlap(ctx, in, count, keep, out)) return fail(PIR_E_INVALID, "in and out must not overlap");
+    if (!count) return PIR_OK;
+    if (!ctx->scratch) return fail(PIR_E_DEVICE, "no scratch array on this device: " + ctx->scratch_err);
+    auto it = ctx->switches.find(keep);
+    if (it == ctx->switches.end() || !it->second) return fail(PIR_E_DEVICE, "switch constants missing");
+    hipStream_t st = (hipStream_t)stream;
+    CW_TRY(begin_async(ctx, st));
+    Launch lc = make_launch(ctx, st);
+    lc.fixcnt = (uint32_t*)ctx->scratch;
+    lc.fix = (uint64_t*)((char*)ctx->scratch + 256);
+    cw::launch_fill(st, (uint64_t*)ctx->scratch, 1, 0);  // the last call on this device may have left anything
+    cw::launch_mod_switch(lc, it->second, keep, in, count, out);
     return end_async(ctx, st);
 }
 
