@@ -103,9 +103,15 @@ int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, uint32_t k, 
 /* Process (Section 3.3.3: selection vector, Algorithm 6, then s inner products with the
  * database, Eq. (1)): answer = [s][2][L][N] for the query [m][2][L][N].  query and answer are dev
  * pointers; asynchronous on `stream` (a hipStream_t).  The query residues are not range-checked
- * (the library never reads them on the host). */
+ * here (that would need a wait on the device): a residue >= q_i gives an undefined answer.
+ * Callers that cannot vouch for their queries check them first with pir_check_query. */
 int pir_answer(pir_ctx* ctx, const pir_key* key, const pir_db* db, const uint64_t* query, uint64_t* answer,
                void* stream);
+
+/* Range check of `count` ciphertexts (dev [count][2][L][N], e.g. a query with count = m): PIR_OK when
+ * every residue of limb j is below q_j, PIR_E_INVALID (the context stays usable) otherwise.  One
+ * read of the ciphertexts on `stream`; waits for the result (synchronous). */
+int pir_check_query(pir_ctx* ctx, const uint64_t* query, uint32_t count, void* stream);
 
 /* Process B queries in one call: the query ciphertexts' selection trees run side by side and
  * queries on the same database share one scan of its payload.  keys[b], dbs[b], queries[b],
@@ -126,12 +132,18 @@ int pir_answer_batch(pir_ctx* ctx, uint32_t B, const pir_key* const* keys, const
  *   pir_serve_submit  queue one query; *ticket receives its id.  key/db from this context; query
  *                     (dev [m][2][L][N]) must be ready on the device when submitted and stay
  *                     unmodified, and answer (dev [s][2][L][N]) stays unread, until the ticket
- *                     completes.  Host-side only: enqueues no device work.
+ *                     completes.  The query's residues are range-checked first (pir_check_query,
+ *                     on a stream of the server's own, waited for; it does not wait for the
+ *                     queued rounds): PIR_E_INVALID for a residue >= q_i, and nothing is queued.
  *   pir_serve_step    admit (in submission order, while each query's buffers fit the context's
  *                     HBM budget) and run one round; returns the number of queries queued or active
- *                     (>= 0), or an error.  PIR_E_NOMEM when no query is active and the oldest
- *                     waiting one does not fit (it stays queued).  Keeps at most two rounds queued
- *                     on the device.  Ordered after the context's other asynchronous calls.
+ *                     (>= 0), or an error.  A query that does not fit waits for running queries to
+ *                     finish; before that, the buffers idle slots keep for reuse and the context's
+ *                     cached work buffers of other calls are released and the allocation retried.
+ *                     PIR_E_NOMEM when no query is active and the oldest waiting one still does not
+ *                     fit (it stays queued; the server and context stay usable).  Keeps at most two
+ *                     rounds queued on the device.  Ordered after the context's other asynchronous
+ *                     calls.
  *   pir_serve_poll    1 when the ticket's answer is complete in device memory (the ticket is then
  *                     released), 0 while it is queued or running, PIR_E_INVALID for an unknown or
  *                     released ticket.
@@ -292,6 +304,17 @@ int pir_map_lossy(pir_ctx* ctx, const uint64_t* keywords, uint64_t n, uint32_t m
  *                     NULL).  Candidates that do not fit the HBM budget are skipped.  Returns the
  *                     number of candidates measured, or an error.  Synchronous; the library's work
  *                     buffers are released afterwards. */
+/* Where the relinearization of each element's root product happens (Section 3.3.3: the answer is
+ * the inner product of the selection vector with the database, Eq. (1), and it is linear in every
+ * selector).  on = 1 (the default): on the fp64 path (every prime below 2^50, N <= 8192), for trees
+ * with a multiplication and databases whose digit sums fit the CRT of two auxiliary primes, the
+ * root products are multiplied into the payload before relinearization, with their relinearization
+ * digits summed separately, and the key multiplies those sums once per answer; elsewhere, and with
+ * on = 0, every selector is relinearized.  The answers are bit-identical either way.  Changes only
+ * while no database is encoded (PIR_E_INVALID otherwise).  pir_get_defer_relin returns the mode. */
+int pir_set_defer_relin(pir_ctx* ctx, int on);
+int pir_get_defer_relin(pir_ctx* ctx);
+
 typedef struct {
     uint32_t chunk_elems;
     uint32_t query_group;
@@ -327,6 +350,13 @@ int pir_profile_read(pir_ctx* ctx, uint32_t max, const char** names, double* tot
  * reference for what the kernels' SQ_INSTS_VALU / SQ_BUSY_CU_CYCLES counters can reach. */
 int pir_probe_fp64(pir_ctx* ctx, int op, uint32_t blocks, uint32_t iters, double* ms, double* wave_instr,
                    void* stream);
+
+/* Diagnostics: the same for the 32-bit integer instructions the integer-path transforms (N = 16384,
+ * or primes at or above 2^50) are built from: op 0 v_mul_lo_u32, 1 v_mul_hi_u32, 2 v_mad_u64_u32,
+ * 3 v_lshl_add_u64 (gfx950's one-instruction 64-bit add).  Arguments, timing and *wave_instr as for
+ * pir_probe_fp64 (one wave-instruction per chain and step).  Synchronous. */
+int pir_probe_int(pir_ctx* ctx, int op, uint32_t blocks, uint32_t iters, double* ms, double* wave_instr,
+                  void* stream);
 
 void pir_db_free(pir_db* db);
 void pir_key_free(pir_key* key);

@@ -24,7 +24,8 @@ EXPORTS = [
     "pir_serve_close", "pir_get_schedule", "pir_set_schedule", "pir_autotune", "pir_graph_capture",
     "pir_graph_launch", "pir_graph_free", "pir_load_galois_key", "pir_expand", "pir_mod_switch",
     "pir_folklore_leaves", "pir_arith_equality", "pir_serve_set_policy", "pir_seeded_query",
-    "pir_serve_set_aging", "pir_probe_fp64", "pir_mod_switch_noalloc",
+    "pir_serve_set_aging", "pir_probe_fp64", "pir_mod_switch_noalloc", "pir_check_query", "pir_probe_int",
+    "pir_set_defer_relin", "pir_get_defer_relin",
 ]
 
 
@@ -105,6 +106,9 @@ def lib():
             "pir_expand": (i32, [vp, pp, u32, vp, u32, u32, vp, vp]),
             "pir_mod_switch": (i32, [vp, vp, u32, u32, vp, vp]),
             "pir_mod_switch_noalloc": (i32, [vp, vp, u32, u32, vp, vp]),
+            "pir_check_query": (i32, [vp, vp, u32, vp]),
+            "pir_set_defer_relin": (i32, [vp, i32]),
+            "pir_get_defer_relin": (i32, [vp]),
             "pir_folklore_leaves": (i32, [vp, vp, u32, vp, vp]),
             "pir_arith_equality": (i32, [vp, vp, vp, vp, u32, u32, vp, vp]),
             "pir_serve_set_policy": (i32, [vp, i32]),
@@ -112,6 +116,8 @@ def lib():
             "pir_serve_set_aging": (i32, [vp, ctypes.c_double]),
             "pir_probe_fp64": (i32, [vp, i32, u32, u32, ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double), vp]),
+            "pir_probe_int": (i32, [vp, i32, u32, u32, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double), vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -245,6 +251,18 @@ class Context:
         _check(lib().pir_get_schedule(self._h, ctypes.byref(out)))
         return out.as_dict()
 
+    @property
+    def defer_relin(self) -> bool:
+        """Whether root products are relinearized after the inner product (pir_set_defer_relin)."""
+        rc = lib().pir_get_defer_relin(self._h)
+        if rc < 0:
+            _check(rc)
+        return rc == 1
+
+    @defer_relin.setter
+    def defer_relin(self, on: bool):
+        _check(lib().pir_set_defer_relin(self._h, 1 if on else 0))
+
     def set_schedule(self, chunk_elems: int, query_group: int, relin_group: int = 0):
         x = _Schedule(chunk_elems, query_group, relin_group, 0.0)
         _check(lib().pir_set_schedule(self._h, ctypes.byref(x)))
@@ -370,6 +388,13 @@ class Context:
         _check(lib().pir_answer(self._h, key._h, db._h, _ptr(query), _ptr(out), _stream(stream, query, out)))
         return out
 
+    def check_query(self, query, stream=None):
+        """Range check of ciphertexts [count, 2, L, N] (pir_check_query): raises PirError
+        (PIR_E_INVALID) if a residue is not below its prime."""
+        query = _dev_u64(query, self.device)
+        assert query.dim() == 4 and tuple(query.shape[1:]) == (2, self.L, self.N)
+        _check(lib().pir_check_query(self._h, _ptr(query), int(query.shape[0]), _stream(stream, query)))
+
     def answer_batch(self, keys, dbs, queries, outs=None, stream=None):
         B = len(queries)
         queries = [_dev_u64(q, self.device) for q in queries]
@@ -451,6 +476,15 @@ class Context:
         ms, wi = ctypes.c_double(), ctypes.c_double()
         _check(lib().pir_probe_fp64(self._h, op, blocks, iters, ctypes.byref(ms), ctypes.byref(wi),
                                     _stream(stream)))
+        return ms.value, wi.value
+
+    PROBE_INT_OPS = ("v_mul_lo_u32", "v_mul_hi_u32", "v_mad_u64_u32", "v_lshl_add_u64")
+
+    def probe_int(self, op: int, blocks: int = 4096, iters: int = 4096, stream=None):
+        """Integer issue-rate probe (pir_probe_int): (milliseconds, wave-instructions) of one timed
+        launch."""
+        ms, wi = ctypes.c_double(), ctypes.c_double()
+        _check(lib().pir_probe_int(self._h, op, blocks, iters, ctypes.byref(ms), ctypes.byref(wi), _stream(stream)))
         return ms.value, wi.value
 
     def profile(self, on: bool = True):

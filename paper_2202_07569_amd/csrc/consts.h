@@ -11,7 +11,8 @@ namespace cw {
 
 constexpr int MAX_L = 12;            // ciphertext primes
 constexpr int MAX_LB = 13;           // auxiliary primes
-constexpr int MAX_LL = MAX_L + MAX_LB;
+constexpr int MAX_LD = 2;            // primes of the deferred key switch's digit sums (after Q and B)
+constexpr int MAX_LL = MAX_L + MAX_LB + MAX_LD;  // per-prime tables: Q, then B, then D
 constexpr int MAX_CONV = MAX_LB;     // >= max(MAX_L, MAX_LB)
 constexpr int MAX_W = 14;            // 64-bit words of a basis product, plus two spare words
 
@@ -39,7 +40,8 @@ constexpr uint64_t FP_PRIME_BOUND = 1ull << 50;
 constexpr uint64_t FP_LAZY_BOUND = 1ull << 48;  // lazy fp64 forward transforms (no reduction between passes)
 
 struct CtxConst {
-    uint32_t N, logN, L, LB, LL, fp;             // fp: transforms run on the fp64 pipe
+    uint32_t N, logN, L, LB, LL, fp;             // fp: transforms run on the fp64 pipe; LL = L + LB (the D
+                                                 // primes, when present, follow at LL and LL + 1)
     uint64_t t;
     uint64_t p[MAX_LL];
     uint64_t bar_mu[MAX_LL];                     // floor(2^(2s) / p), s = bit length of p
@@ -69,6 +71,16 @@ struct SwitchConst {
     ConvTable T;                                 // {q_keep..q_{L-1}} -> {q_0..q_{keep-1}}
     uint64_t yc[MAX_L], ycq[MAX_L];              // [(r / q_i)^{-1}]_{q_i} for dropped i (index i - keep)
     uint64_t rinv[MAX_L], rinvq[MAX_L];          // [r^{-1}]_{q_j} for kept j
+};
+
+// Exact CRT of the deferred key switch's digit sums from its two primes d0, d1 (context primes LL and
+// LL + 1, after Q and B), written b0, b1 below: w = w0 + b0 t, t = (w1 - w0) b0^-1 mod b1, centred
+// (w > half stands for w - b0 b1), then reduced mod every q_j.
+struct CrtConst {  // passed by value
+    uint64_t b0inv, b0invq;            // b0^-1 mod b1 and its Shoup companion
+    uint64_t half_hi, half_lo;         // (b0 b1 - 1) / 2 as a 128-bit number
+    uint64_t b0q[MAX_L], b0qq[MAX_L];  // b0 mod q_j, Shoup companion
+    uint64_t Bq[MAX_L];                // b0 b1 mod q_j
 };
 
 // Operand reference of a tree node: a query ciphertext (leaf) or a memoised inner node.

@@ -65,6 +65,7 @@ struct pir_ctx {
     std::recursive_mutex mu;
     uint64_t* dfix = nullptr;
     uint32_t* dfixcnt = nullptr;
+    uint32_t* dflag = nullptr;  // result word of the residue range check (256-byte allocation)
     size_t fix_cap = 0;
     uint32_t chunk = 0;  // elements per chunk
     uint32_t qb = cw::MAX_QB;     // queries per selector launch
@@ -84,6 +85,10 @@ struct pir_ctx {
     std::map<std::string, ProfAcc> prof_acc;
     std::map<std::pair<uint32_t, uint32_t>, uint64_t*> binom;  // (m, k) -> device table
     std::map<uint32_t, cw::SwitchConst*> switches;            // keep -> device switch constants
+    uint32_t xslab = 0;       // element-queries per tensor + scale launch (X stays in the Infinity Cache)
+    bool defer = true;        // key switch of root products deferred past the inner product (where allowed)
+    bool crt_ok = false;      // the two primes of the deferred key switch exist (fp64 path)
+    cw::CrtConst crt{};
     void* scratch = nullptr;  // this device's copy of the no-allocation scratch array (device address)
     std::string scratch_err;  // why it is missing, if it is
 };
@@ -114,11 +119,25 @@ struct pir_db {
     uint64_t total_pairs = 0;
     size_t pay_bytes = 0, pairs_bytes = 0, refs_bytes = 0;
     bool live = false;           // counted in ctx->live_dbs
+    bool defer_ok = false;       // the digit sums of this database fit the CRT of two auxiliary primes
 };
 
 // ------------------------------------------------------------------------------------------------
 // helpers
 // ------------------------------------------------------------------------------------------------
+// Deferred key switch of the root products (kernels.hip, "Root products with the key switch
+// deferred past the inner product"): used on the fp64 path when the database's digit sums fit the
+// CRT of two auxiliary primes, for trees with at least one multiplication.
+constexpr uint32_t ROOT_A = 2;  // auxiliary primes holding the digit sums
+static bool deferred(const pir_ctx* ctx, const pir_db* db) { return ctx->defer && db->defer_ok; }
+static uint32_t root_rows(const pir_ctx* ctx) { return 2 * ctx->L + ROOT_A * ctx->L; }  // RR
+
+static uint32_t root_units(const pir_ctx* ctx, uint32_t s) {
+    const uint32_t L = ctx->L;
+    return s == 1 ? L + ROOT_A * ((L + 1) / 2) : root_rows(ctx) * ((s + 1) / 2);
+}
+
+
 #define CW_HIP(ctx, expr)                                                                                \
     do {                                                                                                 \
         hipError_t e_ = (expr);                                                                          \
@@ -181,6 +200,20 @@ static int ws_get_t(pir_ctx* ctx, const std::string& name, size_t count, T** out
     CW_TRY(ws_get(ctx, name, count * sizeof(T), &p));
     *out = (T*)p;
     return PIR_OK;
+}
+
+// Release cached work buffers other than the per-chunk ones every answer path uses (X, C, R, Ph, P);
+// the caller has made sure that no queued work still reads them.
+static void trim_work_buffers(pir_ctx* ctx) {
+    for (auto it = ctx->ws.begin(); it != ctx->ws.end();) {
+        const std::string& n = it->first;
+        if (n == "X" || n == "C" || n == "R" || n == "Ph" || n == "P") {
+            ++it;
+            continue;
+        }
+        dev_free(ctx, it->second.p, it->second.bytes);
+        it = ctx->ws.erase(it);
+    }
 }
 
 static Launch make_launch(pir_ctx* ctx, hipStream_t st) {
@@ -347,7 +380,15 @@ extern "C" int pir_setup(const pir_params* params, pir_ctx** out) {
     ctx->primes = q;
     ctx->primes.insert(ctx->primes.end(), B.begin(), B.end());
     ctx->fp = fp;
-    cw::host::build_const(ctx->K, ctx->N, q, B, ctx->t);
+    // fp64 path: two more primes below 2^48 for the deferred key switch's digit sums (their lazy
+    // transforms need no reduction between passes); they follow Q and B in every per-prime table
+    std::vector<uint64_t> D;
+    if (fp) {
+        D = cw::host::primes_below(ctx->N, cw::FP_LAZY_BOUND, 2, ctx->primes);
+        if (D.size() == 2) ctx->primes.insert(ctx->primes.end(), D.begin(), D.end());
+        else D.clear();
+    }
+    cw::host::build_const(ctx->K, ctx->N, q, B, ctx->t, D);
     ctx->K.fp = fp ? 1 : 0;
     if (params->chunk_elems > 4096) return cleanup_early(fail(PIR_E_INVALID, "chunk_elems must be <= 4096"), ctx);
     ctx->chunk = params->chunk_elems ? params->chunk_elems : (ctx->N >= 16384 ? 128 : 256);
@@ -377,11 +418,25 @@ extern "C" int pir_setup(const pir_params* params, pir_ctx** out) {
     ctx->fix_cap = (size_t)3 * ctx->chunk * ctx->N * cw::MAX_QB;  // coefficients of one batched launch
     if ((rc = dev_alloc(ctx, (void**)&ctx->dfix, ctx->fix_cap * 8)) != PIR_OK) return cleanup(rc);
     if ((rc = dev_alloc(ctx, (void**)&ctx->dfixcnt, 256)) != PIR_OK) return cleanup(rc);
+    if ((rc = dev_alloc(ctx, (void**)&ctx->dflag, 256)) != PIR_OK) return cleanup(rc);
     if (hipMemcpy(ctx->dK, &ctx->K, sizeof(CtxConst), hipMemcpyHostToDevice) != hipSuccess ||
         hipMemcpy(ctx->dtw, tw.data(), tw.size() * 8, hipMemcpyHostToDevice) != hipSuccess ||
         hipMemset(ctx->dfixcnt, 0, 256) != hipSuccess || hipEventCreateWithFlags(&ctx->done, hipEventDisableTiming) != hipSuccess ||
         hipDeviceSynchronize() != hipSuccess)
         return cleanup(fail(PIR_E_DEVICE, "device initialisation failed"));
+    // tensor slabs of at most 1 GiB of X (slabs of 64 element-queries, 126 MB at N = 8192, which
+    // stay in the Infinity Cache, measured 9 % slower for the tensor kernel and no faster for the
+    // scale kernel), and at least four workgroups per compute unit per launch
+    {
+        const uint64_t per_eq = (uint64_t)3 * ctx->LL * ctx->N * 8;
+        const uint64_t by_cache = std::max<uint64_t>(1, (1024ull << 20) / per_eq);
+        const uint64_t by_grid = (4ull * ctx->cus + 3 * ctx->LL - 1) / (3 * ctx->LL);
+        ctx->xslab = (uint32_t)std::max(by_cache, by_grid);
+    }
+    if (D.size() == 2) {
+        cw::host::build_crt(ctx->crt, q, D[0], D[1]);
+        ctx->crt_ok = true;
+    }
     // switch constants for every keep, so that response compression never allocates later
     for (uint32_t keep = 1; keep <= ctx->L; ++keep) {
         cw::SwitchConst* dS = nullptr;
@@ -404,10 +459,11 @@ extern "C" void pir_free(pir_ctx* ctx) {
     for (auto& kv : ctx->binom) (void)hipFree(kv.second);
     for (auto& kv : ctx->switches) dev_free(ctx, kv.second, sizeof(cw::SwitchConst));
     dev_free(ctx, ctx->dK, sizeof(CtxConst));
-    dev_free(ctx, ctx->dtw, (size_t)ctx->LL * 4 * ctx->N * 8);
-    if (ctx->dtwf) dev_free(ctx, ctx->dtwf, (size_t)ctx->LL * 4 * ctx->N * 8);
+    dev_free(ctx, ctx->dtw, ctx->primes.size() * 4 * ctx->N * 8);
+    if (ctx->dtwf) dev_free(ctx, ctx->dtwf, ctx->primes.size() * 4 * ctx->N * 8);
     dev_free(ctx, ctx->dfix, ctx->fix_cap * 8);
     dev_free(ctx, ctx->dfixcnt, 256);
+    dev_free(ctx, ctx->dflag, 256);
     if (ctx->done) (void)hipEventDestroy(ctx->done);
     delete ctx;
 }
@@ -647,6 +703,16 @@ extern "C" int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, u
     }
     for (auto& g : db->groups) db->max_pairs = std::max(db->max_pairs, g.np);
     db->total_pairs = pb.pairs.size() / 2;
+    // deferred key switch: every coefficient of a digit sum sum_e D_e P_e lies below
+    // n N max q_i (2^16 - 1) in magnitude, which the CRT of its two primes must hold with its sign
+    if (ctx->crt_ok && k >= 2) {
+        typedef unsigned __int128 u128;
+        uint64_t maxq = 0;
+        for (uint32_t i = 0; i < ctx->L; ++i) maxq = std::max(maxq, ctx->primes[i]);
+        const u128 bound = (u128)std::max<uint64_t>(n, 1) * ctx->N * maxq;  // n < 2^40, N <= 2^14, q < 2^50
+        const u128 prod = (u128)ctx->primes[ctx->LL] * ctx->primes[ctx->LL + 1];
+        db->defer_ok = bound < (prod >> 17) && root_units(ctx, s) <= (uint32_t)cw::ROOT_MAX_UNITS;  // 2 bound 2^16 < b0 b1
+    }
     const size_t pay_bytes = (size_t)n * s * ctx->N * 2;
     int rc = dev_alloc(ctx, (void**)&db->dpay, pay_bytes);
     if (rc == PIR_OK) db->pay_bytes = pay_bytes;
@@ -697,16 +763,35 @@ struct Bufs {
     uint64_t* X = nullptr;   // [QB E][3][LL][N]  tensor products over Q u B
     uint64_t* C = nullptr;   // [QB E][3][L][N]   after scale-and-round, coefficient form
     uint64_t* R = nullptr;   // [QB E][L+2][L][N] transformed digits (only where key switching is staged)
-    uint64_t* Ph = nullptr;  // [E][s][L][N]      transformed payload rows
+    uint64_t* Ph = nullptr;  // [E][s][L (+ ROOT_A)][N] transformed payload rows
+    uint64_t* P = nullptr;   // deferred key switch: per-slice partial sums [slices][QB][s][RR][N]
 };
 
+// Elements per workgroup of the deferred key switch: enough workgroups for four per compute unit,
+// and slices of at most 64 elements.
+static uint32_t root_slice(const pir_ctx* ctx, uint32_t E, uint32_t nq, uint32_t units) {
+    const uint64_t want = 4ull * std::max<uint32_t>(ctx->cus, 1);
+    const uint64_t per = (uint64_t)nq * units;
+    uint64_t slice = ((uint64_t)E * per) / want;
+    return (uint32_t)std::min<uint64_t>(64, std::max<uint64_t>(1, slice));
+}
+
 // Work buffers for launches over up to `nq` queries of E elements each.
-static int get_bufs(pir_ctx* ctx, uint32_t E, uint32_t nq, uint32_t s, Bufs& b) {
+static int get_bufs(pir_ctx* ctx, uint32_t E, uint32_t nq, uint32_t s, Bufs& b, bool defer = false) {
     const size_t N = ctx->N, L = ctx->L, LL = ctx->LL, EQ = (size_t)E * nq;
-    CW_TRY(ws_get_t(ctx, "X", EQ * 3 * LL * N, &b.X));
+    CW_TRY(ws_get_t(ctx, "X", std::min<size_t>(EQ, std::max<size_t>(1, ctx->xslab)) * 3 * LL * N, &b.X));
     CW_TRY(ws_get_t(ctx, "C", EQ * 3 * L * N, &b.C));
     if (cw::relin_needs_staging(ctx->logN)) CW_TRY(ws_get_t(ctx, "R", EQ * (L + 2) * L * N, &b.R));
-    if (s) CW_TRY(ws_get_t(ctx, "Ph", (size_t)E * s * L * N, &b.Ph));
+    if (s) CW_TRY(ws_get_t(ctx, "Ph", (size_t)E * s * (L + (ctx->crt_ok ? ROOT_A : 0)) * N, &b.Ph));
+    if (s && defer) {  // the most partial rows of any launch: up to nq queries, up to s payload rows
+        size_t most = 0;
+        for (uint32_t n = 1; n <= nq; ++n)
+            for (uint32_t sp = 1; sp <= s; ++sp) {
+                const uint32_t sl = root_slice(ctx, E, n, root_units(ctx, sp));
+                most = std::max<size_t>(most, (size_t)((E + sl - 1) / sl) * n * sp);
+            }
+        CW_TRY(ws_get_t(ctx, "P", most * root_rows(ctx) * N, &b.P));
+    }
     return PIR_OK;
 }
 
@@ -717,14 +802,22 @@ struct QState {
     uint64_t* answer = nullptr;       // caller's [s][2][L][N]; accumulates in the transformed domain
     uint64_t* QX = nullptr;           // resident query [m][2][LL][N]
     uint64_t* nodes = nullptr;        // memoised tree nodes [max_pairs][2][LL][N] (k >= 3)
-    uint64_t* sel = nullptr;          // selectors [E][2][L][N]
+    uint64_t* sel = nullptr;          // selectors [E][2][L][N] (deferred: scratch of the tree nodes only)
+    uint64_t* racc = nullptr;         // deferred key switch: accumulators [s][RR][N], transformed
 };
 
 static size_t qx_words(const pir_ctx* ctx, const pir_db* db) { return (size_t)db->m * 2 * ctx->LL * ctx->N; }
 static size_t node_words(const pir_ctx* ctx, const pir_db* db) {
     return db->k >= 3 ? (size_t)std::max<uint32_t>(db->max_pairs, 1) * 2 * ctx->LL * ctx->N : 0;
 }
-static size_t sel_words(const pir_ctx* ctx) { return (size_t)ctx->chunk * 2 * ctx->L * ctx->N; }
+// Selectors of a chunk; with the deferred key switch only the inner tree nodes (k >= 3) need them.
+static size_t sel_words(const pir_ctx* ctx, const pir_db* db) {
+    if (deferred(ctx, db) && db->k < 3) return 0;
+    return (size_t)ctx->chunk * 2 * ctx->L * ctx->N;
+}
+static size_t racc_words(const pir_ctx* ctx, const pir_db* db) {
+    return deferred(ctx, db) ? (size_t)db->s * root_rows(ctx) * ctx->N : 0;
+}
 static uint32_t num_chunks(const pir_ctx* ctx, const pir_db* db) {
     return (uint32_t)((db->n + ctx->chunk - 1) / ctx->chunk);
 }
@@ -747,18 +840,77 @@ static int make_leaves(pir_ctx* ctx, const Launch& lc, const uint64_t* query, ui
 
 // Mult + Relin of bt.E operand pairs (refs into leaves/nodes) for each query of the batch; the
 // results, transformed over Q, go to bt.sel[q].
+// Mult of bt.E operand pairs for each query of the batch: the tensor products, inverse-transformed,
+// scaled and rounded into b.C [nq E][3][L][N] (coefficient form).
+// The tensor products go through X in slabs of at most ctx->xslab rows (element-queries), each
+// scaled into C right after it is written: X is bounded by the slab, not by the launch.
+static void mult_only(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint32_t* refs, const cw::Batch& bt) {
+    const size_t rows = (size_t)bt.nq * bt.E, slab = std::max<size_t>(1, ctx->xslab);
+    for (size_t eq0 = 0; eq0 < rows; eq0 += slab) {
+        const size_t cnt = std::min(slab, rows - eq0);
+        {
+            Prof pr(ctx, "ntt_inv_tensor", lc.stream, bfly(ctx, cnt * 3 * ctx->LL));
+            cw::launch_ntt_inv_tensor(lc, refs, bt, b.X, eq0, cnt);
+        }
+        Prof pr(ctx, "scale", lc.stream, (double)cnt * 3 * ctx->N);
+        cw::launch_scale(lc, b.X, b.C + eq0 * 3 * ctx->L * ctx->N, (uint32_t)cnt);
+    }
+}
+
 static void mult_relin(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint32_t* refs, const cw::Batch& bt) {
+    mult_only(ctx, lc, b, refs, bt);
     const size_t rows = (size_t)bt.nq * bt.E;
-    {
-        Prof pr(ctx, "ntt_inv_tensor", lc.stream, bfly(ctx, rows * 3 * ctx->LL));
-        cw::launch_ntt_inv_tensor(lc, refs, bt, b.X);
-    }
-    {
-        Prof pr(ctx, "scale", lc.stream, (double)rows * 3 * ctx->N);
-        cw::launch_scale(lc, b.X, b.C, (uint32_t)rows);
-    }
     Prof pr(ctx, "relin", lc.stream, bfly(ctx, rows * (ctx->L + 2) * ctx->L));
     cw::launch_relin(lc, b.C, bt, b.R);
+}
+
+// Units of the deferred key switch (see cw::RootUnit): with one payload row per element, the pairs
+// (c0_j, c1_j) modulo q_j and the digit pairs (D_i, D_i+1) modulo each auxiliary prime; otherwise
+// every row alone, with up to two payload rows per unit.
+static cw::RootPlan root_plan(const pir_ctx* ctx, uint32_t s, uint32_t nq, uint32_t E, uint32_t cnt) {
+    cw::RootPlan rp{};
+    const uint32_t L = ctx->L;
+    rp.nq = nq;
+    rp.E = cnt;
+    rp.s = s;
+    rp.LP = L + ROOT_A;
+    rp.RR = root_rows(ctx);
+    rp.A = ROOT_A;
+    auto add = [&](uint32_t src0, uint32_t row0, uint32_t src1, uint32_t row1, bool two, uint32_t prime, uint32_t r0,
+                   uint32_t nr) {
+        cw::RootUnit& u = rp.u[rp.U++];
+        u.src0 = (uint16_t)src0;
+        u.row0 = (uint16_t)row0;
+        u.src1 = (uint16_t)src1;
+        u.row1 = (uint16_t)row1;
+        u.two = two ? 1 : 0;
+        u.prime = (uint8_t)prime;
+        u.prow = (uint8_t)(prime < L ? prime : L + (prime - ctx->LL));
+        u.r0 = (uint8_t)r0;
+        u.nr = (uint8_t)nr;
+    };
+    // rows of C per element: c0 limb j = j, c1 limb j = L + j, digit i = 2L + i; accumulator rows:
+    // c0 / c1 limb j = j / L + j, digit i modulo deferred-switch prime a = 2L + i A + a (context
+    // prime LL + a)
+    const uint32_t LL = ctx->LL;
+    if (s == 1) {
+        for (uint32_t j = 0; j < L; ++j) add(j, j, L + j, L + j, true, j, 0, 1);
+        for (uint32_t a = 0; a < ROOT_A; ++a)
+            for (uint32_t i = 0; i < L; i += 2)
+                add(2 * L + i, 2 * L + i * ROOT_A + a, 2 * L + i + 1, 2 * L + (i + 1) * ROOT_A + a, i + 1 < L, LL + a, 0, 1);
+    } else {
+        for (uint32_t r0 = 0; r0 < s; r0 += 2) {
+            const uint32_t nr = std::min<uint32_t>(2, s - r0);
+            for (uint32_t j = 0; j < 2 * L; ++j) add(j, j, 0, 0, false, j % L, r0, nr);
+            for (uint32_t a = 0; a < ROOT_A; ++a)
+                for (uint32_t i = 0; i < L; ++i) add(2 * L + i, 2 * L + i * ROOT_A + a, 0, 0, false, LL + a, r0, nr);
+        }
+    }
+    rp.lazy = 1;  // lazy transforms when every ciphertext prime is below 2^48 (the D primes are)
+    for (uint32_t j = 0; j < L; ++j) rp.lazy = rp.lazy && ctx->primes[j] < cw::FP_LAZY_BOUND;
+    rp.slice = root_slice(ctx, E, nq, rp.U);
+    rp.nslices = (cnt + rp.slice - 1) / rp.slice;
+    return rp;
 }
 
 static cw::Batch one_query(uint32_t E, const uint64_t* leaves, const uint64_t* nodes, const pir_key* key, uint64_t* sel) {
@@ -815,7 +967,8 @@ static int prepare_query(pir_ctx* ctx, const Launch& lc, const Bufs& b, const pi
     CW_TRY(make_leaves(ctx, lc, qs.query, db->m, qs.QX));
     {
         Prof pr(ctx, "fill", lc.stream);
-        cw::launch_fill(lc.stream, qs.answer, (size_t)db->s * 2 * ctx->L * ctx->N, 0);
+        if (deferred(ctx, db) && db->k >= 2) cw::launch_fill(lc.stream, qs.racc, racc_words(ctx, db), 0);
+        else cw::launch_fill(lc.stream, qs.answer, (size_t)db->s * 2 * ctx->L * ctx->N, 0);
     }
     if (db->groups.size() == 1 && db->groups[0].np)
         make_nodes(ctx, lc, b, db->dpairs, db->groups[0].level_end, qs.QX, qs.key, qs.sel, qs.nodes, ctx->chunk);
@@ -836,6 +989,38 @@ static int chunk_step(pir_ctx* ctx, const Launch& lc, const Bufs& b, const pir_d
             make_nodes(ctx, lc, b, db->dpairs + 2 * (size_t)db->groups[c].p0, db->groups[c].level_end, qs[q]->QX, qs[q]->key,
                        qs[q]->sel, qs[q]->nodes, E);
     const uint32_t* refs = db->drefs + 2 * e0;
+    if (deferred(ctx, db) && k >= 2) {
+        // the chunk's payload modulo the q_j and the auxiliary primes, then per group of queries:
+        // root products, their transforms times the payload summed per slice, slices into the
+        // query's accumulators (the key switch waits for finalize_query)
+        {
+            Prof pr(ctx, "payload_ntt", lc.stream, bfly(ctx, (size_t)cnt * s * (L + ROOT_A)));
+            cw::launch_ntt_payload(lc, db->dpay + e0 * s * N, b.Ph, (size_t)cnt * s, (uint32_t)L + ROOT_A, ctx->LL);
+        }
+        for (uint32_t q0 = 0; q0 < nq; q0 += ctx->qb) {
+            cw::Batch bt{};
+            bt.nq = std::min<uint32_t>(ctx->qb, nq - q0);
+            bt.E = cnt;
+            cw::QueryPtrs qp{};
+            for (uint32_t q = 0; q < bt.nq; ++q) {
+                const QState* x = qs[q0 + q];
+                bt.leaves[q] = x->QX;
+                bt.nodes[q] = x->nodes;
+                bt.rlk[q] = x->key->d;
+                qp.acc[q] = x->racc;
+            }
+            mult_only(ctx, lc, b, refs, bt);
+            const cw::RootPlan rp = root_plan(ctx, s, bt.nq, E, cnt);
+            {
+                Prof pr(ctx, "root_pm", lc.stream,
+                        bfly(ctx, (size_t)bt.nq * cnt * root_rows(ctx) * (s == 1 ? 1 : (s + 1) / 2)));
+                cw::launch_root_pm(lc, b.C, b.Ph, rp, b.P);
+            }
+            Prof pr(ctx, "root_reduce", lc.stream, (double)rp.nslices * bt.nq * s * rp.RR * N);
+            cw::launch_root_reduce(lc, b.P, rp, qp);
+        }
+        return check_launch(ctx);
+    }
     for (uint32_t q0 = 0; q0 < nq; q0 += ctx->qb) {
         cw::Batch bt{};
         bt.nq = std::min<uint32_t>(ctx->qb, nq - q0);
@@ -867,8 +1052,24 @@ static int chunk_step(pir_ctx* ctx, const Launch& lc, const Bufs& b, const pir_d
 }
 
 static int finalize_query(pir_ctx* ctx, const Launch& lc, const pir_db* db, QState& qs) {
-    Prof pr(ctx, "ntt_inv", lc.stream, bfly(ctx, (size_t)db->s * 2 * ctx->L));
-    cw::launch_ntt(lc, true, qs.answer, qs.answer, (size_t)db->s * 2 * ctx->L, ctx->L, 0);
+    const uint32_t L = ctx->L, s = db->s, RR = root_rows(ctx);
+    const size_t N = ctx->N;
+    if (deferred(ctx, db) && db->k >= 2) {
+        // the deferred key switch: digit sums back to coefficients modulo b0 and b1, CRT to the
+        // q_j, transformed again, multiplied by the key and added to the c0 / c1 sums
+        uint64_t *Wc, *WQ;
+        CW_TRY(ws_get_t(ctx, "root_wc", (size_t)s * L * ROOT_A * N, &Wc));
+        CW_TRY(ws_get_t(ctx, "root_wq", (size_t)s * L * L * N, &WQ));
+        Prof pr(ctx, "root_finalize", lc.stream, bfly(ctx, (size_t)s * (L * ROOT_A + L * L)));
+        for (uint32_t r = 0; r < s; ++r)
+            cw::launch_ntt(lc, true, qs.racc + ((size_t)r * RR + 2 * L) * N, Wc + (size_t)r * L * ROOT_A * N,
+                           (size_t)L * ROOT_A, ROOT_A, ctx->LL);
+        cw::launch_root_crt(lc, ctx->crt, Wc, s, WQ);
+        cw::launch_ntt(lc, false, WQ, WQ, (size_t)s * L * L, L, 0);
+        cw::launch_root_combine(lc, qs.racc, WQ, qs.key->d, s, RR, qs.answer);
+    }
+    Prof pr(ctx, "ntt_inv", lc.stream, bfly(ctx, (size_t)s * 2 * L));
+    cw::launch_ntt(lc, true, qs.answer, qs.answer, (size_t)s * 2 * L, L, 0);
     return check_launch(ctx);
 }
 
@@ -878,12 +1079,14 @@ static int answer_same_db(pir_ctx* ctx, hipStream_t st, const pir_db* db, uint32
     const uint32_t E = ctx->chunk;
     Launch lc = make_launch(ctx, st);
     Bufs b;
-    CW_TRY(get_bufs(ctx, E, std::min<uint32_t>(B, ctx->qb), db->s, b));
-    uint64_t *QX, *nodes = nullptr, *sel;
-    const size_t qx_one = qx_words(ctx, db), node_one = node_words(ctx, db), sel_one = sel_words(ctx);
+    CW_TRY(get_bufs(ctx, E, std::min<uint32_t>(B, ctx->qb), db->s, b, deferred(ctx, db)));
+    uint64_t *QX, *nodes = nullptr, *sel = nullptr, *racc = nullptr;
+    const size_t qx_one = qx_words(ctx, db), node_one = node_words(ctx, db), sel_one = sel_words(ctx, db);
+    const size_t racc_one = racc_words(ctx, db);
     CW_TRY(ws_get_t(ctx, "QX", qx_one * B, &QX));
     if (node_one) CW_TRY(ws_get_t(ctx, "nodes", node_one * B, &nodes));
-    CW_TRY(ws_get_t(ctx, "sel", sel_one * B, &sel));
+    if (sel_one) CW_TRY(ws_get_t(ctx, "sel", sel_one * B, &sel));
+    if (racc_one) CW_TRY(ws_get_t(ctx, "racc", racc_one * B, &racc));
     std::vector<QState> st_q(B);
     std::vector<QState*> ptrs(B);
     for (uint32_t q = 0; q < B; ++q) {
@@ -893,7 +1096,8 @@ static int answer_same_db(pir_ctx* ctx, hipStream_t st, const pir_db* db, uint32
         x.answer = answers[q];
         x.QX = QX + q * qx_one;
         x.nodes = node_one ? nodes + q * node_one : nullptr;
-        x.sel = sel + q * sel_one;
+        x.sel = sel_one ? sel + q * sel_one : nullptr;
+        x.racc = racc_one ? racc + q * racc_one : nullptr;
         ptrs[q] = &x;
         CW_TRY(prepare_query(ctx, lc, b, db, x));
     }
@@ -998,6 +1202,27 @@ extern "C" int pir_selectors(pir_ctx* ctx, const pir_key* key, const pir_db* db,
     return end_async(ctx, st);
 }
 
+// Range check of `polys` polynomials [polys][L][N] on stream st; waits for the result.
+static int check_residues(pir_ctx* ctx, hipStream_t st, const uint64_t* x, size_t polys) {
+    if (!polys) return PIR_OK;
+    CW_HIP(ctx, hipSetDevice(ctx->device));
+    Launch lc = make_launch(ctx, st);
+    cw::launch_fill(st, (uint64_t*)ctx->dflag, 1, 0);
+    cw::launch_check_residues(lc, x, polys, ctx->dflag);
+    CW_TRY(check_launch(ctx));
+    uint32_t h = 0;
+    CW_HIP(ctx, hipMemcpyAsync(&h, ctx->dflag, 4, hipMemcpyDeviceToHost, st));
+    CW_HIP(ctx, hipStreamSynchronize(st));
+    if (h) return fail(PIR_E_INVALID, "a query residue is not below its prime (residue >= q_i)");
+    return PIR_OK;
+}
+
+extern "C" int pir_check_query(pir_ctx* ctx, const uint64_t* query, uint32_t count, void* stream) {
+    CW_ENTER(ctx);
+    if (count && !query) return fail(PIR_E_INVALID, "null argument");
+    return check_residues(ctx, (hipStream_t)stream, query, (size_t)count * 2);
+}
+
 // ------------------------------------------------------------------------------------------------
 // serving: continuous batching
 //
@@ -1035,6 +1260,7 @@ struct ServeSlot {
 struct pir_server {
     pir_ctx* ctx = nullptr;
     hipStream_t stream = nullptr;
+    hipStream_t check_stream = nullptr;  // residue checks of submitted queries
     std::vector<ServeSlot> slots;
     std::deque<ServeReq> pending;
     std::map<const pir_db*, uint32_t> cursor;
@@ -1059,6 +1285,11 @@ extern "C" int pir_serve_open(pir_ctx* ctx, uint32_t max_slots, pir_server** out
         delete srv;
         return fail(PIR_E_DEVICE, "stream creation failed");
     }
+    if (hipStreamCreateWithFlags(&srv->check_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipStreamDestroy(srv->stream);
+        delete srv;
+        return fail(PIR_E_DEVICE, "stream creation failed");
+    }
     *out = srv;
     return PIR_OK;
 }
@@ -1070,6 +1301,8 @@ extern "C" int pir_serve_submit(pir_server* srv, const pir_key* key, const pir_d
     CW_ENTER(ctx);
     if (!key || !db || !query || !answer || !ticket) return fail(PIR_E_INVALID, "null argument");
     if (key->ctx != ctx || db->ctx != ctx) return fail(PIR_E_INVALID, "handle from another context");
+    if (key->galois) return fail(PIR_E_INVALID, "a Galois key is not a relinearization key");
+    CW_TRY(check_residues(ctx, srv->check_stream, query, (size_t)2 * db->m));
     *ticket = srv->next_ticket++;
     const uint64_t now = (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
                              std::chrono::steady_clock::now().time_since_epoch())
@@ -1085,8 +1318,9 @@ static int serve_admit(pir_server* srv, const Launch& lc, const Bufs& b) {
         if (srv->pending.empty()) break;
         if (sl.used) continue;
         const ServeReq r = srv->pending.front();
-        const size_t qxw = qx_words(ctx, r.db), nw = node_words(ctx, r.db), sw = sel_words(ctx);
-        const size_t need = qxw + nw + sw;
+        const size_t qxw = qx_words(ctx, r.db), nw = node_words(ctx, r.db), sw = sel_words(ctx, r.db);
+        const size_t rw = racc_words(ctx, r.db);
+        const size_t need = qxw + nw + sw + rw;
         if (sl.buf_words < need) {
             if (sl.buf) {
                 CW_HIP(ctx, hipStreamSynchronize(srv->stream));
@@ -1095,11 +1329,23 @@ static int serve_admit(pir_server* srv, const Launch& lc, const Bufs& b) {
                 sl.buf_words = 0;
             }
             if (dev_alloc(ctx, (void**)&sl.buf, need * 8) != PIR_OK) {
-                bool any = false;
-                for (const ServeSlot& o : srv->slots) any = any || o.used;
-                if (!any) return PIR_E_NOMEM;  // nothing running will free memory: report it
-                g_err.clear();                 // the request waits for a running query to finish
-                return PIR_OK;
+                // idle slots keep their buffers for reuse: release them (once their queued work has
+                // run) and the context's cached work buffers that serving does not use, then retry
+                CW_HIP(ctx, hipStreamSynchronize(srv->stream));
+                for (ServeSlot& o : srv->slots)
+                    if (!o.used && o.buf) {
+                        dev_free(ctx, o.buf, o.buf_words * 8);
+                        o.buf = nullptr;
+                        o.buf_words = 0;
+                    }
+                trim_work_buffers(ctx);
+                if (dev_alloc(ctx, (void**)&sl.buf, need * 8) != PIR_OK) {
+                    bool any = false;
+                    for (const ServeSlot& o : srv->slots) any = any || o.used;
+                    if (!any) return PIR_E_NOMEM;  // nothing running will free memory: report it
+                    g_err.clear();                 // the request waits for a running query to finish
+                    return PIR_OK;
+                }
             }
             sl.buf_words = need;
         }
@@ -1115,7 +1361,8 @@ static int serve_admit(pir_server* srv, const Launch& lc, const Bufs& b) {
         sl.qs.answer = r.answer;
         sl.qs.QX = sl.buf;
         sl.qs.nodes = nw ? sl.buf + qxw : nullptr;
-        sl.qs.sel = sl.buf + qxw + nw;
+        sl.qs.sel = sw ? sl.buf + qxw + nw : nullptr;
+        sl.qs.racc = rw ? sl.buf + qxw + nw + sw : nullptr;
         srv->pending.pop_front();
         ++srv->n_admitted;
         CW_TRY(prepare_query(ctx, lc, b, r.db, sl.qs));
@@ -1146,11 +1393,18 @@ extern "C" int pir_serve_step(pir_server* srv) {
     }
     Launch lc = make_launch(ctx, srv->stream);
     uint32_t max_s = 1;
+    bool defer = false;
     for (const ServeSlot& sl : srv->slots)
-        if (sl.used) max_s = std::max(max_s, sl.db->s);
-    for (const ServeReq& r : srv->pending) max_s = std::max(max_s, r.db->s);
+        if (sl.used) {
+            max_s = std::max(max_s, sl.db->s);
+            defer = defer || deferred(ctx, sl.db);
+        }
+    for (const ServeReq& r : srv->pending) {
+        max_s = std::max(max_s, r.db->s);
+        defer = defer || deferred(ctx, r.db);
+    }
     Bufs b;
-    CW_TRY(get_bufs(ctx, ctx->chunk, ctx->qb, max_s, b));
+    CW_TRY(get_bufs(ctx, ctx->chunk, ctx->qb, max_s, b, defer));
     CW_TRY(serve_admit(srv, lc, b));
     if (srv->policy == PIR_SERVE_SIZE_AGED) {  // one chunk of the query with the smallest priority
         ServeSlot* best = nullptr;
@@ -1278,6 +1532,7 @@ extern "C" void pir_serve_close(pir_server* srv) {
     for (auto& kv : srv->done) (void)hipEventDestroy(kv.second);
     for (hipEvent_t e : srv->rounds) (void)hipEventDestroy(e);
     (void)hipStreamDestroy(srv->stream);
+    (void)hipStreamDestroy(srv->check_stream);
     delete srv;
 }
 
@@ -1382,16 +1637,12 @@ extern "C" int pir_map_lossy(pir_ctx* ctx, const uint64_t* keywords, uint64_t n,
 // ------------------------------------------------------------------------------------------------
 // profiling
 // ------------------------------------------------------------------------------------------------
-extern "C" int pir_probe_fp64(pir_ctx* ctx, int op, uint32_t blocks, uint32_t iters, double* ms,
-                              double* wave_instr, void* stream) {
-    CW_ENTER(ctx);
-    if (!ms || !wave_instr) return fail(PIR_E_INVALID, "null argument");
-    if (op < 0 || op > 3) return fail(PIR_E_INVALID, "op must be 0 (fma), 1 (mul), 2 (add) or 3 (rint + add)");
-    if (blocks < 1 || blocks > (1u << 20) || iters < 1 || iters > (1u << 20))
-        return fail(PIR_E_INVALID, "blocks and iters must lie in [1, 2^20]");
-    hipStream_t st = (hipStream_t)stream;
+// Warm-up launch, then one launch timed with HIP events on `st`; `launch` enqueues the probe into
+// the 8-byte-per-thread buffer `out` and returns its wave-instruction count.
+template <class F>
+static int run_probe(pir_ctx* ctx, hipStream_t st, uint32_t blocks, double* ms, double* wave_instr, F launch) {
     CW_TRY(begin_async(ctx, st));
-    double* out;
+    uint64_t* out;
     CW_TRY(ws_get_t(ctx, "probe", (size_t)blocks * cw::probe_threads(), &out));
     hipEvent_t e0, e1;
     CW_HIP(ctx, hipEventCreate(&e0));
@@ -1399,9 +1650,9 @@ extern "C" int pir_probe_fp64(pir_ctx* ctx, int op, uint32_t blocks, uint32_t it
         (void)hipEventDestroy(e0);
         return fail(PIR_E_DEVICE, "event creation failed");
     }
-    cw::launch_probe_fp64(st, op, blocks, iters, out);  // warm-up
+    launch(out);  // warm-up
     (void)hipEventRecord(e0, st);
-    const double wi = cw::launch_probe_fp64(st, op, blocks, iters, out);
+    const double wi = launch(out);
     (void)hipEventRecord(e1, st);
     float t = 0.f;
     const bool ok = hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&t, e0, e1) == hipSuccess;
@@ -1411,6 +1662,32 @@ extern "C" int pir_probe_fp64(pir_ctx* ctx, int op, uint32_t blocks, uint32_t it
     *ms = t;
     *wave_instr = wi;
     return end_async(ctx, st);
+}
+
+static int check_probe(double* ms, double* wave_instr, int op, uint32_t blocks, uint32_t iters) {
+    if (!ms || !wave_instr) return fail(PIR_E_INVALID, "null argument");
+    if (op < 0 || op > 3) return fail(PIR_E_INVALID, "op must lie in [0, 3]");
+    if (blocks < 1 || blocks > (1u << 20) || iters < 1 || iters > (1u << 20))
+        return fail(PIR_E_INVALID, "blocks and iters must lie in [1, 2^20]");
+    return PIR_OK;
+}
+
+extern "C" int pir_probe_fp64(pir_ctx* ctx, int op, uint32_t blocks, uint32_t iters, double* ms,
+                              double* wave_instr, void* stream) {
+    CW_ENTER(ctx);
+    CW_TRY(check_probe(ms, wave_instr, op, blocks, iters));
+    hipStream_t st = (hipStream_t)stream;
+    return run_probe(ctx, st, blocks, ms, wave_instr,
+                     [&](uint64_t* out) { return cw::launch_probe_fp64(st, op, blocks, iters, (double*)out); });
+}
+
+extern "C" int pir_probe_int(pir_ctx* ctx, int op, uint32_t blocks, uint32_t iters, double* ms, double* wave_instr,
+                             void* stream) {
+    CW_ENTER(ctx);
+    CW_TRY(check_probe(ms, wave_instr, op, blocks, iters));
+    hipStream_t st = (hipStream_t)stream;
+    return run_probe(ctx, st, blocks, ms, wave_instr,
+                     [&](uint64_t* out) { return cw::launch_probe_int(st, op, blocks, iters, out); });
 }
 
 extern "C" int pir_profile_enable(pir_ctx* ctx, int on) {
@@ -1513,6 +1790,20 @@ static int check_schedule(const pir_ctx* ctx, const pir_schedule* s) {
     if (ctx->live_dbs || ctx->live_graphs)
         return fail(PIR_E_INVALID, "the schedule is fixed once a database is encoded");
     return PIR_OK;
+}
+
+extern "C" int pir_set_defer_relin(pir_ctx* ctx, int on) {
+    CW_ENTER(ctx);
+    if (on != 0 && on != 1) return fail(PIR_E_INVALID, "on must be 0 or 1");
+    if (ctx->live_dbs || ctx->live_graphs)
+        return fail(PIR_E_INVALID, "the root key switch mode changes only while no database is encoded");
+    ctx->defer = on == 1;
+    return PIR_OK;
+}
+
+extern "C" int pir_get_defer_relin(pir_ctx* ctx) {
+    CW_ENTER(ctx);
+    return ctx->defer ? 1 : 0;
 }
 
 extern "C" int pir_get_schedule(pir_ctx* ctx, pir_schedule* out) {
@@ -1984,14 +2275,7 @@ extern "C" int pir_arith_equality(pir_ctx* ctx, const pir_key* key, const uint64
         const uint32_t cnt = std::min(E, m - i0);
         cw::launch_pair_refs(st, refs, cnt, i0, m + i0);
         cw::Batch bt = one_query(cnt, QX, nullptr, key, sel);
-        {
-            Prof pr(ctx, "ntt_inv_tensor", st, bfly(ctx, (size_t)cnt * 3 * LL));
-            cw::launch_ntt_inv_tensor(lc, refs, bt, b.X);
-        }
-        {
-            Prof pr(ctx, "scale", st, (double)cnt * 3 * N);
-            cw::launch_scale(lc, b.X, b.C, cnt);
-        }
+        mult_only(ctx, lc, b, refs, bt);
         cw::launch_sum_rows(lc, b.C, cnt, (uint32_t)(3 * L), i0 == 0, S);
     }
     {

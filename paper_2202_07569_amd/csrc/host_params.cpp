@@ -150,8 +150,20 @@ static void build_conv(ConvTable& T, const std::vector<uint64_t>& in, const std:
     }
 }
 
+std::vector<uint64_t> primes_below(uint32_t N, uint64_t below, uint32_t count, const std::vector<uint64_t>& avoid) {
+    std::vector<uint64_t> out;
+    const uint64_t step = 2ull * N;
+    uint64_t c = (below - 1) / step * step + 1;
+    if (c >= below) c -= step;
+    while (out.size() < count && c > step) {
+        if (is_prime(c) && std::find(avoid.begin(), avoid.end(), c) == avoid.end()) out.push_back(c);
+        c -= step;
+    }
+    return out;
+}
+
 void build_const(CtxConst& K, uint32_t N, const std::vector<uint64_t>& q, const std::vector<uint64_t>& B,
-                 uint64_t t) {
+                 uint64_t t, const std::vector<uint64_t>& D) {
     std::memset(&K, 0, sizeof(K));
     K.N = N;
     K.logN = bitlen64(N) - 1;
@@ -161,7 +173,8 @@ void build_const(CtxConst& K, uint32_t N, const std::vector<uint64_t>& q, const 
     K.t = t;
     std::vector<uint64_t> all(q);
     all.insert(all.end(), B.begin(), B.end());
-    for (uint32_t i = 0; i < K.LL; ++i) {
+    all.insert(all.end(), D.begin(), D.end());
+    for (uint32_t i = 0; i < (uint32_t)all.size(); ++i) {
         uint64_t p = all[i];
         K.p[i] = p;
         uint32_t s = bitlen64(p);
@@ -231,6 +244,20 @@ void build_switch(SwitchConst& S, const std::vector<uint64_t>& q, uint32_t keep)
     for (size_t j = 0; j < kept.size(); ++j) {
         S.rinv[j] = invmod(mw_mod(r, kept[j]), kept[j]);
         S.rinvq[j] = shoup(S.rinv[j], kept[j]);
+    }
+}
+
+void build_crt(CrtConst& cc, const std::vector<uint64_t>& q, uint64_t b0, uint64_t b1) {
+    std::memset(&cc, 0, sizeof(cc));
+    cc.b0inv = invmod(b0 % b1, b1);
+    cc.b0invq = shoup(cc.b0inv, b1);
+    const u128 half = ((u128)b0 * b1 - 1) / 2;  // b0 b1 is odd
+    cc.half_hi = (uint64_t)(half >> 64);
+    cc.half_lo = (uint64_t)half;
+    for (size_t j = 0; j < q.size(); ++j) {
+        cc.b0q[j] = b0 % q[j];
+        cc.b0qq[j] = shoup(cc.b0q[j], q[j]);
+        cc.Bq[j] = mulmod(b0 % q[j], b1 % q[j], q[j]);
     }
 }
 

@@ -46,6 +46,21 @@ struct Launch {
     uint32_t* fixcnt;     // its counter; zero between launches
 };
 
+// Root products with the key switch deferred past the inner product (see kernels.hip).  A unit is
+// the work of one workgroup per element: one or two rows of the coefficient-form root products
+// C [nq E][3][L][N] (row src = poly * L + limb), transformed modulo context prime `prime`, each
+// multiplied by payload rows r0 .. r0 + nr - 1 of the element and summed into accumulator row
+// `row` of the query's [s][RR][N] accumulators (rows 0 .. 2L-1: c0 and c1 limbs modulo q_j;
+// row 2L + i A + a: digit i modulo the deferred switch's prime a, context prime LL + a).
+constexpr int ROOT_MAX_UNITS = 112;
+struct RootUnit {
+    uint16_t src0, src1, row0, row1;
+    uint8_t prime, prow, r0, nr, two;  // prow: the prime's row among an element's payload rows
+};
+struct RootPlan {  // passed by value
+    uint32_t nq, E, slice, nslices, s, LP, RR, U, A, lazy;
+    RootUnit u[ROOT_MAX_UNITS];
+};
 hipError_t kernels_init();
 void launch_ntt(const Launch& lc, bool inverse, const uint64_t* in, uint64_t* out, size_t rows, uint32_t nl,
                 uint32_t pbase);
@@ -53,13 +68,19 @@ void launch_ntt(const Launch& lc, bool inverse, const uint64_t* in, uint64_t* ou
 // allowed).
 void launch_ntt_operand(const Launch& lc, const uint64_t* in, uint64_t* out, size_t rows, uint32_t nl,
                         uint32_t pbase);
-void launch_ntt_payload(const Launch& lc, const uint16_t* pay, uint64_t* out, size_t rows_u16);
+// Lift and transform uint16 rows: out [rows_u16][nl][N], row j modulo context prime j for j < L and
+// prime dbase + j - L above (nl = 0: L).
+void launch_ntt_payload(const Launch& lc, const uint16_t* pay, uint64_t* out, size_t rows_u16, uint32_t nl = 0,
+                        uint32_t dbase = 0);
 // Transformed relinearization staging [E][L+2][L][N] straight from a coefficient-form [E][3][L][N].
 void launch_ntt_digits(const Launch& lc, const uint64_t* c3, uint64_t* out, uint32_t E);
 void launch_extend(const Launch& lc, const uint64_t* in, uint64_t* out, size_t G);
 // Tensor product (a0 b0, a0 b1 + a1 b0, a1 b1) of E operand pairs over Q u B, formed while loading
 // and inverse-transformed: X [E][3][LL][N] in coefficient form.
-void launch_ntt_inv_tensor(const Launch& lc, const uint32_t* refs, const Batch& bt, uint64_t* X);
+// Only rows eq0 .. eq0 + count - 1 of the batch (row eq = q E + e; count = 0: to the end), stored from
+// X on (X [count][3][LL][N]).
+void launch_ntt_inv_tensor(const Launch& lc, const uint32_t* refs, const Batch& bt, uint64_t* X, size_t eq0 = 0,
+                           size_t count = 0);
 void launch_scale(const Launch& lc, const uint64_t* X, uint64_t* out, uint32_t E);
 void launch_relin_mac(const Launch& lc, const uint64_t* R, const Batch& bt);
 // Key switching of E coefficient-form products [E][3][L][N] into transformed selectors [E][2][L][N]
@@ -67,6 +88,18 @@ void launch_relin_mac(const Launch& lc, const uint64_t* R, const Batch& bt);
 void launch_relin(const Launch& lc, const uint64_t* c3, const Batch& bt, uint64_t* staging);
 // Whether launch_relin needs its staging buffer [E][L+2][L][N] at this ring degree.
 bool relin_needs_staging(uint32_t logN);
+// Deferred root key switch (fp64 path, N <= 8192): part [nslices][nq][s][RR][N] receives each
+// slice's sums of transformed rows times payload rows Ph [E][s][LP][N] (residues).
+void launch_root_pm(const Launch& lc, const uint64_t* C, const uint64_t* Ph, const RootPlan& plan, uint64_t* part);
+// racc_q [s][RR][N] += sum over slices of part[.][q] (mod each row's prime), q < nq.
+void launch_root_reduce(const Launch& lc, const uint64_t* part, const RootPlan& plan, const QueryPtrs& qp);
+// Wc [s][L][2][N] (coefficient form, digit i modulo d0 and d1) -> WQ [s][L][L][N]: the centred
+// integer digit sum modulo every q_j.
+void launch_root_crt(const Launch& lc, const CrtConst& cc, const uint64_t* Wc, uint32_t s, uint64_t* WQ);
+// answer [s][2][L][N] (transformed) = racc c rows + sum_i WQ^[r][i][j] key[i][poly][j] mod q_j, WQ^
+// transformed; key in the path's operand format.
+void launch_root_combine(const Launch& lc, const uint64_t* racc, const uint64_t* WQ, const uint64_t* rlk, uint32_t s,
+                         uint32_t RR, uint64_t* answer);
 void launch_shoup_companions(const Launch& lc, const uint64_t* v, uint64_t* comp, size_t rows, uint32_t nl);
 void launch_gather_leaf(const Launch& lc, const uint32_t* refs, const Batch& bt);
 void launch_accumulate(const Launch& lc, const QueryPtrs& qp, const uint64_t* Ph, uint32_t nq, uint32_t E,
@@ -106,10 +139,16 @@ void launch_seeded_query(const Launch& lc, const uint64_t* c0, uint32_t count, u
 // one double per thread to out; returns the wave-instructions of the timed operation(s).
 uint32_t probe_threads();
 double launch_probe_fp64(hipStream_t st, int op, uint32_t blocks, uint32_t iters, double* out);
+// Integer issue-rate probe (probe.hip): op 0 v_mul_lo_u32, 1 v_mul_hi_u32, 2 v_mad_u64_u32,
+// 3 v_lshl_add_u64 (64-bit add), on 8 independent chains; one u64 per thread to out.
+double launch_probe_int(hipStream_t st, int op, uint32_t blocks, uint32_t iters, uint64_t* out);
 // Row gather: dst row e = src row order[e] for e < n, rows of `row` uint16 (a multiple of 8).
 void launch_gather_rows(hipStream_t st, const uint16_t* src, const uint64_t* order, uint64_t n, size_t row,
                         uint16_t* dst);
 void launch_fill(hipStream_t st, uint64_t* p, size_t n, uint64_t v);
+// Residue range check of `polys` polynomials [polys][L][N]: sets *flag (device) to 1 if any residue
+// of limb j is >= q_j; the flag is left as it is otherwise.
+void launch_check_residues(const Launch& lc, const uint64_t* x, size_t polys, uint32_t* flag);
 void launch_map_perfect(hipStream_t st, const uint64_t* ids, size_t n, uint32_t m, uint32_t k, const uint64_t* binom,
                         uint32_t* out);
 void launch_map_lossy(hipStream_t st, const uint64_t* kw, size_t n, uint32_t m, uint32_t k, uint64_t seed,

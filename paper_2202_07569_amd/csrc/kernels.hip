@@ -539,14 +539,19 @@ struct RowsInvU64 {
     __device__ void store(size_t g, uint32_t tid, int u, uint64_t v) const { out[natural_pos<Sh>(g, tid, u)] = v; }
 };
 
-// Payload rows: row g = (e s + r) L + j lifts uint16 row (e, r) (values < 2^16 < q_j, so the
-// residue is the value itself) and transforms it modulo q_j.
+// Payload rows: row g = (e s + r) nl + j lifts uint16 row (e, r) (values < 2^16 < every prime, so
+// the residue is the value itself) and transforms it modulo prime j of the context (the L ciphertext
+// primes, then, for nl > L, the first auxiliary primes).
 template <class Sh>
 struct RowsPayload {
     const uint16_t* pay;
     uint64_t* out;
-    uint32_t L;
-    __device__ uint32_t prime(size_t g) const { return (uint32_t)(g % L); }
+    uint32_t L;  // rows per uint16 row (nl)
+    uint32_t q, dbase;  // rows j >= q use context prime dbase + j - q
+    __device__ uint32_t prime(size_t g) const {
+        const uint32_t j = (uint32_t)(g % L);
+        return j < q ? j : dbase + j - q;
+    }
     __device__ void load(size_t g, uint32_t tid, uint64_t* a) const {
         const uint16_t* src = pay + (g / L) * Sh::N;
 #pragma unroll
@@ -597,6 +602,7 @@ struct RowsTensor {
     const CtxConst* K;
     uint32_t LL;
     size_t eshift;  // rows of earlier queries in a batched launch: refs index = element - eshift
+    size_t gshift;  // output row of row g is g - gshift (a launch over part of the batch)
     __device__ uint32_t prime(size_t g) const { return (uint32_t)(g % LL); }
     __device__ void load(size_t g, uint32_t tid, uint64_t* a) const {
         constexpr int N = Sh::N, T = Sh::T;
@@ -652,7 +658,9 @@ struct RowsTensor {
                 a[u] = fmulmod(A[o0 + u * T], B[o1 + u * T], p, pinv) + fmulmod(A[o1 + u * T], B[o0 + u * T], p, pinv);
         }
     }
-    __device__ void store(size_t g, uint32_t tid, int u, uint64_t v) const { out[natural_pos<Sh>(g, tid, u)] = v; }
+    __device__ void store(size_t g, uint32_t tid, int u, uint64_t v) const {
+        out[natural_pos<Sh>(g - gshift, tid, u)] = v;
+    }
 };
 
 // Forward transform of coefficient-form rows (u64 residues in [0, p)) into the fp64 operand
@@ -689,8 +697,8 @@ __global__ __launch_bounds__(Sh::T) void k_ntt_inv(const CtxConst* __restrict__ 
 template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T) void k_ntt_payload(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
                                                        const double* __restrict__ twf, const uint16_t* __restrict__ pay,
-                                                       uint64_t* __restrict__ out) {
-    ntt_fwd_row<Sh, FP>(K, tw, twf, RowsPayload<Sh>{pay, out, K->L});
+                                                       uint64_t* __restrict__ out, uint32_t nl, uint32_t dbase) {
+    ntt_fwd_row<Sh, FP>(K, tw, twf, RowsPayload<Sh>{pay, out, nl, K->L, dbase});
 }
 template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T) void k_ntt_digits(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
@@ -702,17 +710,17 @@ template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T, Sh::LOGN == 13 ? 8 : 1) void k_ntt_inv_tensor(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
                                                           const double* __restrict__ twf,
                                                           const uint32_t* __restrict__ refs, const Batch bt,
-                                                          uint64_t* __restrict__ X, size_t groups) {
+                                                          uint64_t* __restrict__ X, size_t groups, size_t eq0) {
     __shared__ uint64_t sm[Sh::LDS_WORDS];
     size_t el;
     uint32_t r;
     xcd_split(blockIdx.x, 3, el, r);
     if (el >= groups) return;
     const uint32_t LL = K->LL;
-    const size_t eq = el / LL;            // row of the launch: query q, element e
+    const size_t eq = eq0 + el / LL;      // row of the batch: query q, element e; X holds rows from eq0 on
     const uint32_t q = (uint32_t)(eq / bt.E);
     const size_t g = (eq * 3 + r) * LL + el % LL;
-    const RowsTensor<Sh> row{refs, bt.leaves[q], bt.nodes[q], X, K, LL, (size_t)q * bt.E};
+    const RowsTensor<Sh> row{refs, bt.leaves[q], bt.nodes[q], X, K, LL, (size_t)q * bt.E, eq0 * 3 * LL};
     const uint32_t tid = threadIdx.x;
     const uint32_t pi = row.prime(g);
     if constexpr (FP) {
@@ -935,6 +943,265 @@ void launch_relin(const Launch& lc, const uint64_t* c3, const Batch& bt, uint64_
 
 bool relin_needs_staging(uint32_t logN) { return logN >= 14; }
 
+// ---------------------------------------------------------------------------------------------
+// Root products with the key switch deferred past the inner product (fp64 path).
+//
+// The answer is linear in every selector.  With element e's root product c = (c0, c1, c2) and its
+// relinearization digits D_i = [c2]_{q_i} (integers in [0, q_i)),
+//   sel_e = (c0 + sum_i D_i b_i, c1 + sum_i D_i a_i)   and so
+//   answer_r = (sum_e c0 P_er + sum_i b_i W_ir,  sum_e c1 P_er + sum_i a_i W_ir),   W_ir = sum_e D_ei P_er
+// in R_q: the same residues as relinearizing every element first.  W_ir is a sum of negacyclic
+// products of small non-negative integer polynomials, so its coefficients are integers below
+// n N max q_i 2^16 in magnitude; two auxiliary primes with b0 b1 above twice that bound hold it
+// exactly (the host checks the bound per database), and W_ir mod q_j follows by CRT once per
+// answer.  Per element that is 2L transforms modulo the q_j (c0, c1) and 2L modulo b0, b1 (the
+// digits), against L^2 + 2L and 2 L^2 N key products for relinearizing it; the key multiplies the
+// L digit sums once per answer.
+//
+// k_root_pm_f: workgroup (slice, query, unit) transforms the unit's one or two rows of every element
+// of its slice (all modulo one prime, whose forward twiddles are staged in LDS once), multiplies
+// each by the element's transformed payload rows modulo that prime and sums them in registers; the
+// sums leave as residues in [0, p) into part[slice][q][r][row][N].  Workgroups of one slice share
+// an XCD (xcd_split), with the units of one prime side by side (they read the same payload rows).
+// Bounds: without LAZY a transform output is in [-p/2, p/2] and each product below (1/2 + 2^-5) p,
+// so eight products keep a sum below 4.3 p + p/2 < 2^53 before it is reduced again.  LAZY (every
+// prime of the launch below 2^48; the two digit-sum primes always are): inputs below p, no
+// reduction between passes or of the outputs, which stay below 15 p (the lazy stage bound); each
+// product is then below (1/2 + 3 * 15 / 32) p < 2 p and eight of them, with the reduced sum, below
+// 16.5 p < 2^53.
+// ---------------------------------------------------------------------------------------------
+template <class Sh, int S, bool TWO, bool LAZY>
+__global__ __launch_bounds__(Sh::T) void k_root_pm_f(const CtxConst* __restrict__ K, const double* __restrict__ twf,
+                                                     const uint64_t* __restrict__ C, const uint64_t* __restrict__ Ph,
+                                                     uint64_t* __restrict__ part, const RootPlan rp) {
+    __shared__ uint64_t sm[Sh::LDS_WORDS];
+    __shared__ double twl[Sh::LDS_WORDS];  // padded like the exchange buffer
+    constexpr int N = Sh::N, T = Sh::T, EPT = Sh::EPT;
+    const uint32_t L = K->L, tid = threadIdx.x;
+    size_t sl;
+    uint32_t mem;
+    xcd_split(blockIdx.x, rp.nq * rp.U, sl, mem);
+    if (sl >= rp.nslices) return;
+    const uint32_t q = mem % rp.nq;
+    const RootUnit un = rp.u[mem / rp.nq];
+    const uint32_t pr = un.prime;
+    {
+        const double* __restrict__ g = twf + (size_t)pr * 4 * N;  // forward twiddles of the unit's prime
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) twl[lds_pad(u * T + tid)] = g[u * T + tid];
+    }
+    const double p = K->pd[pr], pinv = K->pinv[pr];
+    // a digit (rows 2L..3L-1 of the product) may exceed the unit's prime: reduce it first
+    const bool red0 = un.src0 >= 2 * L && K->pd[un.src0 - 2 * L] > p;
+    const bool two = TWO && un.two;
+    const bool red1 = two && un.src1 >= 2 * L && K->pd[un.src1 - 2 * L] > p;
+    const uint32_t e0 = (uint32_t)sl * rp.slice;
+    const uint32_t e1 = min(rp.E, e0 + rp.slice);
+    double acc0[S][EPT], acc1[TWO ? S : 1][EPT], v[EPT];
+#pragma unroll
+    for (int r = 0; r < S; ++r)
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) acc0[r][u] = 0.0;
+    if constexpr (TWO) {
+#pragma unroll
+        for (int r = 0; r < S; ++r)
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) acc1[r][u] = 0.0;
+    }
+    // steps i = (element, row): the next step's row is loaded while the current one is transformed
+    const uint32_t per = two ? 2u : 1u, steps = (e1 - e0) * per;
+    auto src_of = [&](uint32_t i) {
+        const uint32_t e = e0 + i / per;
+        return C + ((size_t)q * rp.E + e) * 3 * L * N + (size_t)((i % per) ? un.src1 : un.src0) * N;
+    };
+    uint64_t nx[EPT];
+    {
+        const uint64_t* src = src_of(0);
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) nx[u] = src[elem_index<Sh, 0>(tid, u)];
+    }
+    __syncthreads();  // twiddles staged
+    for (uint32_t i = 0; i < steps; ++i) {
+        uint32_t t = tid;
+        asm volatile("" : "+v"(t));  // keep the per-row index arithmetic out of registers across rows
+        const uint32_t e = e0 + i / per, k = i % per;
+        const bool red = k ? red1 : red0;
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) v[u] = u52_to_double(nx[u]);
+        if (red) {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) v[u] = fred(v[u], p, pinv);
+        }
+        if (i + 1 < steps) {
+            const uint64_t* src = src_of(i + 1);
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) nx[u] = src[elem_index<Sh, 0>(t, u)];
+        }
+        ntt_fwd_f<Sh, LAZY, true, !LAZY>(v, sm, t, TwRow{nullptr, twl}, K, pr);
+        asm volatile("" ::: "memory");  // keep the payload loads below the transform
+        const uint64_t* ph = Ph + ((size_t)e * rp.s + un.r0) * rp.LP * N + (size_t)un.prow * N;
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            if (r < (int)un.nr) {
+                const uint64_t* pr_row = ph + (size_t)r * rp.LP * N + t;
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) {
+                    const double w = u52_to_double(pr_row[(size_t)u * T]);
+                    if constexpr (TWO) {
+                        if (k) acc1[r][u] += fmulmod(v[u], w, p, pinv);
+                        else acc0[r][u] += fmulmod(v[u], w, p, pinv);
+                    } else {
+                        acc0[r][u] += fmulmod(v[u], w, p, pinv);
+                    }
+                }
+            }
+        }
+        asm volatile("" ::: "memory");
+        if (k + 1 == per && ((e - e0) & 7u) == 7u) {
+#pragma unroll
+            for (int r = 0; r < S; ++r)
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) {
+                    acc0[r][u] = fred(acc0[r][u], p, pinv);
+                    if constexpr (TWO) acc1[r][u] = fred(acc1[r][u], p, pinv);
+                }
+        }
+    }
+    const size_t LPS = (size_t)rp.RR * N;  // one r block of part
+    uint64_t* out = part + ((sl * rp.nq + q) * rp.s) * LPS + tid;
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+        if (r < (int)un.nr) {
+            uint64_t* o0 = out + (size_t)(un.r0 + r) * LPS + (size_t)un.row0 * N;
+            uint64_t* o1 = out + (size_t)(un.r0 + r) * LPS + (size_t)un.row1 * N;
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                o0[(size_t)u * T] = fp_to_residue(fred(acc0[r][u], p, pinv), p);
+                if constexpr (TWO)
+                    if (two) o1[(size_t)u * T] = fp_to_residue(fred(acc1[r][u], p, pinv), p);
+            }
+        }
+    }
+}
+
+void launch_root_pm(const Launch& lc, const uint64_t* C, const uint64_t* Ph, const RootPlan& plan, uint64_t* part) {
+    if (!plan.E || !plan.nq) return;
+    const unsigned blocks = (unsigned)xcd_grid(plan.nslices, plan.nq * plan.U);
+    // one payload row per element: units are row pairs; otherwise single rows with up to two
+    // payload rows (the accumulators stay at 2 EPT doubles per thread either way)
+    const bool pairs = plan.s == 1;
+#define CW_ROOT(LG, SS, TW, LZ)                                                                              \
+    hipLaunchKernelGGL((k_root_pm_f<DefaultShape<LG>::type, SS, TW, LZ>), dim3(blocks),                       \
+                       dim3(DefaultShape<LG>::type::T), 0, lc.stream, lc.K, lc.twf, C, Ph, part, plan)
+#define CW_ROOT_N(LG)                                 \
+    if (pairs) {                                      \
+        if (plan.lazy) CW_ROOT(LG, 1, true, true);    \
+        else CW_ROOT(LG, 1, true, false);             \
+    } else {                                          \
+        if (plan.lazy) CW_ROOT(LG, 2, false, true);   \
+        else CW_ROOT(LG, 2, false, false);            \
+    }
+    if (lc.logN == 12) {
+        CW_ROOT_N(12)
+    } else if (lc.logN == 13) {
+        CW_ROOT_N(13)
+    }
+#undef CW_ROOT_N
+#undef CW_ROOT
+}
+
+// racc_q[r][row][c] += sum over slices of part[slice][q][r][row][c] (mod the row's prime).
+__global__ void k_root_reduce(const CtxConst* __restrict__ K, const uint64_t* __restrict__ part, const RootPlan rp,
+                              const QueryPtrs qp) {
+    const uint32_t N = K->N, L = K->L;
+    const size_t per = (size_t)rp.s * rp.RR * N;  // one query's accumulators
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= per * rp.nq) return;
+    const uint32_t q = (uint32_t)(gid / per);
+    const size_t x = gid % per;
+    const uint32_t row = (uint32_t)((x / N) % rp.RR);
+    const uint32_t pi = row < 2 * L ? row % L : K->LL + (row - 2 * L) % rp.A;
+    const uint64_t p = K->p[pi];
+    uint64_t a = qp.acc[q][x];
+    for (uint32_t sl = 0; sl < rp.nslices; ++sl) a = add_mod(a, part[((size_t)sl * rp.nq + q) * per + x], p);
+    qp.acc[q][x] = a;
+}
+
+void launch_root_reduce(const Launch& lc, const uint64_t* part, const RootPlan& plan, const QueryPtrs& qp) {
+    const size_t n = (size_t)plan.nq * plan.s * plan.RR * lc.N;
+    if (!n) return;
+    hipLaunchKernelGGL(k_root_reduce, dim3(blocks_for(n)), dim3(EW_THREADS), 0, lc.stream, lc.K, part, plan, qp);
+}
+
+// Wc [s][L][2][N] -> WQ [s][L][L][N] (see launch_root_crt).
+__global__ void k_root_crt(const CtxConst* __restrict__ K, const CrtConst cc, const uint64_t* __restrict__ Wc,
+                           uint32_t s, uint64_t* __restrict__ WQ) {
+    const uint32_t N = K->N, L = K->L;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)s * L * N) return;
+    const size_t c = gid % N, ri = gid / N;  // ri = r L + i
+    const uint64_t b0 = K->p[K->LL], b1 = K->p[K->LL + 1];
+    const uint64_t w0 = Wc[(ri * 2 + 0) * N + c], w1 = Wc[(ri * 2 + 1) * N + c];
+    // t = (w1 - w0) b0^-1 mod b1; w0 < b0 < 2 b1
+    const uint64_t w0b = w0 >= b1 ? w0 - b1 : w0;
+    const uint64_t t = mul_shoup(sub_mod(w1, w0b, b1), cc.b0inv, cc.b0invq, b1);
+    // w = w0 + b0 t in [0, b0 b1); centred: subtract b0 b1 when w > (b0 b1 - 1) / 2
+    const uint64_t lo = b0 * t, hi = __umul64hi(b0, t);
+    const uint64_t wlo = lo + w0, whi = hi + (wlo < lo ? 1u : 0u);
+    const bool neg = whi > cc.half_hi || (whi == cc.half_hi && wlo > cc.half_lo);
+    uint64_t* o = WQ + ri * L * N + c;
+    for (uint32_t j = 0; j < L; ++j) {
+        const uint64_t p = K->p[j], r1 = K->r1[j];
+        uint64_t x = add_mod(reduce64(w0, p, r1), mul_shoup(reduce64(t, p, r1), cc.b0q[j], cc.b0qq[j], p), p);
+        if (neg) x = sub_mod(x, cc.Bq[j], p);
+        o[(size_t)j * N] = x;
+    }
+}
+
+void launch_root_crt(const Launch& lc, const CrtConst& cc, const uint64_t* Wc, uint32_t s, uint64_t* WQ) {
+    const size_t n = (size_t)s * lc.L * lc.N;
+    if (!n) return;
+    hipLaunchKernelGGL(k_root_crt, dim3(blocks_for(n)), dim3(EW_THREADS), 0, lc.stream, lc.K, cc, Wc, s, WQ);
+}
+
+// answer[r][poly][j][c] = racc[r][poly L + j][c] + sum_i WQ^[r][i][j][c] key[i][poly][j][c] mod q_j.
+__global__ void k_root_combine(const CtxConst* __restrict__ K, const uint64_t* __restrict__ racc,
+                               const uint64_t* __restrict__ WQ, const uint64_t* __restrict__ rlk, uint32_t s,
+                               uint32_t RR, uint64_t* __restrict__ answer) {
+    const uint32_t N = K->N, L = K->L;
+    const size_t LN = (size_t)L * N;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= (size_t)s * 2 * LN) return;
+    const size_t c = gid % N;
+    const uint32_t j = (uint32_t)((gid / N) % L);
+    const uint32_t poly = (uint32_t)((gid / LN) % 2);
+    const uint32_t r = (uint32_t)(gid / (2 * LN));
+    const uint64_t p = K->p[j], mu = K->bar_mu[j];
+    const uint32_t sb = K->bar_s[j];
+    uint64_t a = racc[((size_t)r * RR + poly * L + j) * N + c];
+    const size_t half = (size_t)L * 2 * LN;  // integer keys: companions follow the values
+    for (uint32_t i = 0; i < L; ++i) {
+        const uint64_t w = WQ[(((size_t)r * L + i) * L + j) * N + c];
+        const size_t ko = ((size_t)i * 2 + poly) * LN + (size_t)j * N + c;
+        uint64_t kv;
+        if (K->fp) {
+            kv = fp_to_residue(((const double*)rlk)[ko], K->pd[j]);
+            a = add_mod(a, mul_barrett(w, kv, p, mu, sb), p);
+        } else {
+            a = add_mod(a, mul_shoup(w, rlk[ko], rlk[half + ko], p), p);
+        }
+    }
+    answer[gid] = a;
+}
+
+void launch_root_combine(const Launch& lc, const uint64_t* racc, const uint64_t* WQ, const uint64_t* rlk, uint32_t s,
+                         uint32_t RR, uint64_t* answer) {
+    const size_t n = (size_t)s * 2 * lc.L * lc.N;
+    if (!n) return;
+    hipLaunchKernelGGL(k_root_combine, dim3(blocks_for(n)), dim3(EW_THREADS), 0, lc.stream, lc.K, racc, WQ, rlk, s, RR,
+                       answer);
+}
+
 // Static LDS of the transform kernels stays below the 160 KiB per workgroup of gfx950; nothing to
 // raise at run time.
 hipError_t kernels_init() { return hipSuccess; }
@@ -996,17 +1263,22 @@ void launch_ntt_digits(const Launch& lc, const uint64_t* c3, uint64_t* out, uint
     CW_NTT_DISPATCH(lc, k_ntt_digits, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, c3, out)
 }
 
-void launch_ntt_inv_tensor(const Launch& lc, const uint32_t* refs, const Batch& bt, uint64_t* X) {
+void launch_ntt_inv_tensor(const Launch& lc, const uint32_t* refs, const Batch& bt, uint64_t* X, size_t eq0,
+                           size_t count) {
     if (!bt.E || !bt.nq) return;
-    const size_t groups = (size_t)bt.nq * bt.E * lc.LL;
+    const size_t total = (size_t)bt.nq * bt.E;
+    if (count == 0 || eq0 + count > total) count = total - eq0;
+    const size_t groups = count * lc.LL;
     CW_NTT_DISPATCH(lc, k_ntt_inv_tensor, dim3((unsigned)xcd_grid(groups, 3)), lc.K, lc.tw, lc.twf, refs, bt, X,
-                    groups)
+                    groups, eq0)
 }
 
-void launch_ntt_payload(const Launch& lc, const uint16_t* pay, uint64_t* out, size_t rows_u16) {
+void launch_ntt_payload(const Launch& lc, const uint16_t* pay, uint64_t* out, size_t rows_u16, uint32_t nl,
+                        uint32_t dbase) {
     if (!rows_u16) return;
-    const size_t rows = rows_u16 * lc.L;
-    CW_NTT_DISPATCH(lc, k_ntt_payload, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, pay, out)
+    if (!nl) nl = lc.L;
+    const size_t rows = rows_u16 * nl;
+    CW_NTT_DISPATCH(lc, k_ntt_payload, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, pay, out, nl, dbase)
 }
 
 // ---------------------------------------------------------------------------------------------
@@ -1673,27 +1945,60 @@ void launch_fill(hipStream_t st, uint64_t* p, size_t n, uint64_t v) {
     hipLaunchKernelGGL(k_fill, dim3(blocks_for(n)), dim3(EW_THREADS), 0, st, p, n, v);
 }
 
+// Range check of `polys` polynomials [polys][L][N] (residue c of limb j must be below q_j): any
+// residue out of range sets *flag to 1 (grid-stride loop, one residue per thread and step).
+__global__ void k_check_residues(const CtxConst* __restrict__ K, const uint64_t* __restrict__ x, size_t polys,
+                                 uint32_t* __restrict__ flag) {
+    const uint32_t N = K->N, L = K->L;
+    const size_t words = polys * L * N;
+    bool bad = false;
+    for (size_t w = (size_t)blockIdx.x * blockDim.x + threadIdx.x; w < words; w += (size_t)gridDim.x * blockDim.x)
+        bad = bad || x[w] >= K->p[(w / N) % L];
+    if (bad) atomicOr(flag, 1u);
+}
+
+void launch_check_residues(const Launch& lc, const uint64_t* x, size_t polys, uint32_t* flag) {
+    if (!polys) return;
+    const size_t words = polys * lc.L * lc.N;
+    const size_t blocks = std::min<size_t>(blocks_for(words), (size_t)lc.cus * 16);
+    hipLaunchKernelGGL(k_check_residues, dim3(std::max<size_t>(1, blocks)), dim3(EW_THREADS), 0, lc.stream, lc.K, x,
+                       polys, flag);
+}
+
 // ---------------------------------------------------------------------------------------------
 // Codeword tables
 // ---------------------------------------------------------------------------------------------
-// Algorithm 3 (perfect mapping): scan m' = m-1 .. 0, take m' whenever the remaining rank r is at
-// least C(m', h); binom is the saturating table C(a, h), a < m, h <= k.
+// Algorithm 3 (perfect mapping), computed as the inverse of the colex rank that Algorithm 7 defines,
+// x = sum_h C(p_h, h) over the ascending positions p_1 < ... < p_k: for h = k, ..., 1 the position
+// p_h is the largest p below p_{h+1} (below m for h = k) with C(p, h) <= r, the remaining rank, and
+// r then drops by C(p_h, h).  Each p_h is a binary search over the saturating table C(a, h), a < m
+// (k searches of log2 m steps instead of a scan over m).  A rank outside the code leaves r > 0 and
+// marks the whole codeword 0xFFFFFFFF (rejected by the caller).
 __global__ void k_map_perfect(const uint64_t* __restrict__ ids, size_t n, uint32_t m, uint32_t k,
                               const uint64_t* __restrict__ binom, uint32_t* __restrict__ out) {
     const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= n) return;
     uint64_t r = ids[e];
-    uint32_t h = k;
     uint32_t* o = out + e * k;
-    for (int mp = (int)m - 1; mp >= 0 && h > 0; --mp) {
-        const uint64_t c = binom[(size_t)mp * (k + 1) + h];
-        if (r >= c) {
-            r -= c;
-            o[h - 1] = (uint32_t)mp;  // the h-th one from the top is the h-th smallest position
-            --h;
+    int hi = (int)m - 1;
+    bool ok = true;
+    for (uint32_t h = k; h >= 1 && ok; --h) {
+        int lo = (int)h - 1;  // C(h - 1, h) = 0 <= r: the smallest candidate always qualifies
+        ok = lo <= hi;
+        while (ok && lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (binom[(size_t)mid * (k + 1) + h] <= r)
+                lo = mid;
+            else
+                hi = mid - 1;
         }
+        if (!ok) break;
+        o[h - 1] = (uint32_t)lo;  // the h-th one from the top is the h-th smallest position
+        r -= binom[(size_t)lo * (k + 1) + h];
+        hi = lo - 1;
     }
-    for (; h > 0; --h) o[h - 1] = 0xFFFFFFFFu;  // rank outside the code (rejected by the caller)
+    if (!ok || r != 0)
+        for (uint32_t h = 0; h < k; ++h) o[h] = 0xFFFFFFFFu;
 }
 
 void launch_map_perfect(hipStream_t st, const uint64_t* ids, size_t n, uint32_t m, uint32_t k, const uint64_t* binom,
