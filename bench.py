@@ -67,12 +67,16 @@ def parse():
     ap.add_argument("--schedule", default="",
                     help="fixed schedule 'chunk,query_group,relin_group' for both loops instead of tuning")
     ap.add_argument("--chunk", type=int, default=0, help="elements per processing chunk (0: library default)")
+    ap.add_argument("--defer-relin", type=int, default=1, choices=[0, 1],
+                    help="1: relinearize root products after the inner product where the library allows it "
+                         "(pir_set_defer_relin); 0: relinearize every selector")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (reference for rocprofv3 byte counters)")
     ap.add_argument("--serve", type=int, default=-1, choices=[-1, 0, 1],
                     help="also replay the batched-serving trace (4 resident databases, Poisson arrivals)")
     ap.add_argument("--serve-queries", type=int, default=256)
-    ap.add_argument("--serve-rates", default="0.8", help="arrival rates as multiples of 1/S (S: mean plain service time)")
+    ap.add_argument("--serve-rates", default="0.8,2.0",
+                    help="arrival rates as multiples of 1/S (S: mean plain service time): below and above capacity")
     ap.add_argument("--serve-slots", type=int, default=32)
     ap.add_argument("--serve-only", action="store_true", help="skip the mid workload")
     ap.add_argument("--probe", action="store_true",
@@ -109,13 +113,19 @@ def main():
     if args.probe:
         cfg = datagen.CONFIGS[args.workload]
         ctx = Context(cfg.N, cfg.primes, cfg.t)
-        rows = []
-        for op, name in enumerate(Context.PROBE_OPS):
-            ms, wi = ctx.probe_fp64(op)
-            rate = wi / (ms * 1e-3) / (MI355X_CUS * MI355X_CLOCK_HZ)
-            log(f"probe {name}: {ms:.3f} ms, {rate:.3f} wave-instructions per CU per clock at 2.4 GHz")
-            rows.append({"op": name, "ms": ms, "wave_instructions": wi, "per_cu_per_clock": rate})
-        print(json.dumps({"probe_fp64": rows, "cus": MI355X_CUS, "clock_hz": MI355X_CLOCK_HZ}), flush=True)
+        res = {"cus": MI355X_CUS, "clock_hz": MI355X_CLOCK_HZ}
+        for key, ops, fn in (("probe_fp64", Context.PROBE_OPS, ctx.probe_fp64),
+                             ("probe_int", Context.PROBE_INT_OPS, ctx.probe_int)):
+            rows = []
+            for op, name in enumerate(ops):
+                ms, wi = fn(op)
+                rate = wi / (ms * 1e-3) / (MI355X_CUS * MI355X_CLOCK_HZ)
+                log(f"probe {name}: {ms:.3f} ms, {rate:.3f} wave-instructions per CU per clock at 2.4 GHz, "
+                    f"{wi * 64 / (ms * 1e-3) / 1e12:.1f} T lane-ops/s")
+                rows.append({"op": name, "ms": ms, "wave_instructions": wi, "per_cu_per_clock": rate,
+                             "lane_ops_per_s": wi * 64 / (ms * 1e-3)})
+            res[key] = rows
+        print(json.dumps(res), flush=True)
         return
 
     serve = args.serve == 1 or (args.serve == -1 and args.workload == "mid")
@@ -138,6 +148,7 @@ def main():
         """A context with the launch schedule for `batch` queries per call: fixed by --schedule or
         --chunk, else the package's tuning cache, else (or with --autotune 1) the autotuner."""
         c = Context(cfg.N, cfg.primes, cfg.t, chunk_elems=args.chunk)
+        c.defer_relin = bool(args.defer_relin)
         tune, source = None, "default"
         cached = c.cached_schedule(batch, cfg.k, cfg.s)
         if args.schedule:
@@ -229,10 +240,17 @@ def main():
         t_graph, per_graph, _ = timed(lambda: graph.launch(stream=stream), args.steps, args.warmup, False)
         log(f"plain, captured graph {t_graph / args.steps * 1e3:.1f} ms/query")
     log(f"batched B={B}")
-    t_b, per_b, prof = timed(step_batch, args.steps, args.warmup, not args.no_profile)
+    t_b, per_b, _ = timed(step_batch, args.steps, args.warmup, False)
     ms_step = t_b / args.steps * 1e3
     value = B * n * args.steps / t_b
     log(f"batched {ms_step:.1f} ms/step -> {value:.0f} elements/s")
+    # the roofline's per-family launch times: the same step again, with HIP events around every
+    # kernel family's launches on the launching stream (they add a little time of their own)
+    prof, prof_steps, t_bp = {}, 0, 0.0
+    if not args.no_profile:
+        prof_steps = args.steps
+        t_bp, _, prof = timed(step_batch, prof_steps, 1, True)
+        log(f"batched with kernel-family events {t_bp / prof_steps * 1e3:.1f} ms/step")
     torch.cuda.synchronize()
     extras = not args.batched_only
     if extras and not np.array_equal(out_plain.cpu().numpy(), outs[0].cpu().numpy()):
@@ -244,7 +262,9 @@ def main():
     arith = arith_bench(args, ctx, key, cfg, torch, stream) if extras and args.workload == "mid" else None
 
     fp = cfg.N <= 8192 and all(p < FP_PRIME_BOUND for p in tuple(cfg.primes) + ctx.aux_primes)
-    roof = roofline(prof, args.steps, fp, traffic_table(cfg, n, B, ctx.schedule())) if prof else None
+    roof = roofline(prof, prof_steps, fp, traffic_table(cfg, n, B, ctx.schedule())) if prof else None
+    if roof is not None:
+        roof["events_ms_per_step"] = t_bp / prof_steps * 1e3
 
     cpu = None
     sample = args.cpu_sample if args.cpu_sample >= 0 else (256 if cfg.N <= 8192 else 32)
@@ -262,6 +282,7 @@ def main():
                    "batch_queries": B},
         "schedule": {"batched": ctx.schedule(), "plain": ctx_plain.schedule(),
                      "source": {"batched": tune, "plain": tune_plain}},
+        "root_keyswitch": "deferred past the inner product" if args.defer_relin and fp else "per element",
         "plain": {"value": n * args.steps / t_plain, "unit": "elements/s", "ms_per_query": t_plain / args.steps * 1e3,
                   **lat(per_plain)} if extras else None,
         "plain_graph": {"value": n * args.steps / t_graph, "unit": "elements/s",
@@ -283,7 +304,7 @@ def main():
     print(json.dumps(out), flush=True)
 
 
-NTT_FAMILIES = ("ntt_fwd", "ntt_inv", "ntt_inv_tensor", "ntt_digits", "relin", "payload_ntt")
+NTT_FAMILIES = ("ntt_fwd", "ntt_inv", "ntt_inv_tensor", "ntt_digits", "relin", "payload_ntt", "root_pm")
 
 
 def traffic_table(cfg, n, B, schedule):
@@ -360,7 +381,39 @@ def cpu_baseline(cfg, rlk, query, codewords, payload):
             "sample": f"{len(codewords)} of {cfg.n} elements of the same workload, one query, {dt:.1f} s",
             "cpu_model": cpu_model(), "nproc": os.cpu_count(),
             "one_thread": {"value": one / dt1, "unit": "elements/s",
-                           "sample": f"{one} elements of the same workload, one query, {dt1:.1f} s"}}
+                           "sample": f"{one} elements of the same workload, one query, {dt1:.1f} s"},
+            "full_tiny": cpu_full_tiny(threads), "full_mid_recorded": full_mid_record()}
+
+
+def cpu_full_tiny(threads):
+    """The oracle's whole answer for the tiny index-PIR configuration (N = 4096, 3 primes, k = 2,
+    m = 24, n = 256), on all host threads: synthetic key and query, the configuration's database."""
+    from oracle.core import Oracle
+    from oracle.mapping import perfect_map
+    c = datagen.CONFIGS["tiny"]
+    orc = Oracle(c.N, c.primes, c.t)
+    key = orc.load_key(datagen.uniform_residues(c.primes, (c.L, 2), c.N, seed=c.seed * 100 + 1))
+    q = datagen.uniform_residues(c.primes, (c.m, 2), c.N, seed=c.seed * 100 + 10)
+    cw = np.array([perfect_map(int(x), c.m, c.k) for x in datagen.identifier_permutation(c, c.n)], dtype=np.uint32)
+    pay = datagen.payload(c, c.n)
+    log(f"cpu oracle: whole tiny answer ({c.n} elements) on {threads} threads")
+    t0 = time.perf_counter()
+    orc.answer(key, q, cw, pay, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": c.n / dt, "unit": "elements/s", "seconds": dt, "threads": threads,
+            "workload": f"tiny: N={c.N}, {c.L} primes, k={c.k}, m={c.m}, n={c.n}, one query"}
+
+
+def full_mid_record():
+    """The oracle's whole mid answer (n = 16384), as timed when the golden file was written (by
+    tests/golden/make_mid_answer.py, on the machine named in the record, not this host)."""
+    path = os.path.join(ROOT, "tests", "golden", "mid_answer.npz")
+    if not os.path.exists(path):
+        return None
+    with np.load(path, allow_pickle=False) as z:
+        secs, thr, host = float(z["oracle_seconds"]), int(z["oracle_threads"]), str(z["host"])
+    return {"value": 16384 / secs, "unit": "elements/s", "seconds": secs, "threads": thr, "host": host,
+            "where": "recorded when the golden answer was written, not measured in this run"}
 
 
 def expansion_bench(args, ctx, cfg, torch, stream):
@@ -482,10 +535,12 @@ def serve_bench(args, torch):
     in arrival order with pir_answer, and (ii) the continuous-batching server (pir_serve_*) under
     its three policies (round robin, oldest first, size aged).
 
-    Latency runs from a query's arrival (host clock; its ciphertexts are already resident) to its
-    answer being complete on the device.  Elements/s = sum of the queried databases' sizes / time
-    from the first arrival to the last completion.  The rate is a multiple of 1/S, S the plain
-    loop's mean service time over the uniform database mix, measured first.
+    Latency runs from a query's arrival (host clock) to its answer being complete on the device,
+    and includes the upload of its ciphertexts: the client's query sits in pinned host memory until
+    it arrives, and is then copied to a device buffer of its own and submitted (plain loop: copied
+    and answered).  Elements/s = sum of the queried databases' sizes / time from the first arrival
+    to the last completion.  The rate is a multiple of 1/S, S the plain loop's mean service time
+    (query resident) over the uniform database mix, measured first.
     """
     from paper_2202_07569_amd import Context, Server
     cfgs = datagen.batched_configs()
@@ -502,8 +557,9 @@ def serve_bench(args, torch):
         dbs.append(ctx.encode_db(cw.cpu().numpy(), pay, c.m))
         del pay
         pools.append([torch.from_numpy(datagen.uniform_residues(c.primes, (c.m, 2), c.N,
-                                                                seed=c.seed * 100 + 20 + i)).cuda()
+                                                                seed=c.seed * 100 + 20 + i)).pin_memory()
                       for i in range(QUERY_POOL)])
+    resident = [[q.cuda() for q in pool] for pool in pools]  # for the service-time measurement
     stream = torch.cuda.current_stream()
     Q = args.serve_queries
     seed = cfgs[0].seed
@@ -515,15 +571,16 @@ def serve_bench(args, torch):
     # S: plain service time per database (after a warm-up answer on each)
     svc = []
     for d, c in enumerate(cfgs):
-        ctx.answer(keys[0], dbs[d], pools[d][0], out=outs[0] if dbc[0] == d else ctx.empty(c.s, 2, c0.L, c0.N))
+        ctx.answer(keys[0], dbs[d], resident[d][0], out=outs[0] if dbc[0] == d else ctx.empty(c.s, 2, c0.L, c0.N))
         torch.cuda.synchronize()
         reps = []
         for r in range(3):
             a = time.perf_counter()
-            ctx.answer(keys[r % 2], dbs[d], pools[d][r % QUERY_POOL], out=ctx.empty(c.s, 2, c0.L, c0.N))
+            ctx.answer(keys[r % 2], dbs[d], resident[d][r % QUERY_POOL], out=ctx.empty(c.s, 2, c0.L, c0.N))
             torch.cuda.synchronize()
             reps.append(time.perf_counter() - a)
         svc.append(float(np.median(reps)))
+    del resident
     S = float(np.mean(svc))
     log(f"plain service times {[round(x * 1e3, 1) for x in svc]} ms, S = {S * 1e3:.1f} ms")
     # size-aged order: priority = arrival + aging * elements, aging twice the plain cost per element
@@ -538,8 +595,10 @@ def serve_bench(args, torch):
             if now < arr[i]:
                 time.sleep(arr[i] - now)
             d = dbc[i]
-            ctx.answer(keys[keyc[i]], dbs[d], pools[d][i % QUERY_POOL], out=outs[i], stream=stream)
+            q = pools[d][i % QUERY_POOL].to(ctx.device, non_blocking=True)  # the upload, on `stream`
+            ctx.answer(keys[keyc[i]], dbs[d], q, out=outs[i], stream=stream)
             stream.synchronize()
+            del q
             done = time.perf_counter() - t0
             lat[i] = done - arr[i]
         return lat, done - arr[0]
@@ -555,7 +614,8 @@ def serve_bench(args, torch):
             now = time.perf_counter() - t0
             while i < Q and arr[i] <= now:
                 d = dbc[i]
-                live[srv.submit(keys[keyc[i]], dbs[d], pools[d][i % QUERY_POOL], out=outs[i])] = i
+                q = pools[d][i % QUERY_POOL].to(ctx.device, non_blocking=True)  # upload; submit waits for it
+                live[srv.submit(keys[keyc[i]], dbs[d], q, out=outs[i])] = i
                 i += 1
             if not live:
                 time.sleep(max(0.0, arr[i] - (time.perf_counter() - t0)))
@@ -614,7 +674,7 @@ def serve_bench(args, torch):
 # --------------------------------------------------------------------------------------------
 FAMILY_OF_KERNEL = [("k_relin", "relin"), ("k_ntt_inv_tensor", "ntt_inv_tensor"), ("k_scale_fix", None),
                     ("k_scale", "scale"), ("k_accumulate", "accumulate"), ("k_ntt_payload", "payload_ntt"),
-                    ("copyBuffer", "copy")]
+                    ("k_root_pm", "root_pm"), ("k_root_reduce", "root_reduce"), ("copyBuffer", "copy")]
 
 
 def summarize_traffic(fetch_csv, write_csv, copy_mib, workload, n, batch, schedule, out_json):

@@ -269,7 +269,8 @@ static int check_launch(pir_ctx* ctx) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         ctx->poisoned = true;
-        return fail(PIR_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorString(e));
+        return fail(PIR_E_DEVICE, std::string("kernel launch failed: ") + hipGetErrorName(e) + ": " +
+                                      hipGetErrorString(e));
     }
     return PIR_OK;
 }
@@ -398,6 +399,7 @@ extern "C" int pir_setup(const pir_params* params, pir_ctx** out) {
         return rc;
     };
     if (hipSetDevice(ctx->device) != hipSuccess) return cleanup(fail(PIR_E_DEVICE, "hipSetDevice failed"));
+    (void)hipGetLastError();  // a pending error of earlier runtime calls on this thread is not ours
     if (cw::kernels_init() != hipSuccess) return cleanup(fail(PIR_E_DEVICE, "kernel attribute setup failed"));
     {
         hipDeviceProp_t prop;
@@ -479,10 +481,14 @@ extern "C" uint64_t pir_ctx_device_bytes(const pir_ctx* ctx) { return ctx ? ctx-
 
 extern "C" const char* pir_last_error(void) { return g_err.c_str(); }
 
+// Every entry point takes the context's lock and clears the thread's last HIP error: a launch of
+// this library is checked (check_launch) by the call that makes it, so a pending error at entry
+// belongs to earlier, unrelated runtime calls on this thread and must not be taken for ours.
 #define CW_ENTER(ctx)                                                               \
     if (!(ctx)) return fail(PIR_E_INVALID, "null context");                         \
     std::lock_guard<std::recursive_mutex> lock_((ctx)->mu);                         \
-    if ((ctx)->poisoned) return fail(PIR_E_DEVICE, "context poisoned by an earlier device error");
+    if ((ctx)->poisoned) return fail(PIR_E_DEVICE, "context poisoned by an earlier device error"); \
+    (void)hipGetLastError();
 
 // ------------------------------------------------------------------------------------------------
 // keys
@@ -518,10 +524,12 @@ extern "C" int pir_load_key(pir_ctx* ctx, const uint64_t* rlk, pir_key** out) {
     }
     cw::launch_ntt_operand(lc, key->d, key->d, rows, L, 0);
     if (!ctx->fp) cw::launch_shoup_companions(lc, key->d, key->d + half, rows, L);
-    if (hipDeviceSynchronize() != hipSuccess || hipGetLastError() != hipSuccess) {
+    const hipError_t es = hipDeviceSynchronize(), el = hipGetLastError();
+    if (es != hipSuccess || el != hipSuccess) {
         pir_key_free(key);
         ctx->poisoned = true;
-        return fail(PIR_E_DEVICE, "key transform failed");
+        return fail(PIR_E_DEVICE, std::string("key transform failed: ") + hipGetErrorName(es) + " / " +
+                                      hipGetErrorName(el));
     }
     *out = key;
     return PIR_OK;
@@ -1833,8 +1841,12 @@ extern "C" int pir_autotune(pir_ctx* ctx, uint32_t batch, uint32_t k, uint32_t s
     CW_HIP(ctx, hipSetDevice(ctx->device));
     const uint32_t N = ctx->N, L = ctx->L;
     const std::vector<uint64_t> q(ctx->primes.begin(), ctx->primes.begin() + L);
+    // the deferred key switch sums partial products per slice of a chunk, so fewer, longer chunks
+    // save partial-sum traffic: it also tries 1024 and 2048 elements
+    const bool can_defer = ctx->defer && ctx->crt_ok && k >= 2;
     const std::vector<uint32_t> chunks = N >= 16384 ? std::vector<uint32_t>{32, 64, 128, 256}
-                                                    : std::vector<uint32_t>{64, 128, 256, 512};
+                                         : can_defer ? std::vector<uint32_t>{64, 128, 256, 512, 1024, 2048}
+                                                     : std::vector<uint32_t>{64, 128, 256, 512};
     // synthetic database: n elements, the first n weight-k subsets of the smallest m that has them
     const uint64_t n = k == 1 ? 256 : (uint64_t)chunks.back() * 4;
     uint32_t m = k;
