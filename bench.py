@@ -32,10 +32,11 @@ import datagen  # noqa: E402
 
 MI355X_HBM_GBPS = 8000.0
 MI355X_CUS, MI355X_CLOCK_HZ = 256, 2.4e9
-# Integer ALU roof: 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz = 78.6 T lane-ops/s for
-# full-rate 32-bit operations; the 32-bit multipliers (v_mul_lo_u32, v_mul_hi_u32,
-# v_mad_u64_u32) run at half that rate, 39.3 T/s (measured 31-33 T/s with an ALU-only probe).
-MI355X_INT_MUL_PER_S = 256 * 4 * 32 * 2.4e9 / 2
+# Integer ALU roof: the 32-bit multiplies (v_mul_lo_u32, v_mul_hi_u32, v_mad_u64_u32) issue at one
+# wave-instruction (64 lanes) per CU per clock while the CUs are busy (pir_probe_int, counters
+# SQ_INSTS_VALU / SQ_BUSY_CU_CYCLES = 0.94-0.96): 256 x 64 x 2.4 GHz = 39.3 T/s (timed 32-34 T/s
+# at the lower clock of dense multiply chains).
+MI355X_INT_MUL_PER_S = 256 * 64 * 2.4e9
 MULS_PER_BUTTERFLY = 10  # 64-bit Shoup butterfly: hi64(a w') 5 mads, lo64(a w) and lo64(q p) 4 muls + 1 mul_hi
 # fp64 roof: 78.6 TFLOP/s counting an FMA as two flops = 39.3 T fp64 instructions/s.  The fp64
 # butterfly (primes below 2^50) needs 8: y*w, fma, h*(1/p), rint, fma, + l, X + T, X - T.
@@ -67,9 +68,9 @@ def parse():
     ap.add_argument("--schedule", default="",
                     help="fixed schedule 'chunk,query_group,relin_group' for both loops instead of tuning")
     ap.add_argument("--chunk", type=int, default=0, help="elements per processing chunk (0: library default)")
-    ap.add_argument("--defer-relin", type=int, default=1, choices=[0, 1],
-                    help="1: relinearize root products after the inner product where the library allows it "
-                         "(pir_set_defer_relin); 0: relinearize every selector")
+    ap.add_argument("--defer-relin", type=int, default=1, choices=[0, 1, 2],
+                    help="when root products are relinearized after the inner product (pir_set_defer_relin): "
+                         "0 never, 1 where it pays (library default), 2 wherever allowed")
     ap.add_argument("--copy-calibration-mib", type=int, default=0,
                     help="also run a plain device copy of this size (reference for rocprofv3 byte counters)")
     ap.add_argument("--serve", type=int, default=-1, choices=[-1, 0, 1],
@@ -148,7 +149,7 @@ def main():
         """A context with the launch schedule for `batch` queries per call: fixed by --schedule or
         --chunk, else the package's tuning cache, else (or with --autotune 1) the autotuner."""
         c = Context(cfg.N, cfg.primes, cfg.t, chunk_elems=args.chunk)
-        c.defer_relin = bool(args.defer_relin)
+        c.defer_relin = args.defer_relin
         tune, source = None, "default"
         cached = c.cached_schedule(batch, cfg.k, cfg.s)
         if args.schedule:
@@ -262,6 +263,7 @@ def main():
     arith = arith_bench(args, ctx, key, cfg, torch, stream) if extras and args.workload == "mid" else None
 
     fp = cfg.N <= 8192 and all(p < FP_PRIME_BOUND for p in tuple(cfg.primes) + ctx.aux_primes)
+    k_ge2 = cfg.k >= 2
     roof = roofline(prof, prof_steps, fp, traffic_table(cfg, n, B, ctx.schedule())) if prof else None
     if roof is not None:
         roof["events_ms_per_step"] = t_bp / prof_steps * 1e3
@@ -282,7 +284,8 @@ def main():
                    "batch_queries": B},
         "schedule": {"batched": ctx.schedule(), "plain": ctx_plain.schedule(),
                      "source": {"batched": tune, "plain": tune_plain}},
-        "root_keyswitch": "deferred past the inner product" if args.defer_relin and fp else "per element",
+        "root_keyswitch": ("deferred past the inner product" if fp and args.defer_relin and k_ge2 and
+                           (args.defer_relin == 2 or n * (cfg.L * cfg.L - 2 * cfg.L) >= 2048) else "per element"),
         "plain": {"value": n * args.steps / t_plain, "unit": "elements/s", "ms_per_query": t_plain / args.steps * 1e3,
                   **lat(per_plain)} if extras else None,
         "plain_graph": {"value": n * args.steps / t_graph, "unit": "elements/s",

@@ -306,13 +306,15 @@ int pir_map_lossy(pir_ctx* ctx, const uint64_t* keywords, uint64_t n, uint32_t m
  *                     buffers are released afterwards. */
 /* Where the relinearization of each element's root product happens (Section 3.3.3: the answer is
  * the inner product of the selection vector with the database, Eq. (1), and it is linear in every
- * selector).  on = 1 (the default): on the fp64 path (every prime below 2^50, N <= 8192), for trees
- * with a multiplication and databases whose digit sums fit the CRT of two auxiliary primes, the
- * root products are multiplied into the payload before relinearization, with their relinearization
- * digits summed separately, and the key multiplies those sums once per answer; elsewhere, and with
- * on = 0, every selector is relinearized.  The answers are bit-identical either way.  Changes only
- * while no database is encoded (PIR_E_INVALID otherwise).  pir_get_defer_relin returns the mode. */
-int pir_set_defer_relin(pir_ctx* ctx, int on);
+ * selector).  Deferred: on the fp64 path (every prime below 2^50, N <= 8192), for trees with a
+ * multiplication and databases whose digit sums fit the CRT of two dedicated primes, the root
+ * products are multiplied into the payload before relinearization, their relinearization digits
+ * summed separately, and the key multiplies those sums once per answer.  mode 0: never (every
+ * selector is relinearized); 1 (the default): where allowed and the database is large enough to
+ * repay the per-answer work (n (L^2 - 2L) >= 2048); 2: wherever allowed.  The answers are
+ * bit-identical in every mode.  Changes only while no database is encoded (PIR_E_INVALID
+ * otherwise).  pir_get_defer_relin returns the mode. */
+int pir_set_defer_relin(pir_ctx* ctx, int mode);
 int pir_get_defer_relin(pir_ctx* ctx);
 
 typedef struct {

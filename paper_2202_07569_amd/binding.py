@@ -252,16 +252,17 @@ class Context:
         return out.as_dict()
 
     @property
-    def defer_relin(self) -> bool:
-        """Whether root products are relinearized after the inner product (pir_set_defer_relin)."""
+    def defer_relin(self) -> int:
+        """When root products are relinearized after the inner product (pir_set_defer_relin):
+        0 never, 1 where it pays (default), 2 wherever allowed."""
         rc = lib().pir_get_defer_relin(self._h)
         if rc < 0:
             _check(rc)
-        return rc == 1
+        return rc
 
     @defer_relin.setter
-    def defer_relin(self, on: bool):
-        _check(lib().pir_set_defer_relin(self._h, 1 if on else 0))
+    def defer_relin(self, mode: int):
+        _check(lib().pir_set_defer_relin(self._h, int(mode)))
 
     def set_schedule(self, chunk_elems: int, query_group: int, relin_group: int = 0):
         x = _Schedule(chunk_elems, query_group, relin_group, 0.0)

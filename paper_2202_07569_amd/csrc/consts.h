@@ -52,8 +52,8 @@ struct CtxConst {
     double ninvd[MAX_LL], ninvdq[MAX_LL];        // N^{-1} mod p and (N^{-1} mod p)/p as doubles
     uint64_t qinv[MAX_L], qinvq[MAX_L];          // [(q/q_i)^{-1}]_{q_i}
     uint64_t delta[MAX_L];                       // Delta = floor(q/t) mod q_i
-    uint64_t tqinv[MAX_L], tqinvq[MAX_L];        // [t (q/q_i)^{-1}]_{q_i}
-    uint64_t kb1[MAX_LB], kb1q[MAX_LB];          // [t q^{-1} (B/b_j)^{-1}]_{b_j}
+    uint64_t tqinv[MAX_L], tqinvq[MAX_L];        // [t (q/q_i)^{-1} N^{-1}]_{q_i} (scale input lacks N^{-1})
+    uint64_t kb1[MAX_LB], kb1q[MAX_LB];          // [t q^{-1} (B/b_j)^{-1} N^{-1}]_{b_j} (likewise)
     uint64_t kb2[MAX_LB], kb2q[MAX_LB];          // [q^{-1} (B/b_j)^{-1}]_{b_j}
     double tqinvd[MAX_L], kb1d[MAX_LB], kb2d[MAX_LB];  // the same constants as doubles (fp64 path)
     // fp64 scale with the key constant folded into the Q -> B conversion:

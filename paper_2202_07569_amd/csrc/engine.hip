@@ -86,7 +86,7 @@ struct pir_ctx {
     std::map<std::pair<uint32_t, uint32_t>, uint64_t*> binom;  // (m, k) -> device table
     std::map<uint32_t, cw::SwitchConst*> switches;            // keep -> device switch constants
     uint32_t xslab = 0;       // element-queries per tensor + scale launch (X stays in the Infinity Cache)
-    bool defer = true;        // key switch of root products deferred past the inner product (where allowed)
+    int defer_mode = 1;       // root key switch after the inner product: 0 never, 1 where it pays, 2 where allowed
     bool crt_ok = false;      // the two primes of the deferred key switch exist (fp64 path)
     cw::CrtConst crt{};
     void* scratch = nullptr;  // this device's copy of the no-allocation scratch array (device address)
@@ -120,6 +120,7 @@ struct pir_db {
     size_t pay_bytes = 0, pairs_bytes = 0, refs_bytes = 0;
     bool live = false;           // counted in ctx->live_dbs
     bool defer_ok = false;       // the digit sums of this database fit the CRT of two auxiliary primes
+    bool defer_worth = false;    // n (L^2 - 2L) >= 2048: deferring saves more than it adds per answer
 };
 
 // ------------------------------------------------------------------------------------------------
@@ -129,7 +130,12 @@ struct pir_db {
 // deferred past the inner product"): used on the fp64 path when the database's digit sums fit the
 // CRT of two auxiliary primes, for trees with at least one multiplication.
 constexpr uint32_t ROOT_A = 2;  // auxiliary primes holding the digit sums
-static bool deferred(const pir_ctx* ctx, const pir_db* db) { return ctx->defer && db->defer_ok; }
+// Mode 2 defers wherever the bound allows; mode 1 (the default) also asks that the database be
+// large enough to repay the per-answer work (the digit sums' CRT and key products, about L^2 + 3L
+// transforms and a dozen launches) with the L^2 - 2L transforms saved per element.
+static bool deferred(const pir_ctx* ctx, const pir_db* db) {
+    return ctx->defer_mode == 2 ? db->defer_ok : ctx->defer_mode == 1 && db->defer_ok && db->defer_worth;
+}
 static uint32_t root_rows(const pir_ctx* ctx) { return 2 * ctx->L + ROOT_A * ctx->L; }  // RR
 
 static uint32_t root_units(const pir_ctx* ctx, uint32_t s) {
@@ -720,6 +726,8 @@ extern "C" int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, u
         const u128 bound = (u128)std::max<uint64_t>(n, 1) * ctx->N * maxq;  // n < 2^40, N <= 2^14, q < 2^50
         const u128 prod = (u128)ctx->primes[ctx->LL] * ctx->primes[ctx->LL + 1];
         db->defer_ok = bound < (prod >> 17) && root_units(ctx, s) <= (uint32_t)cw::ROOT_MAX_UNITS;  // 2 bound 2^16 < b0 b1
+        const uint64_t L = ctx->L;
+        db->defer_worth = L >= 3 && n * (L * L - 2 * L) >= 2048;
     }
     const size_t pay_bytes = (size_t)n * s * ctx->N * 2;
     int rc = dev_alloc(ctx, (void**)&db->dpay, pay_bytes);
@@ -851,9 +859,11 @@ static int make_leaves(pir_ctx* ctx, const Launch& lc, const uint64_t* query, ui
 // Mult of bt.E operand pairs for each query of the batch: the tensor products, inverse-transformed,
 // scaled and rounded into b.C [nq E][3][L][N] (coefficient form).
 // The tensor products go through X in slabs of at most ctx->xslab rows (element-queries), each
-// scaled into C right after it is written: X is bounded by the slab, not by the launch.
+// scaled into C right after it is written: X is bounded by the slab, not by the launch.  The slabs
+// of a launch are of equal size (to one row), so that no launch is a small tail.
 static void mult_only(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint32_t* refs, const cw::Batch& bt) {
-    const size_t rows = (size_t)bt.nq * bt.E, slab = std::max<size_t>(1, ctx->xslab);
+    const size_t rows = (size_t)bt.nq * bt.E, most = std::max<size_t>(1, ctx->xslab);
+    const size_t nslab = (rows + most - 1) / most, slab = std::max<size_t>(1, (rows + nslab - 1) / nslab);
     for (size_t eq0 = 0; eq0 < rows; eq0 += slab) {
         const size_t cnt = std::min(slab, rows - eq0);
         {
@@ -1800,18 +1810,18 @@ static int check_schedule(const pir_ctx* ctx, const pir_schedule* s) {
     return PIR_OK;
 }
 
-extern "C" int pir_set_defer_relin(pir_ctx* ctx, int on) {
+extern "C" int pir_set_defer_relin(pir_ctx* ctx, int mode) {
     CW_ENTER(ctx);
-    if (on != 0 && on != 1) return fail(PIR_E_INVALID, "on must be 0 or 1");
+    if (mode < 0 || mode > 2) return fail(PIR_E_INVALID, "mode must be 0, 1 or 2");
     if (ctx->live_dbs || ctx->live_graphs)
         return fail(PIR_E_INVALID, "the root key switch mode changes only while no database is encoded");
-    ctx->defer = on == 1;
+    ctx->defer_mode = mode;
     return PIR_OK;
 }
 
 extern "C" int pir_get_defer_relin(pir_ctx* ctx) {
     CW_ENTER(ctx);
-    return ctx->defer ? 1 : 0;
+    return ctx->defer_mode;
 }
 
 extern "C" int pir_get_schedule(pir_ctx* ctx, pir_schedule* out) {
@@ -1843,7 +1853,7 @@ extern "C" int pir_autotune(pir_ctx* ctx, uint32_t batch, uint32_t k, uint32_t s
     const std::vector<uint64_t> q(ctx->primes.begin(), ctx->primes.begin() + L);
     // the deferred key switch sums partial products per slice of a chunk, so fewer, longer chunks
     // save partial-sum traffic: it also tries 1024 and 2048 elements
-    const bool can_defer = ctx->defer && ctx->crt_ok && k >= 2;
+    const bool can_defer = ctx->defer_mode && ctx->crt_ok && k >= 2;
     const std::vector<uint32_t> chunks = N >= 16384 ? std::vector<uint32_t>{32, 64, 128, 256}
                                          : can_defer ? std::vector<uint32_t>{64, 128, 256, 512, 1024, 2048}
                                                      : std::vector<uint32_t>{64, 128, 256, 512};

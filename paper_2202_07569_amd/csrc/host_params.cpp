@@ -205,7 +205,9 @@ void build_const(CtxConst& K, uint32_t N, const std::vector<uint64_t>& q, const 
         uint64_t qhat = mw_mod(mw_prod(q, (int)i), p);
         K.qinv[i] = invmod(qhat, p);
         K.qinvq[i] = shoup(K.qinv[i], p);
-        K.tqinv[i] = mulmod(t % p, K.qinv[i], p);
+        // the scale kernels read the tensor products without the inverse transform's N^-1 (it is
+        // folded here and into kb1): tqinv = t (q/q_i)^-1 N^-1
+        K.tqinv[i] = mulmod(mulmod(t % p, K.qinv[i], p), invmod(N % p, p), p);
         K.tqinvq[i] = shoup(K.tqinv[i], p);
         K.tqinvd[i] = (double)K.tqinv[i];
     }
@@ -215,7 +217,7 @@ void build_const(CtxConst& K, uint32_t N, const std::vector<uint64_t>& q, const 
         uint64_t bhat_inv = invmod(mw_mod(mw_prod(B, (int)j), b), b);
         K.kb2[j] = mulmod(qinv_b, bhat_inv, b);
         K.kb2q[j] = shoup(K.kb2[j], b);
-        K.kb1[j] = mulmod(t % b, K.kb2[j], b);
+        K.kb1[j] = mulmod(mulmod(t % b, K.kb2[j], b), invmod(N % b, b), b);  // with N^-1, like tqinv
         K.kb1q[j] = shoup(K.kb1[j], b);
         K.kb1d[j] = (double)K.kb1[j];
         K.kb2d[j] = (double)K.kb2[j];

@@ -373,13 +373,14 @@ __device__ __forceinline__ void ntt_fwd_f(double* v, uint64_t* sm, uint32_t tid,
         for (int u = 0; u < Sh::EPT; ++u) v[u] = fred(v[u], p, pinv);
     }
 }
-template <class Sh>
+// NINV = false leaves out the factor N^-1 (the caller folds it into a later constant).
+template <class Sh, bool NINV = true>
 __device__ __forceinline__ void ntt_inv_f(double* v, uint64_t* sm, uint32_t tid, TwRow tw, const CtxConst* K,
                                           uint32_t pi) {
     inv_passes<Sh, true, Sh::NP - 1>(v, sm, tid, tw, K, pi);
     const double p = K->pd[pi], pinv = K->pinv[pi], ni = K->ninvd[pi];
 #pragma unroll
-    for (int u = 0; u < Sh::EPT; ++u) v[u] = fred(fmulmod(v[u], ni, p, pinv), p, pinv);
+    for (int u = 0; u < Sh::EPT; ++u) v[u] = NINV ? fred(fmulmod(v[u], ni, p, pinv), p, pinv) : fred(v[u], p, pinv);
 }
 
 // Forward transform of the EPT values a[] (residues in [0, p), first-pass pattern) of thread tid;
@@ -409,14 +410,14 @@ __device__ __forceinline__ void ntt_fwd_regs(uint64_t* a, uint64_t* sm, uint32_t
 
 // Inverse transform (including N^-1) of a[] (transformed layout); returns residues in [0, p) in
 // the first pass's natural-order pattern.
-template <class Sh, bool FP>
+template <class Sh, bool FP, bool NINV = true>
 __device__ __forceinline__ void ntt_inv_regs(uint64_t* a, uint64_t* sm, uint32_t tid, TwRow tw, const CtxConst* K,
                                              uint32_t pi) {
     if constexpr (FP) {
         double v[Sh::EPT];
 #pragma unroll
         for (int u = 0; u < Sh::EPT; ++u) v[u] = u52_to_double(a[u]);
-        ntt_inv_f<Sh>(v, sm, tid, tw, K, pi);
+        ntt_inv_f<Sh, NINV>(v, sm, tid, tw, K, pi);
         const double p = K->pd[pi];
 #pragma unroll
         for (int u = 0; u < Sh::EPT; ++u) a[u] = fp_to_residue(v[u], p);
@@ -425,8 +426,13 @@ __device__ __forceinline__ void ntt_inv_regs(uint64_t* a, uint64_t* sm, uint32_t
         const uint64_t p = K->p[pi], ni = K->ninv[pi], niq = K->ninvq[pi];
 #pragma unroll
         for (int u = 0; u < Sh::EPT; ++u) {
-            const uint64_t x = mul_shoup_lazy(a[u], ni, niq, p);
-            a[u] = x >= p ? x - p : x;
+            if constexpr (NINV) {
+                const uint64_t x = mul_shoup_lazy(a[u], ni, niq, p);
+                a[u] = x >= p ? x - p : x;
+            } else {  // inverse outputs lie in [0, 2p)
+                const uint64_t x = a[u];
+                a[u] = x >= p ? x - p : x;
+            }
         }
     }
 }
@@ -723,17 +729,19 @@ __global__ __launch_bounds__(Sh::T, Sh::LOGN == 13 ? 8 : 1) void k_ntt_inv_tenso
     const RowsTensor<Sh> row{refs, bt.leaves[q], bt.nodes[q], X, K, LL, (size_t)q * bt.E, eq0 * 3 * LL};
     const uint32_t tid = threadIdx.x;
     const uint32_t pi = row.prime(g);
+    // X leaves without the transform's factor N^-1: the scale kernels, its only readers, take it
+    // with their first constants (tqinv, kb1)
     if constexpr (FP) {
         double v[Sh::EPT];
         row.load_f(g, tid, v);
-        ntt_inv_f<Sh>(v, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
+        ntt_inv_f<Sh, false>(v, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
         const double p = K->pd[pi];
 #pragma unroll
         for (int u = 0; u < Sh::EPT; ++u) row.store(g, tid, u, fp_to_residue(v[u], p));
     } else {
         uint64_t a[Sh::EPT];
         row.load(g, tid, a);
-        ntt_inv_regs<Sh, FP>(a, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
+        ntt_inv_regs<Sh, FP, false>(a, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
 #pragma unroll
         for (int u = 0; u < Sh::EPT; ++u) row.store(g, tid, u, a[u]);
     }

@@ -65,6 +65,7 @@ def world():
     qbig = big.query
     # reference context without a budget: single answers, and the sizes the budgets are set from
     ref = Context(TINY.N, TINY.primes, TINY.t, chunk_elems=CHUNK)
+    ref.defer_relin = 2  # the slot layout of large databases (deferred key switch) on these small ones
     rk_s, rk_b = ref.load_key(small.rlk), ref.load_key(big.rlk)
     rd_s = ref.encode_db(small.codewords, small.payload, SMALL.m)
     rd_b = ref.encode_db(big.codewords, big.payload, BIG.m)
@@ -91,6 +92,7 @@ def _budgeted(w, extra):
     from paper_2202_07569_amd import Context, Server
     budget = w["base"] + extra
     ctx = Context(TINY.N, TINY.primes, TINY.t, hbm_budget_bytes=budget, chunk_elems=CHUNK)
+    ctx.defer_relin = 2
     small, big = w["small"], w["big"]
     ks, kb = ctx.load_key(small.rlk), ctx.load_key(big.rlk)
     ds = ctx.encode_db(small.codewords, small.payload, SMALL.m)

@@ -2,7 +2,8 @@
 
 The answer (Eq. (1), Section 3.3.3) is linear in every selector, so the library may multiply each
 element's root product into its payload before relinearizing and relinearize the digit sums once
-per answer (pir_set_defer_relin).  The answers must be bit-identical to relinearizing every selector
+per answer (pir_set_defer_relin; mode 2 forces it on these small databases, which the default mode
+leaves per element).  The answers must be bit-identical to relinearizing every selector
 and to the oracle's, for every shape the deferred path takes: k = 2 and k = 4 trees, one, two,
 three and four plaintexts per element (row pairs for s = 1, single rows with payload pairs above),
 ragged chunks, several queries per launch, and the tiny, mid and wide prime sets.
@@ -43,7 +44,7 @@ def _diff(got, want):
 def _answers(cfg, ins, defer, queries, chunk, qg=8):
     from paper_2202_07569_amd import Context
     ctx = Context(cfg.N, cfg.primes, cfg.t, chunk_elems=chunk)
-    ctx.defer_relin = defer
+    ctx.defer_relin = 2 if defer else 0  # 2: deferred wherever allowed, whatever the database size
     ctx.set_schedule(chunk, min(qg, len(queries)), 0)
     key = ctx.load_key(ins.rlk)
     db = ctx.encode_db(ins.codewords, ins.payload, cfg.m)
@@ -105,12 +106,14 @@ def test_mode_switch_rules():
     cfg = datagen.CONFIGS["tiny"].with_n(8)
     ins = cached_instance(cfg)
     ctx = Context(cfg.N, cfg.primes, cfg.t)
-    assert ctx.defer_relin
-    ctx.defer_relin = False
-    assert not ctx.defer_relin
+    assert ctx.defer_relin == 1  # default: where it pays
+    ctx.defer_relin = 0
+    assert ctx.defer_relin == 0
     db = ctx.encode_db(ins.codewords, ins.payload, cfg.m)
     with pytest.raises(PirError):
-        ctx.defer_relin = True
+        ctx.defer_relin = 2
     db.close()
-    ctx.defer_relin = True
-    assert ctx.defer_relin
+    ctx.defer_relin = 2
+    assert ctx.defer_relin == 2
+    with pytest.raises(PirError):
+        ctx.defer_relin = 3
