@@ -66,7 +66,7 @@ def parse():
                          "-1: use the package's tuning cache when it has the workload, else tune")
     ap.add_argument("--record-schedule", default="", help="write tuned schedules into this cache file")
     ap.add_argument("--schedule", default="",
-                    help="fixed schedule 'chunk,query_group,relin_group' for both loops instead of tuning")
+                    help="fixed schedule 'chunk,query_group,relin_group[,ntt_shape]' for both loops instead of tuning")
     ap.add_argument("--chunk", type=int, default=0, help="elements per processing chunk (0: library default)")
     ap.add_argument("--defer-relin", type=int, default=1, choices=[0, 1, 2],
                     help="when root products are relinearized after the inner product (pir_set_defer_relin): "
@@ -153,13 +153,14 @@ def main():
         tune, source = None, "default"
         cached = c.cached_schedule(batch, cfg.k, cfg.s)
         if args.schedule:
-            ch, qg, rg = (int(x) for x in args.schedule.split(","))
-            c.set_schedule(ch, min(qg, batch), rg)
+            ch, qg, rg, *sh = (int(x) for x in args.schedule.split(","))
+            c.set_schedule(ch, min(qg, batch), rg, sh[0] if sh else 0)
             source = "--schedule"
         elif args.chunk:
             source = "--chunk"
         elif cached is not None and args.autotune != 1:
-            c.set_schedule(cached["chunk_elems"], cached["query_group"], cached["relin_group"])
+            c.set_schedule(cached["chunk_elems"], cached["query_group"], cached["relin_group"],
+                           cached.get("ntt_shape", 0))
             source = "tuning cache"
         elif args.autotune != 0:
             tune = c.autotune(batch=batch, k=cfg.k, s=cfg.s)
@@ -169,7 +170,7 @@ def main():
                 from paper_2202_07569_amd.binding import record_schedule
                 b = tune["best"]
                 record_schedule(cfg.N, cfg.primes, batch, cfg.k, cfg.s,
-                                {k: b[k] for k in ("chunk_elems", "query_group", "relin_group")},
+                                {k: b[k] for k in ("chunk_elems", "query_group", "relin_group", "ntt_shape")},
                                 f"pir_autotune on MI355X, {b['ns_per_elem']:.0f} ns per element-query",
                                 path=args.record_schedule)
         log(f"schedule batch={batch} ({source}): {c.schedule()}")
@@ -321,9 +322,10 @@ def traffic_table(cfg, n, B, schedule):
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         h.update(open(f, "rb").read())
-    sched = {k: schedule[k] for k in ("chunk_elems", "query_group", "relin_group")}
+    sched = {k: schedule.get(k, 0) for k in ("chunk_elems", "query_group", "relin_group", "ntt_shape")}
+    taken = {**{"ntt_shape": 0}, **data.get("schedule", {})}
     if (data.get("kernel_source_sha256") != h.hexdigest() or data.get("workload") != cfg.name
-            or data.get("n") != n or data.get("batch") != B or data.get("schedule") != sched):
+            or data.get("n") != n or data.get("batch") != B or taken != sched):
         return None
     return dict(data["families"])
 
@@ -743,10 +745,11 @@ def summarize_traffic(fetch_csv, write_csv, copy_mib, workload, n, batch, schedu
 
 if __name__ == "__main__":
     if len(sys.argv) > 1 and sys.argv[1] == "--summarize-traffic":
-        # bench.py --summarize-traffic FETCH_CSV WRITE_CSV COPY_MIB WORKLOAD N BATCH CHUNK,QG,RG OUT_JSON
+        # bench.py --summarize-traffic FETCH_CSV WRITE_CSV COPY_MIB WORKLOAD N BATCH CHUNK,QG,RG[,SHAPE] OUT_JSON
         a = sys.argv[2:]
-        ch, qg, rg = (int(x) for x in a[6].split(","))
+        ch, qg, rg, *sh = (int(x) for x in a[6].split(","))
         summarize_traffic(a[0], a[1], int(a[2]), a[3], int(a[4]), int(a[5]),
-                          {"chunk_elems": ch, "query_group": qg, "relin_group": rg}, a[7])
+                          {"chunk_elems": ch, "query_group": qg, "relin_group": rg, "ntt_shape": sh[0] if sh else 0},
+                          a[7])
     else:
         main()

@@ -291,6 +291,10 @@ int pir_map_lossy(pir_ctx* ctx, const uint64_t* keywords, uint64_t n, uint32_t m
  *                side by side on one XCD (they read the same digit rows); G > 0 = blocks of G
  *                elements, limb-major inside a block (workgroups running together read the same
  *                key limb).  N = 16384 stages its key switch and ignores it.
+ *   ntt_shape    transform shape variant, below pir_ntt_shape_count: how the stages of every
+ *                transform are grouped into passes between LDS exchanges.  All variants of a
+ *                ring degree leave the same transformed layout, so the choice never changes a
+ *                result.
  *   ns_per_elem  measured time per element and query (output of the tuner; ignored on input)
  * The schedule is per context and can change only while no database is encoded (PIR_E_INVALID
  * otherwise).
@@ -299,7 +303,8 @@ int pir_map_lossy(pir_ctx* ctx, const uint64_t* keywords, uint64_t n, uint32_t m
  *   pir_autotune      time candidate schedules for `batch` queries per call on one database of
  *                     weight-k codewords and s plaintexts per element, on synthetic inputs of the
  *                     context's parameters (a grid over chunk and query group, then the
- *                     key-switch order at the best pair); apply the fastest and write it to *best (may be NULL).
+ *                     key-switch order at the best pair, then the transform shape at the best
+ *                     schedule); apply the fastest and write it to *best (may be NULL).
  *                     records[0..max_records) receive the measured candidates in order (may be
  *                     NULL).  Candidates that do not fit the HBM budget are skipped.  Returns the
  *                     number of candidates measured, or an error.  Synchronous; the library's work
@@ -321,6 +326,7 @@ typedef struct {
     uint32_t chunk_elems;
     uint32_t query_group;
     uint32_t relin_group;
+    uint32_t ntt_shape;
     double ns_per_elem;
 } pir_schedule;
 int pir_get_schedule(pir_ctx* ctx, pir_schedule* out);
@@ -332,6 +338,12 @@ int pir_autotune(pir_ctx* ctx, uint32_t batch, uint32_t k, uint32_t s, pir_sched
 uint32_t pir_ctx_aux_primes(const pir_ctx* ctx, uint64_t* out_primes /* may be NULL */);
 uint64_t pir_ctx_device_bytes(const pir_ctx* ctx);       /* bytes the library holds on the device */
 uint64_t pir_db_pair_count(const pir_db* db);            /* distinct inner tree nodes (k >= 3)    */
+/* Transform shape variants of the context's ring degree (pir_schedule.ntt_shape), and the number
+ * of stages of each pass of variant `shape` in order (stages: room for 8; returns the number of
+ * passes, 0 for an unknown variant or a null argument).  Each pass runs its stages in registers;
+ * consecutive passes exchange through LDS. */
+uint32_t pir_ntt_shape_count(const pir_ctx* ctx);
+uint32_t pir_ntt_shape_stages(const pir_ctx* ctx, uint32_t shape, uint32_t* stages);
 
 /* Kernel timing with HIP events on the launching stream.  When enabled, every kernel family's
  * launch is bracketed by events; pir_profile_read synchronises on them and returns, per family,

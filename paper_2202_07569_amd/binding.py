@@ -25,7 +25,7 @@ EXPORTS = [
     "pir_graph_launch", "pir_graph_free", "pir_load_galois_key", "pir_expand", "pir_mod_switch",
     "pir_folklore_leaves", "pir_arith_equality", "pir_serve_set_policy", "pir_seeded_query",
     "pir_serve_set_aging", "pir_probe_fp64", "pir_mod_switch_noalloc", "pir_check_query", "pir_probe_int",
-    "pir_set_defer_relin", "pir_get_defer_relin",
+    "pir_set_defer_relin", "pir_get_defer_relin", "pir_ntt_shape_count", "pir_ntt_shape_stages",
 ]
 
 
@@ -43,11 +43,11 @@ class _Params(ctypes.Structure):
 
 class _Schedule(ctypes.Structure):
     _fields_ = [("chunk_elems", ctypes.c_uint32), ("query_group", ctypes.c_uint32), ("relin_group", ctypes.c_uint32),
-                ("ns_per_elem", ctypes.c_double)]
+                ("ntt_shape", ctypes.c_uint32), ("ns_per_elem", ctypes.c_double)]
 
     def as_dict(self) -> dict:
         return {"chunk_elems": self.chunk_elems, "query_group": self.query_group, "relin_group": self.relin_group,
-                "ns_per_elem": self.ns_per_elem}
+                "ntt_shape": self.ntt_shape, "ns_per_elem": self.ns_per_elem}
 
 
 _lib = None
@@ -81,6 +81,8 @@ def lib():
             "pir_ctx_aux_primes": (u32, [vp, vp]),
             "pir_ctx_device_bytes": (u64, [vp]),
             "pir_db_pair_count": (u64, [vp]),
+            "pir_ntt_shape_count": (u32, [vp]),
+            "pir_ntt_shape_stages": (u32, [vp, u32, ctypes.POINTER(ctypes.c_uint32)]),
             "pir_profile_enable": (i32, [vp, i32]),
             "pir_profile_read": (i32, [vp, u32, ctypes.POINTER(ctypes.c_char_p), ctypes.POINTER(ctypes.c_double),
                                        ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_double), i32]),
@@ -264,9 +266,19 @@ class Context:
     def defer_relin(self, mode: int):
         _check(lib().pir_set_defer_relin(self._h, int(mode)))
 
-    def set_schedule(self, chunk_elems: int, query_group: int, relin_group: int = 0):
-        x = _Schedule(chunk_elems, query_group, relin_group, 0.0)
+    def set_schedule(self, chunk_elems: int, query_group: int, relin_group: int = 0, ntt_shape: int = 0):
+        x = _Schedule(chunk_elems, query_group, relin_group, ntt_shape, 0.0)
         _check(lib().pir_set_schedule(self._h, ctypes.byref(x)))
+
+    def ntt_shapes(self) -> list:
+        """Stage counts of the passes of every transform shape variant of this ring degree
+        (pir_ntt_shape_count / pir_ntt_shape_stages)."""
+        out = []
+        for v in range(lib().pir_ntt_shape_count(self._h)):
+            st = (ctypes.c_uint32 * 8)()
+            npass = lib().pir_ntt_shape_stages(self._h, v, st)
+            out.append([int(st[i]) for i in range(npass)])
+        return out
 
     def autotune(self, batch: int = 8, k: int = 4, s: int = 1) -> dict:
         """Time candidate launch schedules on synthetic inputs and apply the fastest (before any

@@ -70,6 +70,7 @@ struct pir_ctx {
     uint32_t chunk = 0;  // elements per chunk
     uint32_t qb = cw::MAX_QB;     // queries per selector launch
     uint32_t relin_group = 0;     // key-switch workgroup order (Launch::relin_group)
+    uint32_t shape = 0;           // transform shape variant (Launch::shape)
     uint32_t live_dbs = 0;        // encoded databases not yet freed
     uint32_t live_graphs = 0;     // captured answers not yet freed
     uint32_t cus = 0;    // compute units
@@ -245,6 +246,7 @@ static Launch make_launch(pir_ctx* ctx, hipStream_t st) {
     lc.LL = ctx->LL;
     lc.cus = ctx->cus;
     lc.relin_group = ctx->relin_group;
+    lc.shape = ctx->shape;
     lc.fix = ctx->dfix;
     lc.fixcnt = ctx->dfixcnt;
     return lc;
@@ -484,6 +486,13 @@ extern "C" uint32_t pir_ctx_aux_primes(const pir_ctx* ctx, uint64_t* out) {
 }
 
 extern "C" uint64_t pir_ctx_device_bytes(const pir_ctx* ctx) { return ctx ? ctx->held : 0; }
+
+extern "C" uint32_t pir_ntt_shape_count(const pir_ctx* ctx) { return ctx ? cw::ntt_shape_count(ctx->logN) : 0; }
+
+extern "C" uint32_t pir_ntt_shape_stages(const pir_ctx* ctx, uint32_t shape, uint32_t* stages) {
+    if (!ctx || !stages || shape >= cw::ntt_shape_count(ctx->logN)) return 0;
+    return cw::ntt_shape_stages(ctx->logN, shape, stages);
+}
 
 extern "C" const char* pir_last_error(void) { return g_err.c_str(); }
 
@@ -1784,6 +1793,7 @@ static void schedule_of(const pir_ctx* ctx, pir_schedule* s, double ns) {
     s->chunk_elems = ctx->chunk;
     s->query_group = ctx->qb;
     s->relin_group = ctx->relin_group;
+    s->ntt_shape = ctx->shape;
     s->ns_per_elem = ns;
 }
 
@@ -1805,6 +1815,8 @@ static int check_schedule(const pir_ctx* ctx, const pir_schedule* s) {
     if (s->query_group < 1 || s->query_group > (uint32_t)cw::MAX_QB)
         return fail(PIR_E_INVALID, "query_group must be in [1, 8]");
     if (s->relin_group > 4096) return fail(PIR_E_INVALID, "relin_group must be <= 4096");
+    if (s->ntt_shape >= cw::ntt_shape_count(ctx->logN))
+        return fail(PIR_E_INVALID, "ntt_shape must be below pir_ntt_shape_count");
     if (ctx->live_dbs || ctx->live_graphs)
         return fail(PIR_E_INVALID, "the schedule is fixed once a database is encoded");
     return PIR_OK;
@@ -1838,6 +1850,7 @@ extern "C" int pir_set_schedule(pir_ctx* ctx, const pir_schedule* s) {
     ctx->chunk = s->chunk_elems;
     ctx->qb = s->query_group;
     ctx->relin_group = s->relin_group;
+    ctx->shape = s->ntt_shape;
     return ensure_fix(ctx);
 }
 
@@ -1906,9 +1919,9 @@ extern "C" int pir_autotune(pir_ctx* ctx, uint32_t batch, uint32_t k, uint32_t s
         qs[b] = dq + b * qw;
         as[b] = da + b * aw;
     }
-    const pir_schedule start{ctx->chunk, ctx->qb, ctx->relin_group, 0.0};
-    pir_schedule cur{ctx->chunk, 1, 0, 0.0};
-    pir_schedule top{0, 0, 0, 0.0};
+    const pir_schedule start{ctx->chunk, ctx->qb, ctx->relin_group, ctx->shape, 0.0};
+    pir_schedule cur{ctx->chunk, 1, 0, ctx->shape, 0.0};
+    pir_schedule top{0, 0, 0, 0, 0.0};
     uint32_t nrec = 0;
     pir_db* db = nullptr;
     uint32_t db_chunk = 0;
@@ -1917,6 +1930,7 @@ extern "C" int pir_autotune(pir_ctx* ctx, uint32_t batch, uint32_t k, uint32_t s
         ctx->chunk = x.chunk_elems;
         ctx->qb = x.query_group;
         ctx->relin_group = x.relin_group;
+        ctx->shape = x.ntt_shape;
         CW_TRY(ensure_fix(ctx));
         if (!db || db_chunk != x.chunk_elems) {  // the element plan depends on the chunk
             if (db) pir_db_free(db);
@@ -1973,6 +1987,16 @@ extern "C" int pir_autotune(pir_ctx* ctx, uint32_t batch, uint32_t k, uint32_t s
             if ((rc = consider(cur)) != PIR_OK) break;
         }
     }
+    // then the transform shape at the best schedule so far (the incumbent has the starting shape)
+    if (rc == PIR_OK && top.chunk_elems) {
+        cur = top;
+        const uint32_t incumbent = top.ntt_shape;
+        for (uint32_t v = 0; v < cw::ntt_shape_count(ctx->logN); ++v) {
+            if (v == incumbent) continue;
+            cur.ntt_shape = v;
+            if ((rc = consider(cur)) != PIR_OK) break;
+        }
+    }
     if (st) (void)hipStreamSynchronize(st);
     if (db) pir_db_free(db);
     pir_key_free(key);
@@ -1987,6 +2011,7 @@ extern "C" int pir_autotune(pir_ctx* ctx, uint32_t batch, uint32_t k, uint32_t s
     ctx->chunk = use.chunk_elems;
     ctx->qb = use.query_group;
     ctx->relin_group = use.relin_group;
+    ctx->shape = use.ntt_shape;
     if (rc != PIR_OK) return rc;
     if (!top.chunk_elems) return fail(PIR_E_NOMEM, "no candidate schedule fits the HBM budget");
     CW_TRY(ensure_fix(ctx));

@@ -42,6 +42,7 @@ struct Launch {
     uint32_t cus;         // compute units of the device
     uint32_t relin_group; // key-switch workgroup order: 0 = the L limbs of an element side by side on
                           // one XCD; G > 0 = blocks of G elements, limb-major inside a block
+    uint32_t shape;       // transform shape variant of this degree (< ntt_shape_count(logN))
     uint64_t* fix;        // fixup list for ambiguous conversions (capacity >= coefficients per launch)
     uint32_t* fixcnt;     // its counter; zero between launches
 };
@@ -62,6 +63,10 @@ struct RootPlan {  // passed by value
     RootUnit u[ROOT_MAX_UNITS];
 };
 hipError_t kernels_init();
+// Transform shape variants of degree 2^logN (all leave the same transformed layout), and the stage
+// counts of variant v's passes in order (returns the number of passes; stages holds up to 8).
+uint32_t ntt_shape_count(uint32_t logN);
+uint32_t ntt_shape_stages(uint32_t logN, uint32_t v, uint32_t* stages);
 void launch_ntt(const Launch& lc, bool inverse, const uint64_t* in, uint64_t* out, size_t rows, uint32_t nl,
                 uint32_t pbase);
 // Forward transform of coefficient-form rows (u64 in [0, p)) into the operand format (in place

@@ -57,24 +57,77 @@ struct Shape {
     static_assert(R0 + R1 + R2 + R3 + R4 == LOGN, "passes must cover every stage");
 };
 
-// The one shape per ring degree used by every kernel that writes or reads the transformed layout:
-// that layout (position u*T + tid) depends on R and the last pass, so all of them must agree.
-// Eight elements per thread leave room for the key-switching accumulators (k_relin); the shape
-// sweep measured them within 3% of the fastest plain transform shapes.
-template <int LOGN>
-struct DefaultShape;
+// The shapes per ring degree that the kernels may use.  Every kernel that writes or reads the
+// transformed layout must agree on that layout (position u*T + tid holds natural index
+// elem_index<Sh, NP-1>(tid, u)), which depends only on R and on the last pass: the stages run in
+// the same order whatever their grouping, so the array they leave is the same.  The variants of
+// one degree therefore share R and the last pass and differ in how the middle stages are grouped
+// into passes (which exchanges stay inside a wavefront, how many stages share the registers
+// between two exchanges); the autotuner picks one per context.  Eight elements per thread leave
+// room for the key-switching accumulators (k_relin).
+template <int LOGN, int V>
+struct ShapeVar;
 template <>
-struct DefaultShape<12> {
+struct ShapeVar<12, 0> {
     using type = Shape<12, 3, 4, 3, 3, 3, 3>;
 };
 template <>
-struct DefaultShape<13> {
+struct ShapeVar<13, 0> {
     using type = Shape<13, 3, 5, 3, 3, 3, 2, 2>;
 };
 template <>
-struct DefaultShape<14> {
+struct ShapeVar<13, 1> {
+    using type = Shape<13, 3, 5, 3, 3, 2, 3, 2>;
+};
+template <>
+struct ShapeVar<13, 2> {
+    using type = Shape<13, 3, 5, 3, 2, 3, 3, 2>;
+};
+template <>
+struct ShapeVar<14, 0> {
     using type = Shape<14, 4, 4, 4, 4, 3, 3>;
 };
+template <>
+struct ShapeVar<14, 1> {
+    using type = Shape<14, 4, 4, 4, 3, 4, 3>;
+};
+__host__ __device__ constexpr uint32_t shape_key(uint32_t logN, uint32_t v) { return logN * 4 + v; }
+
+// Calls f(Sh{}) with the shape variant v of degree 2^logN (nothing for an unknown pair; the host
+// checks the variant against ntt_shape_count first).
+template <class F>
+void with_shape(uint32_t logN, uint32_t v, F&& f) {
+    switch (shape_key(logN, v)) {
+        case shape_key(12, 0): f(ShapeVar<12, 0>::type{}); break;
+        case shape_key(13, 0): f(ShapeVar<13, 0>::type{}); break;
+        case shape_key(13, 1): f(ShapeVar<13, 1>::type{}); break;
+        case shape_key(13, 2): f(ShapeVar<13, 2>::type{}); break;
+        case shape_key(14, 0): f(ShapeVar<14, 0>::type{}); break;
+        case shape_key(14, 1): f(ShapeVar<14, 1>::type{}); break;
+        default: break;
+    }
+}
+
+uint32_t ntt_shape_count(uint32_t logN) { return logN == 13 ? 3 : logN == 14 ? 2 : logN == 12 ? 1 : 0; }
+
+uint32_t ntt_shape_stages(uint32_t logN, uint32_t v, uint32_t* stages) {
+    uint32_t np = 0;
+    with_shape(logN, v, [&](auto tag) {
+        using Sh = decltype(tag);
+        np = Sh::NP;
+        for (int q = 0; q < Sh::NP; ++q) stages[q] = (uint32_t)Sh::r(q);
+    });
+    return np;
+}
+
+template <class A, class B>
+constexpr bool same_layout() {
+    return A::LOGN == B::LOGN && A::R == B::R && A::r(A::NP - 1) == B::r(B::NP - 1);
+}
+static_assert(same_layout<ShapeVar<13, 0>::type, ShapeVar<13, 1>::type>() &&
+                  same_layout<ShapeVar<13, 0>::type, ShapeVar<13, 2>::type>() &&
+                  same_layout<ShapeVar<14, 0>::type, ShapeVar<14, 1>::type>(),
+              "shape variants of one degree must leave the same transformed layout");
 
 template <class Sh, int P>
 struct PassGeo {
@@ -923,31 +976,27 @@ __global__ __launch_bounds__(Sh::T) void k_relin_f(const CtxConst* __restrict__ 
 void launch_relin(const Launch& lc, const uint64_t* c3, const Batch& bt, uint64_t* staging) {
     if (!bt.E || !bt.nq) return;
     const unsigned blocks = (unsigned)relin_grid((size_t)bt.nq * bt.E, lc.L, lc.relin_group);
-#define CW_RELIN(LG)                                                                                      \
-    {                                                                                                     \
-        using Sh = DefaultShape<LG>::type;                                                                \
-        const uint32_t G = lc.relin_group;                                                                \
-        if (lc.fp && lc.q_lazy)                                                                           \
-            hipLaunchKernelGGL((k_relin_f<Sh, true>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.twf, \
-                               c3, bt, G);                                                                \
-        else if (lc.fp)                                                                                   \
-            hipLaunchKernelGGL((k_relin_f<Sh, false>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K,       \
-                               lc.twf, c3, bt, G);                                                        \
-        else                                                                                              \
-            hipLaunchKernelGGL((k_relin<Sh>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, lc.twf, \
-                               c3, bt, G);                                                                \
+    const uint32_t G = lc.relin_group;
+    if (relin_needs_staging(lc.logN)) {
+        launch_ntt_digits(lc, c3, staging, bt.nq * bt.E);
+        launch_relin_mac(lc, staging, bt);
+        return;
     }
-    switch (lc.logN) {
-        case 12: CW_RELIN(12) break;
-        case 13: CW_RELIN(13) break;
-        case 14:
-            launch_ntt_digits(lc, c3, staging, bt.nq * bt.E);
-            launch_relin_mac(lc, staging, bt);
-            break;
-    }
+    with_shape(lc.logN, lc.shape, [&](auto tag) {
+        using Sh = decltype(tag);
+        if constexpr (Sh::LOGN <= 13) {
+            if (lc.fp && lc.q_lazy)
+                hipLaunchKernelGGL((k_relin_f<Sh, true>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.twf, c3,
+                                   bt, G);
+            else if (lc.fp)
+                hipLaunchKernelGGL((k_relin_f<Sh, false>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.twf, c3,
+                                   bt, G);
+            else
+                hipLaunchKernelGGL((k_relin<Sh>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, lc.twf, c3,
+                                   bt, G);
+        }
+    });
 }
-
-#undef CW_RELIN
 
 bool relin_needs_staging(uint32_t logN) { return logN >= 14; }
 
@@ -1028,6 +1077,19 @@ __global__ __launch_bounds__(Sh::T) void k_root_pm_f(const CtxConst* __restrict_
 #pragma unroll
         for (int u = 0; u < EPT; ++u) nx[u] = src[elem_index<Sh, 0>(tid, u)];
     }
+    // One payload row per element (S = 1, every unit has nr = 1 and r0 = 0): the row of the next
+    // element is loaded once its predecessor's last product is taken, so that it arrives during the
+    // next transform instead of after it.
+    constexpr bool PF = S == 1;
+    auto prow_of = [&](uint32_t e) {
+        return Ph + ((size_t)e * rp.s + un.r0) * rp.LP * N + (size_t)un.prow * N;
+    };
+    uint64_t pw[PF ? EPT : 1];
+    if constexpr (PF) {
+        const uint64_t* s0 = prow_of(e0) + tid;
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) pw[u] = s0[(size_t)u * T];
+    }
     __syncthreads();  // twiddles staged
     for (uint32_t i = 0; i < steps; ++i) {
         uint32_t t = tid;
@@ -1047,9 +1109,26 @@ __global__ __launch_bounds__(Sh::T) void k_root_pm_f(const CtxConst* __restrict_
         }
         ntt_fwd_f<Sh, LAZY, true, !LAZY>(v, sm, t, TwRow{nullptr, twl}, K, pr);
         asm volatile("" ::: "memory");  // keep the payload loads below the transform
-        const uint64_t* ph = Ph + ((size_t)e * rp.s + un.r0) * rp.LP * N + (size_t)un.prow * N;
+        if constexpr (PF) {
 #pragma unroll
-        for (int r = 0; r < S; ++r) {
+            for (int u = 0; u < EPT; ++u) {
+                const double w = u52_to_double(pw[u]);
+                if constexpr (TWO) {
+                    if (k) acc1[0][u] += fmulmod(v[u], w, p, pinv);
+                    else acc0[0][u] += fmulmod(v[u], w, p, pinv);
+                } else {
+                    acc0[0][u] += fmulmod(v[u], w, p, pinv);
+                }
+            }
+            if (k + 1 == per && e + 1 < e1) {
+                const uint64_t* sn = prow_of(e + 1) + t;
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) pw[u] = sn[(size_t)u * T];
+            }
+        }
+        const uint64_t* ph = prow_of(e);
+#pragma unroll
+        for (int r = 0; r < (PF ? 0 : S); ++r) {
             if (r < (int)un.nr) {
                 const uint64_t* pr_row = ph + (size_t)r * rp.LP * N + t;
 #pragma unroll
@@ -1098,24 +1177,22 @@ void launch_root_pm(const Launch& lc, const uint64_t* C, const uint64_t* Ph, con
     // one payload row per element: units are row pairs; otherwise single rows with up to two
     // payload rows (the accumulators stay at 2 EPT doubles per thread either way)
     const bool pairs = plan.s == 1;
-#define CW_ROOT(LG, SS, TW, LZ)                                                                              \
-    hipLaunchKernelGGL((k_root_pm_f<DefaultShape<LG>::type, SS, TW, LZ>), dim3(blocks),                       \
-                       dim3(DefaultShape<LG>::type::T), 0, lc.stream, lc.K, lc.twf, C, Ph, part, plan)
-#define CW_ROOT_N(LG)                                 \
-    if (pairs) {                                      \
-        if (plan.lazy) CW_ROOT(LG, 1, true, true);    \
-        else CW_ROOT(LG, 1, true, false);             \
-    } else {                                          \
-        if (plan.lazy) CW_ROOT(LG, 2, false, true);   \
-        else CW_ROOT(LG, 2, false, false);            \
-    }
-    if (lc.logN == 12) {
-        CW_ROOT_N(12)
-    } else if (lc.logN == 13) {
-        CW_ROOT_N(13)
-    }
-#undef CW_ROOT_N
+    with_shape(lc.logN, lc.shape, [&](auto tag) {
+        using Sh = decltype(tag);
+        if constexpr (Sh::LOGN <= 13) {
+#define CW_ROOT(SS, TW, LZ)                                                                                  \
+    hipLaunchKernelGGL((k_root_pm_f<Sh, SS, TW, LZ>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.twf, C, Ph, \
+                       part, plan)
+            if (pairs) {
+                if (plan.lazy) CW_ROOT(1, true, true);
+                else CW_ROOT(1, true, false);
+            } else {
+                if (plan.lazy) CW_ROOT(2, false, true);
+                else CW_ROOT(2, false, false);
+            }
 #undef CW_ROOT
+        }
+    });
 }
 
 // racc_q[r][row][c] += sum over slices of part[slice][q][r][row][c] (mod the row's prime).
@@ -1216,20 +1293,33 @@ hipError_t kernels_init() { return hipSuccess; }
 
 // Dispatch on the ring degree and on the transform arithmetic (fp64 only for N <= 8192: the
 // N = 16384 shape has four-stage passes, outside the fp64 bound).
+#define CW_FP_SPLIT(LC, KERN, GRID, ...)                                                                      \
+    if ((LC).fp) hipLaunchKernelGGL((KERN<Sh, true>), GRID, dim3(Sh::T), 0, (LC).stream, __VA_ARGS__);          \
+    else hipLaunchKernelGGL((KERN<Sh, false>), GRID, dim3(Sh::T), 0, (LC).stream, __VA_ARGS__);
 #define CW_NTT_DISPATCH(LC, KERN, GRID, ...)                                                                 \
-    switch ((LC).logN) {                                                                                    \
-        case 12: {                                                                                          \
-            using Sh = DefaultShape<12>::type;                                                              \
-            if ((LC).fp) hipLaunchKernelGGL((KERN<Sh, true>), GRID, dim3(Sh::T), 0, (LC).stream, __VA_ARGS__);  \
-            else hipLaunchKernelGGL((KERN<Sh, false>), GRID, dim3(Sh::T), 0, (LC).stream, __VA_ARGS__);         \
+    switch (shape_key((LC).logN, (LC).shape)) {                                                             \
+        case shape_key(12, 0): {                                                                            \
+            using Sh = ShapeVar<12, 0>::type;                                                               \
+            CW_FP_SPLIT(LC, KERN, GRID, __VA_ARGS__)                                                        \
         } break;                                                                                            \
-        case 13: {                                                                                          \
-            using Sh = DefaultShape<13>::type;                                                              \
-            if ((LC).fp) hipLaunchKernelGGL((KERN<Sh, true>), GRID, dim3(Sh::T), 0, (LC).stream, __VA_ARGS__);  \
-            else hipLaunchKernelGGL((KERN<Sh, false>), GRID, dim3(Sh::T), 0, (LC).stream, __VA_ARGS__);         \
+        case shape_key(13, 0): {                                                                            \
+            using Sh = ShapeVar<13, 0>::type;                                                               \
+            CW_FP_SPLIT(LC, KERN, GRID, __VA_ARGS__)                                                        \
         } break;                                                                                            \
-        case 14: {                                                                                          \
-            using Sh = DefaultShape<14>::type;                                                              \
+        case shape_key(13, 1): {                                                                            \
+            using Sh = ShapeVar<13, 1>::type;                                                               \
+            CW_FP_SPLIT(LC, KERN, GRID, __VA_ARGS__)                                                        \
+        } break;                                                                                            \
+        case shape_key(13, 2): {                                                                            \
+            using Sh = ShapeVar<13, 2>::type;                                                               \
+            CW_FP_SPLIT(LC, KERN, GRID, __VA_ARGS__)                                                        \
+        } break;                                                                                            \
+        case shape_key(14, 0): {                                                                            \
+            using Sh = ShapeVar<14, 0>::type;                                                               \
+            hipLaunchKernelGGL((KERN<Sh, false>), GRID, dim3(Sh::T), 0, (LC).stream, __VA_ARGS__);             \
+        } break;                                                                                            \
+        case shape_key(14, 1): {                                                                            \
+            using Sh = ShapeVar<14, 1>::type;                                                               \
             hipLaunchKernelGGL((KERN<Sh, false>), GRID, dim3(Sh::T), 0, (LC).stream, __VA_ARGS__);             \
         } break;                                                                                            \
     }
@@ -1251,18 +1341,12 @@ void launch_ntt_operand(const Launch& lc, const uint64_t* in, uint64_t* out, siz
         launch_ntt(lc, false, in, out, rows, nl, pbase);
         return;
     }
-    switch (lc.logN) {
-        case 12: {
-            using Sh = DefaultShape<12>::type;
+    with_shape(lc.logN, lc.shape, [&](auto tag) {
+        using Sh = decltype(tag);
+        if constexpr (Sh::LOGN <= 13)
             hipLaunchKernelGGL(k_ntt_fwd_operand<Sh>, dim3((unsigned)rows), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,
                                lc.twf, in, (double*)out, nl, pbase);
-        } break;
-        case 13: {
-            using Sh = DefaultShape<13>::type;
-            hipLaunchKernelGGL(k_ntt_fwd_operand<Sh>, dim3((unsigned)rows), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,
-                               lc.twf, in, (double*)out, nl, pbase);
-        } break;
-    }
+    });
 }
 
 void launch_ntt_digits(const Launch& lc, const uint64_t* c3, uint64_t* out, uint32_t E) {

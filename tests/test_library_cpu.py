@@ -82,11 +82,14 @@ def test_serving_calls_reject_null_server():
 
 def test_schedule_calls_reject_null_context():
     L = binding.lib()
-    s = binding._Schedule(64, 2, 0, 0.0)
+    s = binding._Schedule(64, 2, 0, 0, 0.0)
     assert L.pir_get_schedule(None, ctypes.byref(s)) == binding.PIR_E_INVALID
     assert L.pir_set_schedule(None, ctypes.byref(s)) == binding.PIR_E_INVALID
     assert L.pir_autotune(None, 1, 2, 1, None, 0, None) == binding.PIR_E_INVALID
     assert "null context" in L.pir_last_error().decode()
+    st = (ctypes.c_uint32 * 8)()
+    assert L.pir_ntt_shape_count(None) == 0
+    assert L.pir_ntt_shape_stages(None, 0, st) == 0
 
 
 def test_seeded_query_rejects_null_context():
@@ -120,6 +123,7 @@ def test_package_tuning_cache_is_well_formed():
     for e in json.load(open(SCHEDULE_CACHE))["entries"]:
         sch = e["schedule"]
         assert 1 <= sch["chunk_elems"] <= 4096 and 1 <= sch["query_group"] <= 8 and sch["relin_group"] >= 0
+        assert 0 <= sch.get("ntt_shape", 0) < {4096: 1, 8192: 3, 16384: 2}[e["N"]]
         assert all(p % (2 * e["N"]) == 1 for p in e["primes"])
 
 
