@@ -285,7 +285,7 @@ def main():
                    "batch_queries": B},
         "schedule": {"batched": ctx.schedule(), "plain": ctx_plain.schedule(),
                      "source": {"batched": tune, "plain": tune_plain}},
-        "root_keyswitch": ("deferred past the inner product" if fp and args.defer_relin and k_ge2 and
+        "root_keyswitch": ("deferred past the inner product" if args.defer_relin and k_ge2 and
                            (args.defer_relin == 2 or n * (cfg.L * cfg.L - 2 * cfg.L) >= 2048) else "per element"),
         "plain": {"value": n * args.steps / t_plain, "unit": "elements/s", "ms_per_query": t_plain / args.steps * 1e3,
                   **lat(per_plain)} if extras else None,

@@ -311,8 +311,8 @@ int pir_map_lossy(pir_ctx* ctx, const uint64_t* keywords, uint64_t n, uint32_t m
  *                     buffers are released afterwards. */
 /* Where the relinearization of each element's root product happens (Section 3.3.3: the answer is
  * the inner product of the selection vector with the database, Eq. (1), and it is linear in every
- * selector).  Deferred: on the fp64 path (every prime below 2^50, N <= 8192), for trees with a
- * multiplication and databases whose digit sums fit the CRT of two dedicated primes, the root
+ * selector).  Deferred: for trees with a multiplication and databases whose digit sums fit the
+ * CRT of two dedicated primes (below 2^48 on the fp64 path, below 2^61 on the integer path), the root
  * products are multiplied into the payload before relinearization, their relinearization digits
  * summed separately, and the key multiplies those sums once per answer.  mode 0: never (every
  * selector is relinearized); 1 (the default): where allowed and the database is large enough to

@@ -88,7 +88,7 @@ struct pir_ctx {
     std::map<uint32_t, cw::SwitchConst*> switches;            // keep -> device switch constants
     uint32_t xslab = 0;       // element-queries per tensor + scale launch (X stays in the Infinity Cache)
     int defer_mode = 1;       // root key switch after the inner product: 0 never, 1 where it pays, 2 where allowed
-    bool crt_ok = false;      // the two primes of the deferred key switch exist (fp64 path)
+    bool crt_ok = false;      // the two primes of the deferred key switch exist
     cw::CrtConst crt{};
     void* scratch = nullptr;  // this device's copy of the no-allocation scratch array (device address)
     std::string scratch_err;  // why it is missing, if it is
@@ -128,8 +128,8 @@ struct pir_db {
 // helpers
 // ------------------------------------------------------------------------------------------------
 // Deferred key switch of the root products (kernels.hip, "Root products with the key switch
-// deferred past the inner product"): used on the fp64 path when the database's digit sums fit the
-// CRT of two auxiliary primes, for trees with at least one multiplication.
+// deferred past the inner product"): used when the database's digit sums fit the CRT of two
+// auxiliary primes, for trees with at least one multiplication.
 constexpr uint32_t ROOT_A = 2;  // auxiliary primes holding the digit sums
 // Mode 2 defers wherever the bound allows; mode 1 (the default) also asks that the database be
 // large enough to repay the per-answer work (the digit sums' CRT and key products, about L^2 + 3L
@@ -389,14 +389,12 @@ extern "C" int pir_setup(const pir_params* params, pir_ctx** out) {
     ctx->primes = q;
     ctx->primes.insert(ctx->primes.end(), B.begin(), B.end());
     ctx->fp = fp;
-    // fp64 path: two more primes below 2^48 for the deferred key switch's digit sums (their lazy
-    // transforms need no reduction between passes); they follow Q and B in every per-prime table
-    std::vector<uint64_t> D;
-    if (fp) {
-        D = cw::host::primes_below(ctx->N, cw::FP_LAZY_BOUND, 2, ctx->primes);
-        if (D.size() == 2) ctx->primes.insert(ctx->primes.end(), D.begin(), D.end());
-        else D.clear();
-    }
+    // two more primes for the deferred key switch's digit sums, after Q and B in every per-prime
+    // table: below 2^48 on the fp64 path (their lazy transforms need no reduction between passes),
+    // below 2^61 on the integer path (the lazy integer transform keeps values below 4p < 2^64)
+    std::vector<uint64_t> D = cw::host::primes_below(ctx->N, fp ? cw::FP_LAZY_BOUND : (1ull << 61), 2, ctx->primes);
+    if (D.size() == 2) ctx->primes.insert(ctx->primes.end(), D.begin(), D.end());
+    else D.clear();
     cw::host::build_const(ctx->K, ctx->N, q, B, ctx->t, D);
     ctx->K.fp = fp ? 1 : 0;
     if (params->chunk_elems > 4096) return cleanup_early(fail(PIR_E_INVALID, "chunk_elems must be <= 4096"), ctx);

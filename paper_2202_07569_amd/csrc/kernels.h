@@ -93,7 +93,7 @@ void launch_relin_mac(const Launch& lc, const uint64_t* R, const Batch& bt);
 void launch_relin(const Launch& lc, const uint64_t* c3, const Batch& bt, uint64_t* staging);
 // Whether launch_relin needs its staging buffer [E][L+2][L][N] at this ring degree.
 bool relin_needs_staging(uint32_t logN);
-// Deferred root key switch (fp64 path, N <= 8192): part [nslices][nq][s][RR][N] receives each
+// Deferred root key switch (fp64 or integer transforms): part [nslices][nq][s][RR][N] receives each
 // slice's sums of transformed rows times payload rows Ph [E][s][LP][N] (residues).
 void launch_root_pm(const Launch& lc, const uint64_t* C, const uint64_t* Ph, const RootPlan& plan, uint64_t* part);
 // racc_q [s][RR][N] += sum over slices of part[.][q] (mod each row's prime), q < nq.

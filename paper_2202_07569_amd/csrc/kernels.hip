@@ -1001,7 +1001,7 @@ void launch_relin(const Launch& lc, const uint64_t* c3, const Batch& bt, uint64_
 bool relin_needs_staging(uint32_t logN) { return logN >= 14; }
 
 // ---------------------------------------------------------------------------------------------
-// Root products with the key switch deferred past the inner product (fp64 path).
+// Root products with the key switch deferred past the inner product.
 //
 // The answer is linear in every selector.  With element e's root product c = (c0, c1, c2) and its
 // relinearization digits D_i = [c2]_{q_i} (integers in [0, q_i)),
@@ -1171,6 +1171,118 @@ __global__ __launch_bounds__(Sh::T) void k_root_pm_f(const CtxConst* __restrict_
     }
 }
 
+// Integer form of k_root_pm_f (some prime at or above 2^50, or N = 16384): the same units and
+// sums with the integer transform, whose twiddles (value and Shoup companion) come from global
+// memory (at N = 16384 the exchange buffer leaves no room for them in LDS), and Barrett products of
+// the transformed row with the payload rows, added into accumulators kept in [0, p).  The next
+// row is loaded during the current transform where eight elements per thread leave the registers
+// for it (N <= 8192).
+template <class Sh, int S, bool TWO>
+__global__ __launch_bounds__(Sh::T) void k_root_pm_i(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
+                                                     const uint64_t* __restrict__ C, const uint64_t* __restrict__ Ph,
+                                                     uint64_t* __restrict__ part, const RootPlan rp) {
+    __shared__ uint64_t sm[Sh::LDS_WORDS];
+    constexpr int N = Sh::N, T = Sh::T, EPT = Sh::EPT;
+    constexpr bool PF = EPT <= 8;
+    const uint32_t L = K->L, tid = threadIdx.x;
+    size_t sl;
+    uint32_t mem;
+    xcd_split(blockIdx.x, rp.nq * rp.U, sl, mem);
+    if (sl >= rp.nslices) return;
+    const uint32_t q = mem % rp.nq;
+    const RootUnit un = rp.u[mem / rp.nq];
+    const uint32_t pr = un.prime;
+    const uint64_t p = K->p[pr], r1 = K->r1[pr], mu = K->bar_mu[pr];
+    const uint32_t sb = K->bar_s[pr];
+    const TwRow twr = tw_row(tw, nullptr, pr, N);
+    // a digit (rows 2L..3L-1 of the product) may exceed the unit's prime: reduce it first
+    const bool red0 = un.src0 >= 2 * L && K->p[un.src0 - 2 * L] > p;
+    const bool two = TWO && un.two;
+    const bool red1 = two && un.src1 >= 2 * L && K->p[un.src1 - 2 * L] > p;
+    const uint32_t e0 = (uint32_t)sl * rp.slice;
+    const uint32_t e1 = min(rp.E, e0 + rp.slice);
+    uint64_t acc0[S][EPT], acc1[TWO ? S : 1][EPT], a[EPT];
+#pragma unroll
+    for (int r = 0; r < S; ++r)
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) acc0[r][u] = 0;
+    if constexpr (TWO) {
+#pragma unroll
+        for (int r = 0; r < S; ++r)
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) acc1[r][u] = 0;
+    }
+    const uint32_t per = two ? 2u : 1u, steps = (e1 - e0) * per;
+    auto src_of = [&](uint32_t i) {
+        const uint32_t e = e0 + i / per;
+        return C + ((size_t)q * rp.E + e) * 3 * L * N + (size_t)((i % per) ? un.src1 : un.src0) * N;
+    };
+    uint64_t nx[PF ? EPT : 1];
+    if constexpr (PF) {
+        const uint64_t* src = src_of(0);
+#pragma unroll
+        for (int u = 0; u < EPT; ++u) nx[u] = src[elem_index<Sh, 0>(tid, u)];
+    }
+    for (uint32_t i = 0; i < steps; ++i) {
+        uint32_t t = tid;
+        asm volatile("" : "+v"(t));  // keep the per-row index arithmetic out of registers across rows
+        const uint32_t e = e0 + i / per, k = i % per;
+        const bool red = k ? red1 : red0;
+        if constexpr (PF) {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) a[u] = nx[u];
+            if (i + 1 < steps) {
+                const uint64_t* src = src_of(i + 1);
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) nx[u] = src[elem_index<Sh, 0>(t, u)];
+            }
+        } else {
+            const uint64_t* src = src_of(i);
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) a[u] = src[elem_index<Sh, 0>(t, u)];
+        }
+        if (red) {
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) a[u] = reduce64(a[u], p, r1);
+        }
+        ntt_fwd_regs<Sh, false>(a, sm, t, twr, K, pr);
+        asm volatile("" ::: "memory");  // keep the payload loads below the transform
+        const uint64_t* ph = Ph + ((size_t)e * rp.s + un.r0) * rp.LP * N + (size_t)un.prow * N;
+#pragma unroll
+        for (int r = 0; r < S; ++r) {
+            if (r < (int)un.nr) {
+                const uint64_t* pr_row = ph + (size_t)r * rp.LP * N + t;
+#pragma unroll
+                for (int u = 0; u < EPT; ++u) {
+                    const uint64_t x = mul_barrett(a[u], pr_row[(size_t)u * T], p, mu, sb);
+                    if constexpr (TWO) {
+                        if (k) acc1[r][u] = add_mod(acc1[r][u], x, p);
+                        else acc0[r][u] = add_mod(acc0[r][u], x, p);
+                    } else {
+                        acc0[r][u] = add_mod(acc0[r][u], x, p);
+                    }
+                }
+            }
+        }
+        asm volatile("" ::: "memory");
+    }
+    const size_t LPS = (size_t)rp.RR * N;  // one r block of part
+    uint64_t* out = part + ((sl * rp.nq + q) * rp.s) * LPS + tid;
+#pragma unroll
+    for (int r = 0; r < S; ++r) {
+        if (r < (int)un.nr) {
+            uint64_t* o0 = out + (size_t)(un.r0 + r) * LPS + (size_t)un.row0 * N;
+            uint64_t* o1 = out + (size_t)(un.r0 + r) * LPS + (size_t)un.row1 * N;
+#pragma unroll
+            for (int u = 0; u < EPT; ++u) {
+                o0[(size_t)u * T] = acc0[r][u];
+                if constexpr (TWO)
+                    if (two) o1[(size_t)u * T] = acc1[r][u];
+            }
+        }
+    }
+}
+
 void launch_root_pm(const Launch& lc, const uint64_t* C, const uint64_t* Ph, const RootPlan& plan, uint64_t* part) {
     if (!plan.E || !plan.nq) return;
     const unsigned blocks = (unsigned)xcd_grid(plan.nslices, plan.nq * plan.U);
@@ -1179,6 +1291,15 @@ void launch_root_pm(const Launch& lc, const uint64_t* C, const uint64_t* Ph, con
     const bool pairs = plan.s == 1;
     with_shape(lc.logN, lc.shape, [&](auto tag) {
         using Sh = decltype(tag);
+        if (!lc.fp) {
+            if (pairs)
+                hipLaunchKernelGGL((k_root_pm_i<Sh, 1, true>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw, C,
+                                   Ph, part, plan);
+            else
+                hipLaunchKernelGGL((k_root_pm_i<Sh, 2, false>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,
+                                   C, Ph, part, plan);
+            return;
+        }
         if constexpr (Sh::LOGN <= 13) {
 #define CW_ROOT(SS, TW, LZ)                                                                                  \
     hipLaunchKernelGGL((k_root_pm_f<Sh, SS, TW, LZ>), dim3(blocks), dim3(Sh::T), 0, lc.stream, lc.K, lc.twf, C, Ph, \

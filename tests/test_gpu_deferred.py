@@ -6,7 +6,8 @@ per answer (pir_set_defer_relin; mode 2 forces it on these small databases, whic
 leaves per element).  The answers must be bit-identical to relinearizing every selector
 and to the oracle's, for every shape the deferred path takes: k = 2 and k = 4 trees, one, two,
 three and four plaintexts per element (row pairs for s = 1, single rows with payload pairs above),
-ragged chunks, several queries per launch, and the tiny, mid and wide prime sets.
+ragged chunks, several queries per launch, the tiny, mid and wide prime sets on the fp64
+transforms, and the keyword parameters and 52-55-bit primes on the integer transforms.
 """
 import numpy as np
 import pytest
@@ -59,6 +60,8 @@ CASES = {
     "mid-k4-s3": datagen.Config("mid-k4-s3", 8192, datagen.Q_N8192, 65537, 4, 9, 40, 3, 72),
     # k = 3 (depth 2) needs the mid modulus for the answer to decrypt (tiny's 108 bits run out)
     "mid-k3-s4": datagen.Config("mid-k3-s4", 8192, datagen.Q_N8192, 65537, 3, 8, 30, 4, 73),
+    # keyword parameters: N = 16384, eight 54/55-bit primes, integer transforms, s = 2
+    "kw-k4-s2": datagen.Config("kw-k4-s2", 16384, datagen.Q_N16384, 65537, 4, 12, 24, 2, 75),
 }
 
 
@@ -87,10 +90,14 @@ def test_deferred_equals_per_element_and_oracle(name):
 
 
 @pytest.mark.parametrize("primes", [(0x1fffffffce001, 0x1fffffff96001, 0x1ffffffce001),
-                                    (0x3ffffff84001, 0xfffffdc001, 0x7ffe6001)], ids=["wide", "mixed"])
+                                    (0x3ffffff84001, 0xfffffdc001, 0x7ffe6001),
+                                    (0x7ffffffffb4001, 0x3ffffffffd6001, 0xffffffffca001)],
+                         ids=["wide", "mixed", "int55"])
 def test_deferred_with_other_primes(primes):
     """49/49/45-bit primes (digits close to the auxiliary primes, which may be smaller than a
-    digit's prime: such digits are reduced before their transform) and 46/40/31-bit primes."""
+    digit's prime: such digits are reduced before their transform), 46/40/31-bit primes, and
+    55/54/52-bit primes (at or above 2^50: integer transforms at N = 4096, digit-sum primes below
+    2^61)."""
     cfg = datagen.Config("defer-primes", 4096, primes, 65537, 2, 10, 33, 1, 74)
     ins = cached_instance(cfg)
     _say(f"primes {[p.bit_length() for p in primes]}: deferred against the oracle")
