@@ -960,17 +960,23 @@ static void make_nodes(pir_ctx* ctx, const Launch& lc, const Bufs& b, const uint
         for (uint32_t p0 = start; p0 < end; p0 += E) {
             const uint32_t cnt = std::min(E, end - p0);
             mult_relin(ctx, lc, b, pairs + 2 * (size_t)p0, one_query(cnt, leaves, nodes, key, tmp));
+            // the node's rows modulo the q_j are the key switch's output, already transformed: they
+            // are taken as they are; only the auxiliary rows go through coefficients and back
+            uint64_t* dst = nodes + (size_t)p0 * 2 * LL * N;
+            {
+                Prof pr(ctx, "extend", lc.stream, (double)2 * cnt * N);
+                cw::launch_operand_q_rows(lc, tmp, dst, (size_t)2 * cnt);
+            }
             {
                 Prof pr(ctx, "ntt_inv", lc.stream, bfly(ctx, (size_t)cnt * 2 * L));
                 cw::launch_ntt(lc, true, tmp, tmp, (size_t)cnt * 2 * L, L, 0);
             }
-            uint64_t* dst = nodes + (size_t)p0 * 2 * LL * N;
             {
                 Prof pr(ctx, "extend", lc.stream, (double)2 * cnt * N);
-                cw::launch_extend(lc, tmp, dst, (size_t)2 * cnt);
+                cw::launch_extend(lc, tmp, dst, (size_t)2 * cnt, false);
             }
-            Prof pr(ctx, "ntt_fwd", lc.stream, bfly(ctx, (size_t)cnt * 2 * LL));
-            cw::launch_ntt_operand(lc, dst, dst, (size_t)cnt * 2 * LL, LL, 0);
+            Prof pr(ctx, "ntt_fwd", lc.stream, bfly(ctx, (size_t)cnt * 2 * (LL - L)));
+            cw::launch_ntt_operand(lc, dst, dst, (size_t)cnt * 2 * (LL - L), LL, 0, L);
         }
         start = end;
     }

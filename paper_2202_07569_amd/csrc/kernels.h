@@ -70,16 +70,21 @@ uint32_t ntt_shape_stages(uint32_t logN, uint32_t v, uint32_t* stages);
 void launch_ntt(const Launch& lc, bool inverse, const uint64_t* in, uint64_t* out, size_t rows, uint32_t nl,
                 uint32_t pbase);
 // Forward transform of coefficient-form rows (u64 in [0, p)) into the operand format (in place
-// allowed).
+// allowed).  skip > 0: the rows form blocks of nl of which the first `skip` are left as they are;
+// rows counts the transformed ones (blocks * (nl - skip)).
 void launch_ntt_operand(const Launch& lc, const uint64_t* in, uint64_t* out, size_t rows, uint32_t nl,
-                        uint32_t pbase);
+                        uint32_t pbase, uint32_t skip = 0);
 // Lift and transform uint16 rows: out [rows_u16][nl][N], row j modulo context prime j for j < L and
 // prime dbase + j - L above (nl = 0: L).
 void launch_ntt_payload(const Launch& lc, const uint16_t* pay, uint64_t* out, size_t rows_u16, uint32_t nl = 0,
                         uint32_t dbase = 0);
 // Transformed relinearization staging [E][L+2][L][N] straight from a coefficient-form [E][3][L][N].
 void launch_ntt_digits(const Launch& lc, const uint64_t* c3, uint64_t* out, uint32_t E);
-void launch_extend(const Launch& lc, const uint64_t* in, uint64_t* out, size_t G);
+// Exact centred extension of coefficient-form [G][L][N] to [G][LL][N] (Q rows copied unless
+// write_q is false, then only the B rows are written).
+void launch_extend(const Launch& lc, const uint64_t* in, uint64_t* out, size_t G, bool write_q = true);
+// Rows j < L of out [G][LL][N] in the operand format from transformed residues in [G][L][N].
+void launch_operand_q_rows(const Launch& lc, const uint64_t* in, uint64_t* out, size_t G);
 // Tensor product (a0 b0, a0 b1 + a1 b0, a1 b1) of E operand pairs over Q u B, formed while loading
 // and inverse-transformed: X [E][3][LL][N] in coefficient form.
 // Only rows eq0 .. eq0 + count - 1 of the batch (row eq = q E + e; count = 0: to the end), stored from

@@ -571,18 +571,27 @@ __device__ __forceinline__ size_t natural_pos(size_t g, uint32_t tid, int u) {
     return g * Sh::N + elem_index<Sh, 0>(tid, u);
 }
 
-// Plain rows of a [rows][N] array, prime = pbase + row mod nl.
+// Plain rows of a [rows][N] array, prime = pbase + row mod nl.  With skip > 0 the array is blocks
+// of nl rows of which the first `skip` are left as they are: transform g is row skip + g mod
+// (nl - skip) of block g / (nl - skip).
 template <class Sh>
 struct RowsFwdU64 {
     const uint64_t* in;
     uint64_t* out;
-    uint32_t nl, pbase;
-    __device__ uint32_t prime(size_t g) const { return pbase + (uint32_t)(g % nl); }
-    __device__ void load(size_t g, uint32_t tid, uint64_t* a) const {
-#pragma unroll
-        for (int u = 0; u < Sh::EPT; ++u) a[u] = in[natural_pos<Sh>(g, tid, u)];
+    uint32_t nl, pbase, skip;
+    __device__ size_t row(size_t g) const {
+        const uint32_t w = nl - skip;
+        return (g / w) * nl + skip + g % w;
     }
-    __device__ void store(size_t g, uint32_t tid, int u, uint64_t v) const { out[transformed_pos<Sh>(g, tid, u)] = v; }
+    __device__ uint32_t prime(size_t g) const { return pbase + (uint32_t)(row(g) % nl); }
+    __device__ void load(size_t g, uint32_t tid, uint64_t* a) const {
+        const size_t r = row(g);
+#pragma unroll
+        for (int u = 0; u < Sh::EPT; ++u) a[u] = in[natural_pos<Sh>(r, tid, u)];
+    }
+    __device__ void store(size_t g, uint32_t tid, int u, uint64_t v) const {
+        out[transformed_pos<Sh>(row(g), tid, u)] = v;
+    }
 };
 
 template <class Sh>
@@ -724,14 +733,16 @@ struct RowsTensor {
 
 // Forward transform of coefficient-form rows (u64 residues in [0, p)) into the fp64 operand
 // format: integer-valued doubles in [-p/2, p/2], transformed layout.
+// skip: as in RowsFwdU64 (the first `skip` rows of every block of nl stay as they are).
 template <class Sh>
 __global__ __launch_bounds__(Sh::T) void k_ntt_fwd_operand(const CtxConst* __restrict__ K,
                                                            const uint64_t* __restrict__ tw,
                                                            const double* __restrict__ twf, const uint64_t* in,
-                                                           double* out, uint32_t nl, uint32_t pbase) {
+                                                           double* out, uint32_t nl, uint32_t pbase, uint32_t skip) {
     __shared__ uint64_t sm[Sh::LDS_WORDS];
     const uint32_t tid = threadIdx.x;
-    const size_t g = blockIdx.x;
+    const uint32_t w = nl - skip;
+    const size_t g = (size_t)(blockIdx.x / w) * nl + skip + blockIdx.x % w;
     const uint32_t pi = pbase + (uint32_t)(g % nl);
     double v[Sh::EPT];
 #pragma unroll
@@ -744,8 +755,8 @@ __global__ __launch_bounds__(Sh::T) void k_ntt_fwd_operand(const CtxConst* __res
 template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T) void k_ntt_fwd(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
                                                    const double* __restrict__ twf, const uint64_t* in, uint64_t* out,
-                                                   uint32_t nl, uint32_t pbase) {
-    ntt_fwd_row<Sh, FP>(K, tw, twf, RowsFwdU64<Sh>{in, out, nl, pbase});
+                                                   uint32_t nl, uint32_t pbase, uint32_t skip) {
+    ntt_fwd_row<Sh, FP>(K, tw, twf, RowsFwdU64<Sh>{in, out, nl, pbase, skip});
 }
 template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T) void k_ntt_inv(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
@@ -1451,22 +1462,22 @@ void launch_ntt(const Launch& lc, bool inverse, const uint64_t* in, uint64_t* ou
     if (inverse) {
         CW_NTT_DISPATCH(lc, k_ntt_inv, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, in, out, nl, pbase)
     } else {
-        CW_NTT_DISPATCH(lc, k_ntt_fwd, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, in, out, nl, pbase)
+        CW_NTT_DISPATCH(lc, k_ntt_fwd, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, in, out, nl, pbase, 0u)
     }
 }
 
 void launch_ntt_operand(const Launch& lc, const uint64_t* in, uint64_t* out, size_t rows, uint32_t nl,
-                        uint32_t pbase) {
+                        uint32_t pbase, uint32_t skip) {
     if (!rows) return;
     if (!lc.fp) {
-        launch_ntt(lc, false, in, out, rows, nl, pbase);
+        CW_NTT_DISPATCH(lc, k_ntt_fwd, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, in, out, nl, pbase, skip)
         return;
     }
     with_shape(lc.logN, lc.shape, [&](auto tag) {
         using Sh = decltype(tag);
         if constexpr (Sh::LOGN <= 13)
             hipLaunchKernelGGL(k_ntt_fwd_operand<Sh>, dim3((unsigned)rows), dim3(Sh::T), 0, lc.stream, lc.K, lc.tw,
-                               lc.twf, in, (double*)out, nl, pbase);
+                               lc.twf, in, (double*)out, nl, pbase, skip);
     });
 }
 
@@ -1499,7 +1510,7 @@ void launch_ntt_payload(const Launch& lc, const uint16_t* pay, uint64_t* out, si
 // ---------------------------------------------------------------------------------------------
 template <int NL>
 __device__ __forceinline__ bool extend_coeff(const CtxConst* K, const uint64_t* x, size_t xs, uint64_t* o, size_t os,
-                                             bool exact) {
+                                             bool exact, bool write_q) {
     const uint32_t L = K->L, LB = K->LB;
     uint64_t y[NL];
 #pragma unroll
@@ -1507,7 +1518,7 @@ __device__ __forceinline__ bool extend_coeff(const CtxConst* K, const uint64_t* 
         if (i < (int)L) {
             uint64_t xi = x[i * xs];
             y[i] = mul_shoup(xi, K->qinv[i], K->qinvq[i], K->p[i]);
-            o[i * os] = xi;
+            if (write_q) o[i * os] = xi;
         }
     bool amb = false;
     uint32_t v = exact ? conv_round_exact(K->qb, y) : conv_round_fast<NL>(K->qb, y, L, amb);
@@ -1517,41 +1528,70 @@ __device__ __forceinline__ bool extend_coeff(const CtxConst* K, const uint64_t* 
 
 template <int NL>
 __global__ void k_extend(const CtxConst* __restrict__ K, const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
-                         size_t G, uint64_t* fix, uint32_t* fixcnt) {
+                         size_t G, uint64_t* fix, uint32_t* fixcnt, uint32_t write_q) {
     const uint32_t N = K->N, L = K->L, LL = K->LL;
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= G * N) return;
     const size_t g = gid / N, c = gid % N;
-    if (extend_coeff<NL>(K, in + g * L * N + c, N, out + g * LL * N + c, N, false)) fix[atomicAdd(fixcnt, 1u)] = gid;
+    if (extend_coeff<NL>(K, in + g * L * N + c, N, out + g * LL * N + c, N, false, write_q != 0))
+        fix[atomicAdd(fixcnt, 1u)] = gid;
 }
 
 template <int NL>
 __global__ void k_extend_fix(const CtxConst* __restrict__ K, const uint64_t* __restrict__ in, uint64_t* __restrict__ out,
-                             uint64_t* fix, uint32_t* fixcnt) {
+                             uint64_t* fix, uint32_t* fixcnt, uint32_t write_q) {
     const uint32_t N = K->N, L = K->L, LL = K->LL;
     const uint32_t n = *fixcnt;
     for (uint32_t f = threadIdx.x; f < n; f += blockDim.x) {
         const size_t gid = fix[f];
         const size_t g = gid / N, c = gid % N;
-        extend_coeff<NL>(K, in + g * L * N + c, N, out + g * LL * N + c, N, true);
+        extend_coeff<NL>(K, in + g * L * N + c, N, out + g * LL * N + c, N, true, write_q != 0);
     }
     __syncthreads();
     if (threadIdx.x == 0) *fixcnt = 0;
 }
 
-void launch_extend(const Launch& lc, const uint64_t* in, uint64_t* out, size_t G) {
+void launch_extend(const Launch& lc, const uint64_t* in, uint64_t* out, size_t G, bool write_q) {
     if (!G) return;
     const unsigned nb = blocks_for(G * lc.N);
+    const uint32_t wq = write_q ? 1u : 0u;
+#define CW_EXT(NL)                                                                                            \
+    hipLaunchKernelGGL(k_extend<NL>, dim3(nb), dim3(EW_THREADS), 0, lc.stream, lc.K, in, out, G, lc.fix, lc.fixcnt, wq); \
+    hipLaunchKernelGGL(k_extend_fix<NL>, dim3(1), dim3(256), 0, lc.stream, lc.K, in, out, lc.fix, lc.fixcnt, wq);
     if (lc.L <= 4) {
-        hipLaunchKernelGGL(k_extend<4>, dim3(nb), dim3(EW_THREADS), 0, lc.stream, lc.K, in, out, G, lc.fix, lc.fixcnt);
-        hipLaunchKernelGGL(k_extend_fix<4>, dim3(1), dim3(256), 0, lc.stream, lc.K, in, out, lc.fix, lc.fixcnt);
+        CW_EXT(4)
     } else if (lc.L <= 8) {
-        hipLaunchKernelGGL(k_extend<8>, dim3(nb), dim3(EW_THREADS), 0, lc.stream, lc.K, in, out, G, lc.fix, lc.fixcnt);
-        hipLaunchKernelGGL(k_extend_fix<8>, dim3(1), dim3(256), 0, lc.stream, lc.K, in, out, lc.fix, lc.fixcnt);
+        CW_EXT(8)
     } else {
-        hipLaunchKernelGGL(k_extend<12>, dim3(nb), dim3(EW_THREADS), 0, lc.stream, lc.K, in, out, G, lc.fix, lc.fixcnt);
-        hipLaunchKernelGGL(k_extend_fix<12>, dim3(1), dim3(256), 0, lc.stream, lc.K, in, out, lc.fix, lc.fixcnt);
+        CW_EXT(12)
     }
+#undef CW_EXT
+}
+
+// Rows j < L of out [G][LL][N] (transformed operands) from in [G][L][N] (transformed residues in
+// [0, p)): the same values, as centred doubles on the fp64 path (what k_ntt_fwd_operand leaves).
+__global__ void k_operand_q_rows(const CtxConst* __restrict__ K, const uint64_t* __restrict__ in,
+                                 uint64_t* __restrict__ out, size_t G) {
+    const uint32_t N = K->N, L = K->L, LL = K->LL;
+    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= G * L * N) return;
+    const size_t c = gid % N, gj = gid / N;
+    const uint32_t j = (uint32_t)(gj % L);
+    const size_t g = gj / L;
+    const uint64_t x = in[gid];
+    uint64_t o = x;
+    if (K->fp) {
+        const uint64_t p = K->p[j];
+        const double d = x > (p - 1) / 2 ? (double)x - K->pd[j] : (double)x;
+        o = (uint64_t)__double_as_longlong(d);
+    }
+    out[(g * LL + j) * N + c] = o;
+}
+
+void launch_operand_q_rows(const Launch& lc, const uint64_t* in, uint64_t* out, size_t G) {
+    const size_t n = G * lc.L * lc.N;
+    if (!n) return;
+    hipLaunchKernelGGL(k_operand_q_rows, dim3(blocks_for(n)), dim3(EW_THREADS), 0, lc.stream, lc.K, in, out, G);
 }
 
 // ---------------------------------------------------------------------------------------------
