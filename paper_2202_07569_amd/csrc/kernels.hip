@@ -271,13 +271,74 @@ __device__ __forceinline__ void fwd_pass_fp(double* a, uint32_t tid, const doubl
     }
 }
 
-template <class Sh, int P>
+// Inverse transforms with bounds tracked at compile time (LZ > 0).  In a pass the pair of a
+// butterfly has one bound b (in units of p), set by the pass bits its registers share; the sum
+// leaves below 2b and the product below m(2b) = 1/2 + c 2b, where c = 3 p_max 2^-53 (the fmulmod
+// bound above).  So every register's bound at the end of a pass is a function of its register
+// index alone, given the pass's entry bound; registers above `thr` are reduced there (to 1/2 +
+// 2^-40), and the next pass starts from the largest bound left.  Every value stays below the
+// all-sum chain's entry bound 2^rp, which is checked against cap = 2^53 / p_max.
+// LZ = 1: any prime below 2^50 (c = 3/8, cap 8), thr 0.6 (every register reduced between passes,
+//         none before the first: the inputs are tensor products, below 1.4 p);
+// LZ = 2: primes below 2^44 (c = 3/512, cap 512), thr 32 (one register reduced in a transform).
+struct InvLazy {
+    double c, cap, thr, a0;
+};
+__host__ __device__ constexpr InvLazy inv_lazy(int LZ) {
+    return LZ == 2 ? InvLazy{3.0 / 512, 512.0, 32.0, 1.4} : InvLazy{3.0 / 8, 8.0, 0.6, 1.4};
+}
+template <class Sh>
+__host__ __device__ constexpr double inv_reg_bound(int P, int u, double a, double c) {
+    const int rp = Sh::r(P), x = Sh::R - rp;
+    double b = a;
+    for (int sp = rp - 1; sp >= 0; --sp) {
+        const int pb = x + rp - 1 - sp;
+        b = ((u >> pb) & 1) ? 0.5 + c * 2 * b : 2 * b;
+    }
+    return b;
+}
+// entry bound of inverse pass P (the passes run from NP - 1 down to 0)
+template <class Sh>
+__host__ __device__ constexpr double inv_pass_in(int P, int LZ) {
+    const InvLazy z = inv_lazy(LZ);
+    double a = z.a0;
+    for (int q = Sh::NP - 1; q > P; --q) {
+        double m = 0.5 + 0x1p-40;
+        for (int u = 0; u < Sh::EPT; ++u) {
+            const double b = inv_reg_bound<Sh>(q, u, a, z.c);
+            if (b <= z.thr && b > m) m = b;
+        }
+        a = m;
+    }
+    return a;
+}
+// registers reduced at the end of pass P (bit u), none after the last (the caller reduces all)
+template <class Sh>
+__host__ __device__ constexpr uint32_t inv_fred_mask(int P, int LZ) {
+    uint32_t mask = 0;
+    if (P == 0) return 0;
+    const double a = inv_pass_in<Sh>(P, LZ);
+    for (int u = 0; u < Sh::EPT; ++u)
+        if (inv_reg_bound<Sh>(P, u, a, inv_lazy(LZ).c) > inv_lazy(LZ).thr) mask |= 1u << u;
+    return mask;
+}
+template <class Sh>
+__host__ __device__ constexpr bool inv_lazy_exact(int LZ) {
+    for (int P = Sh::NP - 1; P >= 0; --P)
+        if (inv_pass_in<Sh>(P, LZ) * (double)(1 << Sh::r(P)) >= inv_lazy(LZ).cap) return false;
+    return true;
+}
+
+template <class Sh, int P, int LZ = 0>
 __device__ __forceinline__ void inv_pass_fp(double* a, uint32_t tid, const double* __restrict__ tw, double p,
                                             double pinv) {
     using G = PassGeo<Sh, P>;
     static_assert(G::rp <= 3, "the fp64 bound needs passes of at most three stages");
+    static_assert(LZ == 0 || inv_lazy_exact<Sh>(LZ), "the lazy inverse transform would leave the exact range");
+    if constexpr (LZ == 0) {
 #pragma unroll
-    for (int u = 0; u < Sh::EPT; ++u) a[u] = fred(a[u], p, pinv);
+        for (int u = 0; u < Sh::EPT; ++u) a[u] = fred(a[u], p, pinv);
+    }
 #pragma unroll
     for (int sp = G::rp - 1; sp >= 0; --sp) {
         const int s = G::S0 + sp;
@@ -293,6 +354,12 @@ __device__ __forceinline__ void inv_pass_fp(double* a, uint32_t tid, const doubl
             a[u0] = X + Y;
             a[u1] = fmulmod(X - Y, ts[c], p, pinv);
         }
+    }
+    if constexpr (LZ > 0) {
+        constexpr uint32_t mask = inv_fred_mask<Sh>(P, LZ);
+#pragma unroll
+        for (int u = 0; u < Sh::EPT; ++u)
+            if ((mask >> u) & 1u) a[u] = fred(a[u], p, pinv);
     }
 }
 #pragma clang fp contract(on)
@@ -388,15 +455,15 @@ __device__ __forceinline__ void fwd_passes(void* av, void* smv, uint32_t tid, Tw
     }
 }
 
-template <class Sh, bool FP, int P>
+template <class Sh, bool FP, int P, int LZ = 0>
 __device__ __forceinline__ void inv_passes(void* av, void* smv, uint32_t tid, TwRow tw, const CtxConst* K,
                                            uint32_t pi) {
     if constexpr (FP) {
         double* a = (double*)av;
-        inv_pass_fp<Sh, P>(a, tid, tw.f + 2 * Sh::N, K->pd[pi], K->pinv[pi]);
+        inv_pass_fp<Sh, P, LZ>(a, tid, tw.f + 2 * Sh::N, K->pd[pi], K->pinv[pi]);
         if constexpr (P > 0) {
             exchange<Sh, P, P - 1, P == Sh::NP - 1>(a, (double*)smv, tid);
-            inv_passes<Sh, FP, P - 1>(av, smv, tid, tw, K, pi);
+            inv_passes<Sh, FP, P - 1, LZ>(av, smv, tid, tw, K, pi);
         }
     } else {
         uint64_t* a = (uint64_t*)av;
@@ -426,11 +493,12 @@ __device__ __forceinline__ void ntt_fwd_f(double* v, uint64_t* sm, uint32_t tid,
         for (int u = 0; u < Sh::EPT; ++u) v[u] = fred(v[u], p, pinv);
     }
 }
-// NINV = false leaves out the factor N^-1 (the caller folds it into a later constant).
-template <class Sh, bool NINV = true>
+// NINV = false leaves out the factor N^-1 (the caller folds it into a later constant).  LZ > 0:
+// the lazy schedules of inv_pass_fp (inputs below 1.4 p; LZ = 2 only for primes below 2^44).
+template <class Sh, bool NINV = true, int LZ = 0>
 __device__ __forceinline__ void ntt_inv_f(double* v, uint64_t* sm, uint32_t tid, TwRow tw, const CtxConst* K,
                                           uint32_t pi) {
-    inv_passes<Sh, true, Sh::NP - 1>(v, sm, tid, tw, K, pi);
+    inv_passes<Sh, true, Sh::NP - 1, LZ>(v, sm, tid, tw, K, pi);
     const double p = K->pd[pi], pinv = K->pinv[pi], ni = K->ninvd[pi];
 #pragma unroll
     for (int u = 0; u < Sh::EPT; ++u) v[u] = NINV ? fred(fmulmod(v[u], ni, p, pinv), p, pinv) : fred(v[u], p, pinv);
@@ -794,11 +862,15 @@ __global__ __launch_bounds__(Sh::T, Sh::LOGN == 13 ? 8 : 1) void k_ntt_inv_tenso
     const uint32_t tid = threadIdx.x;
     const uint32_t pi = row.prime(g);
     // X leaves without the transform's factor N^-1: the scale kernels, its only readers, take it
-    // with their first constants (tqinv, kb1)
+    // with their first constants (tqinv, kb1).  The tensor products enter below 1.4 p, so the
+    // inverse transform takes a lazy schedule (rows modulo primes below 2^44 almost unreduced).
     if constexpr (FP) {
         double v[Sh::EPT];
         row.load_f(g, tid, v);
-        ntt_inv_f<Sh, false>(v, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
+        constexpr int LZB = inv_lazy_exact<Sh>(1) ? 1 : 0;    // a first pass of three stages from 1.4 p
+        constexpr int LZQ = inv_lazy_exact<Sh>(2) ? 2 : LZB;  // would reach 11.2 p, beyond 8 p below 2^50
+        if (K->pd[pi] < 0x1p44) ntt_inv_f<Sh, false, LZQ>(v, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
+        else ntt_inv_f<Sh, false, LZB>(v, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
         const double p = K->pd[pi];
 #pragma unroll
         for (int u = 0; u < Sh::EPT; ++u) row.store(g, tid, u, fp_to_residue(v[u], p));

@@ -26,17 +26,21 @@ def _host(t):
     return t.cpu().numpy()
 
 
-def test_graph_replays_answer_new_queries():
+@pytest.mark.parametrize("defer", [1, 2], ids=["default", "deferred"])
+def test_graph_replays_answer_new_queries(defer):
+    """Mode 2 puts the root products' deferred key switch (accumulators cleared by a fill kernel,
+    digit sums relinearized once per answer) under capture."""
     import torch
     from oracle.client import encrypt_query
     from paper_2202_07569_amd import Context
     cfg = TINY64
     ins = cached_instance(cfg)
     ctx = Context(cfg.N, cfg.primes, cfg.t, chunk_elems=24)
+    ctx.defer_relin = defer
     key = ctx.load_key(ins.rlk)
     db = ctx.encode_db(ins.codewords, ins.payload, cfg.m)
     qbuf = torch.from_numpy(ins.query).cuda()
-    _say("graph capture tiny n=64")
+    _say(f"graph capture tiny n=64, deferral mode {defer}")
     g = ctx.capture([key], [db], [qbuf])
     want = ins.orc.answer(ins.key, ins.query, ins.codewords, ins.payload)
     assert np.array_equal(_host(g.outs[0]), want)  # the capture's own eager run
