@@ -1828,13 +1828,17 @@ void launch_scale(const Launch& lc, const uint64_t* X, uint64_t* out, uint32_t E
 // Key switching: sel = (c0 + sum_i D_i b_i, c1 + sum_i D_i a_i), transformed over Q.
 // rlk: [L][2][L][N] transformed values followed by [L][2][L][N] Shoup companions.
 // ---------------------------------------------------------------------------------------------
+// Workgroup b covers EW_THREADS coefficients of limb j of element-query eq, with eq varying fastest:
+// the workgroups running together (and those of one XCD, b mod 8) read the same slice of the key
+// limb (2L values and their companions per coefficient, 32 MB for the whole key at N = 16384),
+// which then comes from L2, and stream different staged digit rows.
 __global__ void k_relin_mac(const CtxConst* __restrict__ K, const uint64_t* __restrict__ R, const Batch bt) {
     const uint32_t N = K->N, L = K->L;
-    const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (gid >= (size_t)bt.nq * bt.E * L * N) return;
-    const size_t c = gid % N, ej = gid / N;
-    const uint32_t j = (uint32_t)(ej % L);
-    const size_t eq = ej / L;
+    const size_t EQ = (size_t)bt.nq * bt.E, b = blockIdx.x;
+    const size_t eq = b % EQ, rest = b / EQ;
+    const uint32_t j = (uint32_t)(rest % L);
+    const size_t c = (rest / L) * blockDim.x + threadIdx.x;
+    if (c >= N) return;
     const uint32_t q = (uint32_t)(eq / bt.E);
     const size_t e = eq % bt.E;
     const uint64_t* __restrict__ rlk = bt.rlk[q];
@@ -1857,8 +1861,8 @@ __global__ void k_relin_mac(const CtxConst* __restrict__ K, const uint64_t* __re
 
 void launch_relin_mac(const Launch& lc, const uint64_t* R, const Batch& bt) {
     if (!bt.E || !bt.nq) return;
-    hipLaunchKernelGGL(k_relin_mac, dim3(blocks_for((size_t)bt.nq * bt.E * lc.L * lc.N)), dim3(EW_THREADS), 0,
-                       lc.stream, lc.K, R, bt);
+    const size_t blocks = (size_t)bt.nq * bt.E * lc.L * ((lc.N + EW_THREADS - 1) / EW_THREADS);
+    hipLaunchKernelGGL(k_relin_mac, dim3((unsigned)blocks), dim3(EW_THREADS), 0, lc.stream, lc.K, R, bt);
 }
 
 // Shoup companions of a transformed key: comp[i] = floor(v[i] 2^64 / p) with p from the limb index.
