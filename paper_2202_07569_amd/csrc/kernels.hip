@@ -838,11 +838,26 @@ __global__ __launch_bounds__(Sh::T) void k_ntt_payload(const CtxConst* __restric
                                                        uint64_t* __restrict__ out, uint32_t nl, uint32_t dbase) {
     ntt_fwd_row<Sh, FP>(K, tw, twf, RowsPayload<Sh>{pay, out, nl, K->L, dbase});
 }
+// Staged digit transforms: row g = (e, i, j) of [E][L+2][L][N].  The L workgroups of one (e, i)
+// read the same digit row (reduced modulo each q_j while loading); xcd_split puts them on one XCD,
+// so the row comes from HBM once and from that XCD's L2 for the others.
 template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T) void k_ntt_digits(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
                                                       const double* __restrict__ twf, const uint64_t* __restrict__ c3,
-                                                      uint64_t* __restrict__ out) {
-    ntt_fwd_row<Sh, FP>(K, tw, twf, RowsDigits<Sh>{c3, out, K, K->L});
+                                                      uint64_t* __restrict__ out, size_t groups) {
+    __shared__ uint64_t sm[Sh::LDS_WORDS];
+    const uint32_t L = K->L, tid = threadIdx.x;
+    size_t grp;
+    uint32_t j;
+    xcd_split(blockIdx.x, L, grp, j);
+    if (grp >= groups) return;
+    const size_t g = grp * L + j;
+    const RowsDigits<Sh> row{c3, out, K, L};
+    uint64_t a[Sh::EPT];
+    row.load(g, tid, a);
+    ntt_fwd_regs<Sh, FP>(a, sm, tid, tw_row(tw, twf, j, Sh::N), K, j);
+#pragma unroll
+    for (int u = 0; u < Sh::EPT; ++u) row.store(g, tid, u, a[u]);
 }
 template <class Sh, bool FP>
 __global__ __launch_bounds__(Sh::T, Sh::LOGN == 13 ? 8 : 1) void k_ntt_inv_tensor(const CtxConst* __restrict__ K, const uint64_t* __restrict__ tw,
@@ -1555,8 +1570,8 @@ void launch_ntt_operand(const Launch& lc, const uint64_t* in, uint64_t* out, siz
 
 void launch_ntt_digits(const Launch& lc, const uint64_t* c3, uint64_t* out, uint32_t E) {
     if (!E) return;
-    const size_t rows = (size_t)E * (lc.L + 2) * lc.L;
-    CW_NTT_DISPATCH(lc, k_ntt_digits, dim3((unsigned)rows), lc.K, lc.tw, lc.twf, c3, out)
+    const size_t groups = (size_t)E * (lc.L + 2);
+    CW_NTT_DISPATCH(lc, k_ntt_digits, dim3((unsigned)xcd_grid(groups, lc.L)), lc.K, lc.tw, lc.twf, c3, out, groups)
 }
 
 void launch_ntt_inv_tensor(const Launch& lc, const uint32_t* refs, const Batch& bt, uint64_t* X, size_t eq0,
