@@ -264,7 +264,6 @@ def main():
     arith = arith_bench(args, ctx, key, cfg, torch, stream) if extras and args.workload == "mid" else None
 
     fp = cfg.N <= 8192 and all(p < FP_PRIME_BOUND for p in tuple(cfg.primes) + ctx.aux_primes)
-    k_ge2 = cfg.k >= 2
     roof = roofline(prof, prof_steps, fp, traffic_table(cfg, n, B, ctx.schedule())) if prof else None
     if roof is not None:
         roof["events_ms_per_step"] = t_bp / prof_steps * 1e3
@@ -285,8 +284,7 @@ def main():
                    "batch_queries": B},
         "schedule": {"batched": ctx.schedule(), "plain": ctx_plain.schedule(),
                      "source": {"batched": tune, "plain": tune_plain}},
-        "root_keyswitch": ("deferred past the inner product" if args.defer_relin and k_ge2 and
-                           (args.defer_relin == 2 or n * (cfg.L * cfg.L - 2 * cfg.L) >= 2048) else "per element"),
+        "root_keyswitch": "deferred past the inner product" if db.root_deferred else "per element",
         "plain": {"value": n * args.steps / t_plain, "unit": "elements/s", "ms_per_query": t_plain / args.steps * 1e3,
                   **lat(per_plain)} if extras else None,
         "plain_graph": {"value": n * args.steps / t_graph, "unit": "elements/s",

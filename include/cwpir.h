@@ -338,6 +338,10 @@ int pir_autotune(pir_ctx* ctx, uint32_t batch, uint32_t k, uint32_t s, pir_sched
 uint32_t pir_ctx_aux_primes(const pir_ctx* ctx, uint64_t* out_primes /* may be NULL */);
 uint64_t pir_ctx_device_bytes(const pir_ctx* ctx);       /* bytes the library holds on the device */
 uint64_t pir_db_pair_count(const pir_db* db);            /* distinct inner tree nodes (k >= 3)    */
+/* 1 when answers on this database relinearize the root products after the inner product
+ * (pir_set_defer_relin: the mode at encoding, the digit-sum bound and k >= 2), else 0 (also for a
+ * null database). */
+int pir_db_root_deferred(const pir_db* db);
 /* Transform shape variants of the context's ring degree (pir_schedule.ntt_shape), and the number
  * of stages of each pass of variant `shape` in order (stages: room for 8; returns the number of
  * passes, 0 for an unknown variant or a null argument).  Each pass runs its stages in registers;

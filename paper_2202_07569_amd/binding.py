@@ -26,6 +26,7 @@ EXPORTS = [
     "pir_folklore_leaves", "pir_arith_equality", "pir_serve_set_policy", "pir_seeded_query",
     "pir_serve_set_aging", "pir_probe_fp64", "pir_mod_switch_noalloc", "pir_check_query", "pir_probe_int",
     "pir_set_defer_relin", "pir_get_defer_relin", "pir_ntt_shape_count", "pir_ntt_shape_stages",
+    "pir_db_root_deferred",
 ]
 
 
@@ -81,6 +82,7 @@ def lib():
             "pir_ctx_aux_primes": (u32, [vp, vp]),
             "pir_ctx_device_bytes": (u64, [vp]),
             "pir_db_pair_count": (u64, [vp]),
+            "pir_db_root_deferred": (i32, [vp]),
             "pir_ntt_shape_count": (u32, [vp]),
             "pir_ntt_shape_stages": (u32, [vp, u32, ctypes.POINTER(ctypes.c_uint32)]),
             "pir_profile_enable": (i32, [vp, i32]),
@@ -196,6 +198,12 @@ class Database:
     @property
     def pair_count(self) -> int:
         return lib().pir_db_pair_count(self._h)
+
+    @property
+    def root_deferred(self) -> bool:
+        """Whether answers relinearize the root products after the inner product
+        (pir_db_root_deferred)."""
+        return bool(lib().pir_db_root_deferred(self._h))
 
     def close(self):
         if self._h:

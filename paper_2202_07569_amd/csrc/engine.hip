@@ -779,6 +779,10 @@ extern "C" void pir_db_free(pir_db* db) {
 
 extern "C" uint64_t pir_db_pair_count(const pir_db* db) { return db ? db->total_pairs : 0; }
 
+extern "C" int pir_db_root_deferred(const pir_db* db) {
+    return db && db->ctx && deferred(db->ctx, db) && db->k >= 2 ? 1 : 0;
+}
+
 // ------------------------------------------------------------------------------------------------
 // the path
 // ------------------------------------------------------------------------------------------------
@@ -918,17 +922,19 @@ static cw::RootPlan root_plan(const pir_ctx* ctx, uint32_t s, uint32_t nq, uint3
     // c0 / c1 limb j = j / L + j, digit i modulo deferred-switch prime a = 2L + i A + a (context
     // prime LL + a)
     const uint32_t LL = ctx->LL;
+    // the units of one digit (or digit pair) modulo the two primes are adjacent: their workgroups
+    // run side by side on one XCD (xcd_split) and read the digit rows once from HBM
     if (s == 1) {
         for (uint32_t j = 0; j < L; ++j) add(j, j, L + j, L + j, true, j, 0, 1);
-        for (uint32_t a = 0; a < ROOT_A; ++a)
-            for (uint32_t i = 0; i < L; i += 2)
+        for (uint32_t i = 0; i < L; i += 2)
+            for (uint32_t a = 0; a < ROOT_A; ++a)
                 add(2 * L + i, 2 * L + i * ROOT_A + a, 2 * L + i + 1, 2 * L + (i + 1) * ROOT_A + a, i + 1 < L, LL + a, 0, 1);
     } else {
         for (uint32_t r0 = 0; r0 < s; r0 += 2) {
             const uint32_t nr = std::min<uint32_t>(2, s - r0);
             for (uint32_t j = 0; j < 2 * L; ++j) add(j, j, 0, 0, false, j % L, r0, nr);
-            for (uint32_t a = 0; a < ROOT_A; ++a)
-                for (uint32_t i = 0; i < L; ++i) add(2 * L + i, 2 * L + i * ROOT_A + a, 0, 0, false, LL + a, r0, nr);
+            for (uint32_t i = 0; i < L; ++i)
+                for (uint32_t a = 0; a < ROOT_A; ++a) add(2 * L + i, 2 * L + i * ROOT_A + a, 0, 0, false, LL + a, r0, nr);
         }
     }
     rp.lazy = 1;  // lazy transforms when every ciphertext prime is below 2^48 (the D primes are)

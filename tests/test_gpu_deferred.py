@@ -117,10 +117,18 @@ def test_mode_switch_rules():
     ctx.defer_relin = 0
     assert ctx.defer_relin == 0
     db = ctx.encode_db(ins.codewords, ins.payload, cfg.m)
+    assert not db.root_deferred
     with pytest.raises(PirError):
         ctx.defer_relin = 2
     db.close()
     ctx.defer_relin = 2
     assert ctx.defer_relin == 2
+    db = ctx.encode_db(ins.codewords, ins.payload, cfg.m)
+    assert db.root_deferred  # k = 2, and eight elements fit the digit-sum bound
+    db.close()
+    ctx.defer_relin = 1
+    db = ctx.encode_db(ins.codewords, ins.payload, cfg.m)
+    assert not db.root_deferred  # too small to repay the per-answer work
+    db.close()
     with pytest.raises(PirError):
         ctx.defer_relin = 3

@@ -89,6 +89,7 @@ def test_schedule_calls_reject_null_context():
     assert "null context" in L.pir_last_error().decode()
     st = (ctypes.c_uint32 * 8)()
     assert L.pir_ntt_shape_count(None) == 0
+    assert L.pir_db_root_deferred(None) == 0
     assert L.pir_ntt_shape_stages(None, 0, st) == 0
 
 
