@@ -86,7 +86,7 @@ struct pir_ctx {
     std::map<std::string, ProfAcc> prof_acc;
     std::map<std::pair<uint32_t, uint32_t>, uint64_t*> binom;  // (m, k) -> device table
     std::map<uint32_t, cw::SwitchConst*> switches;            // keep -> device switch constants
-    uint32_t xslab = 0;       // element-queries per tensor + scale launch (X stays in the Infinity Cache)
+    uint32_t xslab = 0;       // most element-queries per tensor + scale launch (bounds the X buffer)
     int defer_mode = 1;       // root key switch after the inner product: 0 never, 1 where it pays, 2 where allowed
     bool crt_ok = false;      // the two primes of the deferred key switch exist
     cw::CrtConst crt{};
@@ -730,7 +730,7 @@ extern "C" int pir_encode_db(pir_ctx* ctx, uint64_t n, uint32_t s, uint32_t m, u
         typedef unsigned __int128 u128;
         uint64_t maxq = 0;
         for (uint32_t i = 0; i < ctx->L; ++i) maxq = std::max(maxq, ctx->primes[i]);
-        const u128 bound = (u128)std::max<uint64_t>(n, 1) * ctx->N * maxq;  // n < 2^40, N <= 2^14, q < 2^50
+        const u128 bound = (u128)std::max<uint64_t>(n, 1) * ctx->N * maxq;  // n < 2^40, N <= 2^14, q < 2^62
         const u128 prod = (u128)ctx->primes[ctx->LL] * ctx->primes[ctx->LL + 1];
         db->defer_ok = bound < (prod >> 17) && root_units(ctx, s) <= (uint32_t)cw::ROOT_MAX_UNITS;  // 2 bound 2^16 < b0 b1
         const uint64_t L = ctx->L;

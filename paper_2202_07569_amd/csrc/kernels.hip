@@ -280,7 +280,8 @@ __device__ __forceinline__ void fwd_pass_fp(double* a, uint32_t tid, const doubl
 // all-sum chain's entry bound 2^rp, which is checked against cap = 2^53 / p_max.
 // LZ = 1: any prime below 2^50 (c = 3/8, cap 8), thr 0.6 (every register reduced between passes,
 //         none before the first: the inputs are tensor products, below 1.4 p);
-// LZ = 2: primes below 2^44 (c = 3/512, cap 512), thr 32 (one register reduced in a transform).
+// LZ = 2: primes below 2^44 (c = 3/512, cap 512), thr 32 (one or two registers reduced in a whole
+//         transform, depending on the shape).
 struct InvLazy {
     double c, cap, thr, a0;
 };
