@@ -796,11 +796,24 @@ struct Bufs {
 
 // Elements per workgroup of the deferred key switch: enough workgroups for four per compute unit,
 // and slices of at most 64 elements.
+// A root workgroup runs alone on its compute unit (its exchange buffer and twiddle copy fill the
+// LDS; at N = 4096 two fit), so a launch takes ceil(workgroups / resident) rounds of one
+// workgroup's time, which grows with the slice (plus about one element's worth of set-up: the
+// twiddle copy, the first row, the sums written out).  The slice minimises that product; among
+// equal costs the longer slice writes fewer partial sums.
 static uint32_t root_slice(const pir_ctx* ctx, uint32_t E, uint32_t nq, uint32_t units) {
-    const uint64_t want = 4ull * std::max<uint32_t>(ctx->cus, 1);
+    const uint64_t resident = (uint64_t)std::max<uint32_t>(ctx->cus, 1) * (ctx->fp && ctx->N == 4096 ? 2 : 1);
     const uint64_t per = (uint64_t)nq * units;
-    uint64_t slice = ((uint64_t)E * per) / want;
-    return (uint32_t)std::min<uint64_t>(64, std::max<uint64_t>(1, slice));
+    uint64_t best = 1, best_cost = ~0ull;
+    for (uint64_t slice = 1; slice <= 64; ++slice) {
+        const uint64_t groups = ((uint64_t)std::max<uint32_t>(E, 1) + slice - 1) / slice * per;
+        const uint64_t cost = (groups + resident - 1) / resident * (slice + 1);
+        if (cost <= best_cost) {
+            best_cost = cost;
+            best = slice;
+        }
+    }
+    return (uint32_t)best;
 }
 
 // Work buffers for launches over up to `nq` queries of E elements each.
