@@ -335,11 +335,21 @@ def roofline(prof, steps, fp, traffic):
     MULS_PER_BUTTERFLY 32-bit multiplies; fp64 path (every prime below 2^50): FP64_OPS_PER_BUTTERFLY
     fp64 instructions.  peak = the unit's rate / that count; achieved = algorithmic butterflies of
     one launch (rows x N/2 x log2 N) / the launch's average duration from HIP events on its stream.
+    Every family also gets its fraction of the butterfly roof (transform families) and, where the
+    committed counter summary has its bytes per launch, its HBM rate and fraction of 8 TB/s.
     """
     name, (tot_ms, launches, work) = max(prof.items(), key=lambda kv: kv[1][0])
     avg_ms = tot_ms / launches
     fam = {k: {"ms_per_step": v[0] / steps, "launches_per_step": v[1] / steps,
                "work_per_s": (v[2] / (v[0] * 1e-3)) if v[0] else None} for k, v in sorted(prof.items())}
+    bfly_peak = (MI355X_FP64_INSTR_PER_S / FP64_OPS_PER_BUTTERFLY) if fp else (MI355X_INT_MUL_PER_S / MULS_PER_BUTTERFLY)
+    for k, v in fam.items():  # every family's fraction of its roof: butterflies, and HBM where counted
+        if k in NTT_FAMILIES and v["work_per_s"]:
+            v["alu_frac"] = v["work_per_s"] / bfly_peak
+        tr = traffic.get(k, {}).get("bytes_per_launch") if traffic else None
+        if tr and v["launches_per_step"]:
+            gbps = tr / (v["ms_per_step"] / v["launches_per_step"] * 1e-3) / 1e9
+            v.update({"hbm_GBps": gbps, "hbm_frac": gbps / MI355X_HBM_GBPS})
     out = {"kernel": name, "avg_launch_ms": avg_ms, "launches_per_step": launches / steps, "families": fam}
     if name in NTT_FAMILIES:
         per_launch = work / launches

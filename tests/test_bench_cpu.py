@@ -88,3 +88,9 @@ def test_roofline_arithmetic():
     assert r["traffic"] == 1.2e9 and r["hbm_GBps_at_traffic"] == pytest.approx(1.2e9 / 6e-3 / 1e9)
     assert r["launches_per_step"] == 50
     assert bench.roofline(prof, 2, True, None)["traffic"] is None
+    # every family: its fraction of the butterfly roof (transforms) and of HBM (where counted)
+    fam = r["families"]
+    assert fam["relin"]["alu_frac"] == pytest.approx(achieved / peak)
+    assert fam["relin"]["hbm_GBps"] == pytest.approx(1.2e9 / 6e-3 / 1e9)
+    assert fam["relin"]["hbm_frac"] == pytest.approx(1.2e9 / 6e-3 / 8e12)
+    assert "alu_frac" not in fam["scale"] and "hbm_frac" not in fam["scale"]
