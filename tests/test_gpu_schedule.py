@@ -77,6 +77,11 @@ def test_every_ntt_shape_gives_identical_answers(defer):
     from paper_2202_07569_amd import PirError
     with pytest.raises(PirError):
         ctx.set_schedule(24, 2, 0, len(shapes))
+    tiny = datagen.CONFIGS["tiny"]
+    t = Context(tiny.N, tiny.primes, tiny.t)
+    assert t.ntt_shapes() == [[3, 3, 3, 3]]  # one shape at N = 4096
+    with pytest.raises(PirError):
+        t.set_schedule(24, 2, 0, 1)
 
 
 def test_keyword_parameters_under_both_shapes():
