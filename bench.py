@@ -79,6 +79,9 @@ def parse():
     ap.add_argument("--serve-rates", default="0.8,2.0",
                     help="arrival rates as multiples of 1/S (S: mean plain service time): below and above capacity")
     ap.add_argument("--serve-slots", type=int, default=32)
+    ap.add_argument("--serve-schedule", default="cache", choices=["cache", "default"],
+                    help="launch schedule of the serving context: the tuning cache's for the mid parameters "
+                         "in batches of 8, or the library default")
     ap.add_argument("--serve-only", action="store_true", help="skip the mid workload")
     ap.add_argument("--probe", action="store_true",
                     help="only the fp64 issue-rate probe (pir_probe_fp64): wave-instructions per CU per clock")
@@ -559,6 +562,13 @@ def serve_bench(args, torch):
     cfgs = datagen.batched_configs()
     c0 = cfgs[0]
     ctx = Context(c0.N, c0.primes, c0.t, hbm_budget_bytes=96 << 30)
+    # the launch schedule the tuning cache holds for these parameters in batches of 8 (the plain
+    # loop and the server share the context, so both run it)
+    cached = ctx.cached_schedule(8, 4, 1)
+    if cached is not None and args.serve_schedule == "cache":
+        ctx.set_schedule(cached["chunk_elems"], cached["query_group"], cached["relin_group"],
+                         cached.get("ntt_shape", 0))
+    log(f"serving schedule ({args.serve_schedule}): {ctx.schedule()}")
     keys = [ctx.load_key(datagen.uniform_residues(c0.primes, (c0.L, 2), c0.N, seed=c0.seed * 100 + 1 + i))
             for i in range(2)]
     dbs, pools = [], []
@@ -650,7 +660,8 @@ def serve_bench(args, torch):
                        + ", ".join(f"({c.n}, {c.s}, {c.k})" for c in cfgs)
                        + f"; N={c0.N}, {c0.L} primes, t={c0.t}; {Q} queries, uniform database choice, "
                          f"{len(keys)} keys",
-           "plain_service_ms": [x * 1e3 for x in svc], "S_ms": S * 1e3, "slots": args.serve_slots, "rates": []}
+           "plain_service_ms": [x * 1e3 for x in svc], "S_ms": S * 1e3, "slots": args.serve_slots,
+           "schedule": {k: v for k, v in ctx.schedule().items() if k != "ns_per_elem"}, "rates": []}
     for mult in [float(x) for x in args.serve_rates.split(",")]:
         rate = mult / S
         arr = datagen.poisson_arrivals(seed + int(mult * 1000), Q, rate)
