@@ -1424,7 +1424,7 @@ __global__ void k_root_reduce(const CtxConst* __restrict__ K, const uint64_t* __
     if (gid >= per * rp.nq) return;
     const uint32_t q = (uint32_t)(gid / per);
     const size_t x = gid % per;
-    const uint32_t row = (uint32_t)((x / N) % rp.RR);
+    const uint32_t row = (uint32_t)((x >> K->logN) % rp.RR);  // N is a power of two
     const uint32_t pi = row < 2 * L ? row % L : K->LL + (row - 2 * L) % rp.A;
     const uint64_t p = K->p[pi];
     uint64_t a = qp.acc[q][x];
@@ -1444,7 +1444,7 @@ __global__ void k_root_crt(const CtxConst* __restrict__ K, const CrtConst cc, co
     const uint32_t N = K->N, L = K->L;
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (size_t)s * L * N) return;
-    const size_t c = gid % N, ri = gid / N;  // ri = r L + i
+    const size_t c = gid & (N - 1), ri = gid >> K->logN;  // ri = r L + i (N is a power of two)
     const uint64_t b0 = K->p[K->LL], b1 = K->p[K->LL + 1];
     const uint64_t w0 = Wc[(ri * 2 + 0) * N + c], w1 = Wc[(ri * 2 + 1) * N + c];
     // t = (w1 - w0) b0^-1 mod b1; w0 < b0 < 2 b1
@@ -1477,8 +1477,8 @@ __global__ void k_root_combine(const CtxConst* __restrict__ K, const uint64_t* _
     const size_t LN = (size_t)L * N;
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (size_t)s * 2 * LN) return;
-    const size_t c = gid % N;
-    const uint32_t j = (uint32_t)((gid / N) % L);
+    const size_t c = gid & (N - 1);
+    const uint32_t j = (uint32_t)((gid >> K->logN) % L);
     const uint32_t poly = (uint32_t)((gid / LN) % 2);
     const uint32_t r = (uint32_t)(gid / (2 * LN));
     const uint64_t p = K->p[j], mu = K->bar_mu[j];
@@ -1620,7 +1620,7 @@ __global__ void k_extend(const CtxConst* __restrict__ K, const uint64_t* __restr
     const uint32_t N = K->N, L = K->L, LL = K->LL;
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= G * N) return;
-    const size_t g = gid / N, c = gid % N;
+    const size_t g = gid >> K->logN, c = gid & (N - 1);  // N is a power of two
     if (extend_coeff<NL>(K, in + g * L * N + c, N, out + g * LL * N + c, N, false, write_q != 0))
         fix[atomicAdd(fixcnt, 1u)] = gid;
 }
@@ -1632,7 +1632,7 @@ __global__ void k_extend_fix(const CtxConst* __restrict__ K, const uint64_t* __r
     const uint32_t n = *fixcnt;
     for (uint32_t f = threadIdx.x; f < n; f += blockDim.x) {
         const size_t gid = fix[f];
-        const size_t g = gid / N, c = gid % N;
+        const size_t g = gid >> K->logN, c = gid & (N - 1);
         extend_coeff<NL>(K, in + g * L * N + c, N, out + g * LL * N + c, N, true, write_q != 0);
     }
     __syncthreads();
@@ -1663,7 +1663,7 @@ __global__ void k_operand_q_rows(const CtxConst* __restrict__ K, const uint64_t*
     const uint32_t N = K->N, L = K->L, LL = K->LL;
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= G * L * N) return;
-    const size_t c = gid % N, gj = gid / N;
+    const size_t c = gid & (N - 1), gj = gid >> K->logN;  // N is a power of two
     const uint32_t j = (uint32_t)(gj % L);
     const size_t g = gj / L;
     const uint64_t x = in[gid];
@@ -1786,7 +1786,7 @@ __global__ void k_scale(const CtxConst* __restrict__ K, const uint64_t* __restri
     const uint32_t N = K->N, LL = K->LL;
     const size_t gid = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (gid >= (size_t)E * 3 * N) return;
-    const size_t c = gid % N, er = gid / N;
+    const size_t c = gid & (N - 1), er = gid >> K->logN;  // N is a power of two
     uint64_t cq[NL];
     bool amb;
     if constexpr (FP) amb = scale_coeff_fp<NL, NB, EX>(K, X + er * LL * N + c, N, cq);
@@ -1802,7 +1802,7 @@ __global__ void k_scale_fix(const CtxConst* __restrict__ K, const uint64_t* __re
     const uint32_t n = *fixcnt;
     for (uint32_t f = threadIdx.x; f < n; f += blockDim.x) {
         const size_t gid = fix[f];
-        const size_t c = gid % N, er = gid / N;
+        const size_t c = gid & (N - 1), er = gid >> K->logN;
         uint64_t cq[NL];
         scale_coeff<NL, NB>(K, X + er * LL * N + c, N, cq, true);
         scale_store<NL>(K, cq, out, er, c);
@@ -1917,7 +1917,7 @@ __global__ void k_gather_leaf(const CtxConst* __restrict__ K, const uint32_t* __
     if (gid >= (size_t)bt.nq * per) return;
     const uint32_t q = (uint32_t)(gid / per);
     const size_t gq = gid % per;
-    const size_t c = gq % N, rest = gq / N;
+    const size_t c = gq & (N - 1), rest = gq >> K->logN;  // N is a power of two
     const uint32_t j = (uint32_t)(rest % L);
     const size_t ep = rest / L;
     const uint32_t poly = (uint32_t)(ep % 2);
