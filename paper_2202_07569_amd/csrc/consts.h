@@ -56,8 +56,12 @@ struct CtxConst {
     uint64_t kb1[MAX_LB], kb1q[MAX_LB];          // [t q^{-1} (B/b_j)^{-1} N^{-1}]_{b_j} (likewise)
     uint64_t kb2[MAX_LB], kb2q[MAX_LB];          // [q^{-1} (B/b_j)^{-1}]_{b_j}
     double tqinvd[MAX_L], kb1d[MAX_LB], kb2d[MAX_LB];  // the same constants as doubles (fp64 path)
-    // fp64 scale with the key constant folded into the Q -> B conversion:
-    //   z_j = kb1_j x_j + sum_i y_i [-kb2_j (q/q_i)]_{b_j} + v [kb2_j q]_{b_j}   (mod b_j)
+    // fp64 path: the tensor products' inverse transform multiplies row k by foldd[k] (tqinv_k for Q,
+    // kb1_{k-L} for B, 1 for the digit-sum primes), so the scale kernel reads y_i and kb1_j x_j
+    // directly; with the key constant folded into the Q -> B conversion it then forms
+    //   z_j = [kb1_j x_j] + sum_i y_i [-kb2_j (q/q_i)]_{b_j} + v [kb2_j q]_{b_j}   (mod b_j),
+    // the last constant centred (|fqpd| < b_j / 2), so that v fqpd is an exact double product.
+    double foldd[MAX_LL];
     double fqbd[MAX_L][MAX_LB], fqpd[MAX_LB];
     ConvTable qb;                                // q -> B
     ConvTable bq;                                // B -> q

@@ -416,7 +416,7 @@ extern "C" int pir_setup(const pir_params* params, pir_ctx** out) {
     std::vector<uint64_t> tw;
     std::vector<double> twf;
     cw::host::build_twiddles(tw, ctx->primes, ctx->N);
-    if (fp) cw::host::build_twiddles_fp(twf, tw, ctx->primes, ctx->N);
+    if (fp) cw::host::build_twiddles_fp(twf, tw, ctx->primes, ctx->N, ctx->K);
     int rc;
     if ((rc = dev_alloc(ctx, (void**)&ctx->dK, sizeof(CtxConst))) != PIR_OK) return cleanup(rc);
     if ((rc = dev_alloc(ctx, (void**)&ctx->dtw, tw.size() * 8)) != PIR_OK) return cleanup(rc);

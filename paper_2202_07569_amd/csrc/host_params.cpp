@@ -227,8 +227,12 @@ void build_const(CtxConst& K, uint32_t N, const std::vector<uint64_t>& q, const 
     for (uint32_t j = 0; j < K.LB; ++j) {
         const uint64_t b = B[j];
         for (uint32_t i = 0; i < K.L; ++i) K.fqbd[i][j] = (double)mulmod(b - K.kb2[j], K.qb.M[i][j], b);
-        K.fqpd[j] = (double)mulmod(K.kb2[j], K.qb.Pm[j], b);
+        const uint64_t f = mulmod(K.kb2[j], K.qb.Pm[j], b);
+        K.fqpd[j] = f > b / 2 ? -(double)(b - f) : (double)f;  // centred
     }
+    for (uint32_t k = 0; k < cw::MAX_LL; ++k) K.foldd[k] = 1.0;
+    for (uint32_t i = 0; i < K.L; ++i) K.foldd[i] = K.tqinvd[i];
+    for (uint32_t j = 0; j < K.LB; ++j) K.foldd[K.L + j] = K.kb1d[j];
 }
 
 void build_switch(SwitchConst& S, const std::vector<uint64_t>& q, uint32_t keep) {
@@ -271,17 +275,18 @@ static uint32_t bitrev(uint32_t x, uint32_t logn) {
 }
 
 void build_twiddles_fp(std::vector<double>& twf, const std::vector<uint64_t>& tw, const std::vector<uint64_t>& primes,
-                       uint32_t N) {
+                       uint32_t N, const CtxConst& K) {
     twf.assign(tw.size(), 0.0);
     for (size_t k = 0; k < primes.size(); ++k) {
-        const double p = (double)primes[k];
+        const uint64_t p = primes[k];
+        const uint64_t f = k < K.L ? K.tqinv[k] : k < K.LL ? K.kb1[k - K.L] : 1;  // the fold constant
         const uint64_t* src = tw.data() + k * 4 * (size_t)N;
         double* dst = twf.data() + k * 4 * (size_t)N;
         for (uint32_t i = 0; i < N; ++i) {
             dst[i] = (double)src[i];                          // exact: below 2^53
-            dst[N + i] = (double)src[i] / p;                  // w / p, correctly rounded
+            dst[N + i] = (double)src[i] / (double)p;          // w / p, correctly rounded
             dst[2 * N + i] = (double)src[2 * N + i];
-            dst[3 * N + i] = (double)src[2 * N + i] / p;
+            dst[3 * N + i] = (double)mulmod(src[2 * N + i], f, p);  // w_inv times the prime's fold constant
         }
     }
 }

@@ -28,9 +28,10 @@ void build_const(CtxConst& K, uint32_t N, const std::vector<uint64_t>& q, const 
 std::vector<uint64_t> primes_below(uint32_t N, uint64_t below, uint32_t count, const std::vector<uint64_t>& avoid);
 // [prime][4][N]: psi^bitrev(i), its Shoup companion, psi^-bitrev(i), its Shoup companion.
 void build_twiddles(std::vector<uint64_t>& tw, const std::vector<uint64_t>& primes, uint32_t N);
-// The same tables as doubles: [prime][4][N] = w, w/p, w_inv, w_inv/p (fp64 transform).
+// The same tables as doubles: [prime][4][N] = w, w/p, w_inv, [w_inv f]_p (fp64 transform), where f
+// is the prime's fold constant (K.foldd: tqinv for Q, kb1 for B, 1 for the digit-sum primes).
 void build_twiddles_fp(std::vector<double>& twf, const std::vector<uint64_t>& tw, const std::vector<uint64_t>& primes,
-                       uint32_t N);
+                       uint32_t N, const CtxConst& K);
 std::vector<uint64_t> binom_table(uint32_t m, uint32_t k);
 // Constants of the switch from q to its first `keep` primes.
 void build_switch(SwitchConst& S, const std::vector<uint64_t>& q, uint32_t keep);

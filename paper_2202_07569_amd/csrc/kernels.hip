@@ -330,29 +330,35 @@ __host__ __device__ constexpr bool inv_lazy_exact(int LZ) {
     return true;
 }
 
-template <class Sh, int P, int LZ = 0>
+// FOLD (first pass only): the transform's first stage also multiplies by the constant f, the upper
+// output as fmulmod(X + Y, f) and the lower one through the twiddle row [w_inv f]_p that follows the
+// inverse twiddles (tw + N); by linearity the whole transform then returns f times its result.
+// Both products stay within the bounds the lazy schedules assume for X + Y and (X - Y) w.
+template <class Sh, int P, int LZ = 0, bool FOLD = false>
 __device__ __forceinline__ void inv_pass_fp(double* a, uint32_t tid, const double* __restrict__ tw, double p,
-                                            double pinv) {
+                                            double pinv, double f = 1.0) {
     using G = PassGeo<Sh, P>;
     static_assert(G::rp <= 3, "the fp64 bound needs passes of at most three stages");
     static_assert(LZ == 0 || inv_lazy_exact<Sh>(LZ), "the lazy inverse transform would leave the exact range");
+    static_assert(!FOLD || P == Sh::NP - 1, "the fold belongs to the first stage");
     if constexpr (LZ == 0) {
 #pragma unroll
         for (int u = 0; u < Sh::EPT; ++u) a[u] = fred(a[u], p, pinv);
     }
 #pragma unroll
     for (int sp = G::rp - 1; sp >= 0; --sp) {
+        const bool fold = FOLD && sp == G::rp - 1;
         const int s = G::S0 + sp;
         const int pb = G::x + G::rp - 1 - sp;
         const uint32_t tb = (1u << s) + (elem_index<Sh, P>(tid, 0u) >> (Sh::LOGN - s));
-        const double* __restrict__ ts = tw + tb;
+        const double* __restrict__ ts = tw + (fold ? Sh::N : 0) + tb;
 #pragma unroll
         for (int u0 = 0; u0 < Sh::EPT; ++u0) {
             if (u0 & (1 << pb)) continue;
             const int u1 = u0 | (1 << pb);
             const uint32_t c = elem_index<Sh, P>(0u, (uint32_t)u0) >> (Sh::LOGN - s);
             const double X = a[u0], Y = a[u1];
-            a[u0] = X + Y;
+            a[u0] = fold ? fmulmod(X + Y, f, p, pinv) : X + Y;
             a[u1] = fmulmod(X - Y, ts[c], p, pinv);
         }
     }
@@ -456,15 +462,16 @@ __device__ __forceinline__ void fwd_passes(void* av, void* smv, uint32_t tid, Tw
     }
 }
 
-template <class Sh, bool FP, int P, int LZ = 0>
+template <class Sh, bool FP, int P, int LZ = 0, bool FOLD = false>
 __device__ __forceinline__ void inv_passes(void* av, void* smv, uint32_t tid, TwRow tw, const CtxConst* K,
                                            uint32_t pi) {
     if constexpr (FP) {
         double* a = (double*)av;
-        inv_pass_fp<Sh, P, LZ>(a, tid, tw.f + 2 * Sh::N, K->pd[pi], K->pinv[pi]);
+        constexpr bool F = FOLD && P == Sh::NP - 1;
+        inv_pass_fp<Sh, P, LZ, F>(a, tid, tw.f + 2 * Sh::N, K->pd[pi], K->pinv[pi], F ? K->foldd[pi] : 1.0);
         if constexpr (P > 0) {
             exchange<Sh, P, P - 1, P == Sh::NP - 1>(a, (double*)smv, tid);
-            inv_passes<Sh, FP, P - 1, LZ>(av, smv, tid, tw, K, pi);
+            inv_passes<Sh, FP, P - 1, LZ, FOLD>(av, smv, tid, tw, K, pi);
         }
     } else {
         uint64_t* a = (uint64_t*)av;
@@ -496,10 +503,11 @@ __device__ __forceinline__ void ntt_fwd_f(double* v, uint64_t* sm, uint32_t tid,
 }
 // NINV = false leaves out the factor N^-1 (the caller folds it into a later constant).  LZ > 0:
 // the lazy schedules of inv_pass_fp (inputs below 1.4 p; LZ = 2 only for primes below 2^44).
-template <class Sh, bool NINV = true, int LZ = 0>
+// FOLD: the result is multiplied by the prime's fold constant K->foldd[pi] (see inv_pass_fp).
+template <class Sh, bool NINV = true, int LZ = 0, bool FOLD = false>
 __device__ __forceinline__ void ntt_inv_f(double* v, uint64_t* sm, uint32_t tid, TwRow tw, const CtxConst* K,
                                           uint32_t pi) {
-    inv_passes<Sh, true, Sh::NP - 1, LZ>(v, sm, tid, tw, K, pi);
+    inv_passes<Sh, true, Sh::NP - 1, LZ, FOLD>(v, sm, tid, tw, K, pi);
     const double p = K->pd[pi], pinv = K->pinv[pi], ni = K->ninvd[pi];
 #pragma unroll
     for (int u = 0; u < Sh::EPT; ++u) v[u] = NINV ? fred(fmulmod(v[u], ni, p, pinv), p, pinv) : fred(v[u], p, pinv);
@@ -878,15 +886,16 @@ __global__ __launch_bounds__(Sh::T, Sh::LOGN == 13 ? 8 : 1) void k_ntt_inv_tenso
     const uint32_t tid = threadIdx.x;
     const uint32_t pi = row.prime(g);
     // X leaves without the transform's factor N^-1: the scale kernels, its only readers, take it
-    // with their first constants (tqinv, kb1).  The tensor products enter below 1.4 p, so the
-    // inverse transform takes a lazy schedule (rows modulo primes below 2^44 almost unreduced).
+    // with their first constants (tqinv, kb1), which the fp64 transform multiplies in at its first
+    // stage (X row k holds [f_k x]_{p_k}, f = K->foldd).  The tensor products enter below 1.4 p, so
+    // the inverse transform takes a lazy schedule (rows modulo primes below 2^44 almost unreduced).
     if constexpr (FP) {
         double v[Sh::EPT];
         row.load_f(g, tid, v);
         constexpr int LZB = inv_lazy_exact<Sh>(1) ? 1 : 0;    // a first pass of three stages from 1.4 p
         constexpr int LZQ = inv_lazy_exact<Sh>(2) ? 2 : LZB;  // would reach 11.2 p, beyond 8 p below 2^50
-        if (K->pd[pi] < 0x1p44) ntt_inv_f<Sh, false, LZQ>(v, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
-        else ntt_inv_f<Sh, false, LZB>(v, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
+        if (K->pd[pi] < 0x1p44) ntt_inv_f<Sh, false, LZQ, true>(v, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
+        else ntt_inv_f<Sh, false, LZB, true>(v, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
         const double p = K->pd[pi];
 #pragma unroll
         for (int u = 0; u < Sh::EPT; ++u) row.store(g, tid, u, fp_to_residue(v[u], p));
@@ -1685,15 +1694,16 @@ void launch_operand_q_rows(const Launch& lc, const uint64_t* in, uint64_t* out, 
 // ---------------------------------------------------------------------------------------------
 // Exact scale-and-round of a coefficient-form tensor product X over Q u B:
 //   r = [t X]_q (centred, exact Q -> B), y = (t X - r) / q in B, c = y (exact centred B -> Q).
-// Output: coefficient form [E][3][L][N].
+// Output: coefficient form [E][3][L][N].  PRE: X row k already holds [f_k X]_{p_k} with the first
+// constants f (tqinv for Q, kb1 for B), as the fp64 tensor transform leaves it.
 // ---------------------------------------------------------------------------------------------
-template <int NL, int NB>
+template <int NL, int NB, bool PRE>
 __device__ __forceinline__ bool scale_coeff(const CtxConst* K, const uint64_t* x, size_t xs, uint64_t* cq, bool exact) {
     const uint32_t L = K->L, LB = K->LB;
     uint64_t y[NL];
 #pragma unroll
     for (int i = 0; i < NL; ++i)
-        if (i < (int)L) y[i] = mul_shoup(x[i * xs], K->tqinv[i], K->tqinvq[i], K->p[i]);
+        if (i < (int)L) y[i] = PRE ? x[i * xs] : mul_shoup(x[i * xs], K->tqinv[i], K->tqinvq[i], K->p[i]);
     bool amb = false;
     const uint32_t v = exact ? conv_round_exact(K->qb, y) : conv_round_fast<NL>(K->qb, y, L, amb);
     uint64_t z[NB];
@@ -1703,7 +1713,7 @@ __device__ __forceinline__ bool scale_coeff(const CtxConst* K, const uint64_t* x
             const uint64_t b = K->p[L + j];
             const uint64_t rb = conv_out<NL>(K->qb, y, L, v, j);
             const uint64_t xb = x[(L + j) * xs];
-            z[j] = sub_mod(mul_shoup(xb, K->kb1[j], K->kb1q[j], b), mul_shoup(rb, K->kb2[j], K->kb2q[j], b), b);
+            z[j] = sub_mod(PRE ? xb : mul_shoup(xb, K->kb1[j], K->kb1q[j], b), mul_shoup(rb, K->kb2[j], K->kb2q[j], b), b);
         }
     const uint32_t v2 = exact ? conv_round_exact(K->bq, z) : conv_round_fast<NB>(K->bq, z, LB, amb);
 #pragma unroll
@@ -1712,25 +1722,28 @@ __device__ __forceinline__ bool scale_coeff(const CtxConst* K, const uint64_t* x
     return amb;
 }
 
-// fp64 form (every prime below 2^50): the same conversions on signed representatives.  The
-// rounding decisions v, v2 come from double sums whose error is below 2^-45; a sum within 2^-40
-// of a half is reported as ambiguous and the exact integer form redoes the coefficient.  The key
-// constant kb2 is folded into the Q -> B products (fqbd, fqpd), so z_j is one sum of L + 2 products;
-// every product is below 0.7 b in magnitude, so sums of up to 7 of them stay below 2^53 (b < 2^50)
-// and are reduced once.
+// fp64 form (every prime below 2^50; X as the fp64 tensor transform leaves it, PRE above): the same
+// conversions on doubles.  y_i in [0, q_i), so S = sum y_i / q_i lies in [0, L) and v in [0, L].  The
+// rounding decisions v, v2 come from double sums whose error is below 2^-45; a sum within 2^-40 of a
+// half is reported as ambiguous and the exact integer form redoes the coefficient.  The key constant
+// kb2 is folded into the Q -> B products (fqbd, fqpd), so z_j is the input [kb1 x_j] (below b), L
+// products (each below (1/2 + 3 q_i 2^-53) b <= 0.875 b in magnitude) and v fqpd, an exact product
+// (|fqpd| < b/2): for L <= 5 the sum stays below (1 + 1.375 L) b < 2^53 (b < 2^50) and is reduced
+// once.  The outputs take -v2 [B]_{q_i}, exact as well (|v2| <= (LB + 1)/2, B mod q_i below q_i),
+// and LB products below 0.69 q_i (|z_j| <= b/2 < 2^49): for LB <= 6 below 8 q_i.  The general form
+// (EX = false) reduces the two exact products and every few sums.
 #pragma clang fp contract(off)
 template <int NL, int NB, bool EX>
 __device__ __forceinline__ bool scale_coeff_fp(const CtxConst* K, const uint64_t* x, size_t xs, uint64_t* cq) {
     const uint32_t L = EX ? NL : K->L, LB = EX ? NB : K->LB;
-    static_assert(!EX || (NL + 2 <= 7 && NB + 1 <= 7), "the single-reduction bound covers 7 products");
+    static_assert(!EX || (NL <= 5 && NB <= 6), "the single-reduction bounds");
     double y[NL];
     double S = 0.0;
 #pragma unroll
     for (int i = 0; i < NL; ++i)
         if (i < (int)L) {
-            const double p = K->pd[i], pinv = K->pinv[i];
-            y[i] = fmulmod(u52_to_double(x[i * xs]), K->tqinvd[i], p, pinv);
-            S += y[i] * pinv;
+            y[i] = u52_to_double(x[i * xs]);
+            S += y[i] * K->pinv[i];
         }
     const double v = __builtin_rint(S);
     bool amb = __builtin_fabs(S - v) > 0.5 - 0x1p-40;
@@ -1741,8 +1754,8 @@ __device__ __forceinline__ bool scale_coeff_fp(const CtxConst* K, const uint64_t
         if (j < (int)LB) {
             const uint32_t jj = L + j;
             const double b = K->pd[jj], binv = K->pinv[jj];
-            double acc = fmulmod(u52_to_double(x[jj * xs]), K->kb1d[j], b, binv) +
-                         fmulmod(v, K->fqpd[j], b, binv);
+            const double vf = v * K->fqpd[j];  // exact: |v| <= L <= 12, |fqpd| < 2^49
+            double acc = u52_to_double(x[jj * xs]) + (EX ? vf : fred(vf, b, binv));
 #pragma unroll
             for (int i = 0; i < NL; ++i)
                 if (i < (int)L) {
@@ -1758,7 +1771,8 @@ __device__ __forceinline__ bool scale_coeff_fp(const CtxConst* K, const uint64_t
     for (int i = 0; i < NL; ++i)
         if (i < (int)L) {
             const double p = K->pd[i], pinv = K->pinv[i];
-            double c = -fmulmod(v2, K->bq.Pmd[i], p, pinv);
+            const double vp = v2 * K->bq.Pmd[i];  // exact: |v2| <= 7, B mod q_i < 2^50
+            double c = EX ? -vp : -fred(vp, p, pinv);
 #pragma unroll
             for (int j = 0; j < NB; ++j)
                 if (j < (int)LB) {
@@ -1790,12 +1804,13 @@ __global__ void k_scale(const CtxConst* __restrict__ K, const uint64_t* __restri
     uint64_t cq[NL];
     bool amb;
     if constexpr (FP) amb = scale_coeff_fp<NL, NB, EX>(K, X + er * LL * N + c, N, cq);
-    else amb = scale_coeff<NL, NB>(K, X + er * LL * N + c, N, cq, false);
+    else amb = scale_coeff<NL, NB, false>(K, X + er * LL * N + c, N, cq, false);
     if (amb) fix[atomicAdd(fixcnt, 1u)] = gid;
     scale_store<NL>(K, cq, out, er, c);
 }
 
-template <int NL, int NB>
+// PRE: X as the fp64 tensor transform leaves it (rows already multiplied by their first constants).
+template <int NL, int NB, bool PRE>
 __global__ void k_scale_fix(const CtxConst* __restrict__ K, const uint64_t* __restrict__ X, uint64_t* __restrict__ out,
                             uint64_t* fix, uint32_t* fixcnt) {
     const uint32_t N = K->N, LL = K->LL;
@@ -1804,7 +1819,7 @@ __global__ void k_scale_fix(const CtxConst* __restrict__ K, const uint64_t* __re
         const size_t gid = fix[f];
         const size_t c = gid & (N - 1), er = gid >> K->logN;
         uint64_t cq[NL];
-        scale_coeff<NL, NB>(K, X + er * LL * N + c, N, cq, true);
+        scale_coeff<NL, NB, PRE>(K, X + er * LL * N + c, N, cq, true);
         scale_store<NL>(K, cq, out, er, c);
     }
     __syncthreads();
@@ -1821,15 +1836,20 @@ void launch_scale(const Launch& lc, const uint64_t* X, uint64_t* out, uint32_t E
     else                                                                                                      \
         hipLaunchKernelGGL((k_scale<NLV, NBV, false>), dim3(nb), dim3(EW_THREADS), 0, lc.stream, lc.K, X, out, E, \
                            lc.fix, lc.fixcnt);                                                                \
-    hipLaunchKernelGGL((k_scale_fix<NLV, NBV>), dim3(1), dim3(256), 0, lc.stream, lc.K, X, out, lc.fix, lc.fixcnt);
+    if (lc.fp)                                                                                                \
+        hipLaunchKernelGGL((k_scale_fix<NLV, NBV, true>), dim3(1), dim3(256), 0, lc.stream, lc.K, X, out, lc.fix, \
+                           lc.fixcnt);                                                                        \
+    else                                                                                                      \
+        hipLaunchKernelGGL((k_scale_fix<NLV, NBV, false>), dim3(1), dim3(256), 0, lc.stream, lc.K, X, out, lc.fix, \
+                           lc.fixcnt);
     if (lc.fp && lc.L == 5 && lc.LB == 5) {  // the N = 8192 parameter sets
         hipLaunchKernelGGL((k_scale<5, 5, true, true>), dim3(nb), dim3(EW_THREADS), 0, lc.stream, lc.K, X, out, E,
                            lc.fix, lc.fixcnt);
-        hipLaunchKernelGGL((k_scale_fix<8, 9>), dim3(1), dim3(256), 0, lc.stream, lc.K, X, out, lc.fix, lc.fixcnt);
+        hipLaunchKernelGGL((k_scale_fix<8, 9, true>), dim3(1), dim3(256), 0, lc.stream, lc.K, X, out, lc.fix, lc.fixcnt);
     } else if (lc.fp && lc.L == 3 && lc.LB == 3) {  // N = 4096, three 36-bit primes
         hipLaunchKernelGGL((k_scale<3, 3, true, true>), dim3(nb), dim3(EW_THREADS), 0, lc.stream, lc.K, X, out, E,
                            lc.fix, lc.fixcnt);
-        hipLaunchKernelGGL((k_scale_fix<4, 5>), dim3(1), dim3(256), 0, lc.stream, lc.K, X, out, lc.fix, lc.fixcnt);
+        hipLaunchKernelGGL((k_scale_fix<4, 5, true>), dim3(1), dim3(256), 0, lc.stream, lc.K, X, out, lc.fix, lc.fixcnt);
     } else if (lc.L <= 4 && lc.LB <= 5) {
         CW_SCALE(4, 5)
     } else if (lc.L <= 8 && lc.LB <= 9) {

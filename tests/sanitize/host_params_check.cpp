@@ -27,7 +27,7 @@ int main() {
             std::vector<uint64_t> tw;
             host::build_twiddles(tw, all, c.N);
             std::vector<double> twf;
-            host::build_twiddles_fp(twf, tw, all, c.N);
+            host::build_twiddles_fp(twf, tw, all, c.N, K);
             for (uint32_t keep = 1; keep <= c.q.size(); ++keep) {
                 static SwitchConst S;
                 host::build_switch(S, c.q, keep);
