@@ -123,11 +123,20 @@ __device__ __noinline__ uint32_t conv_round_exact(const ConvTable& T, const uint
     return c + 1;  // 2V = (2c+1)P is impossible for odd P
 }
 
-// out_j = sum_i y_i [(P/p_i) mod r_j] - v [P mod r_j]   (mod r_j), for j < T.nout
+// out_j = sum_i y_i [(P/p_i) mod r_j] - v [P mod r_j]   (mod r_j), for j < T.nout.  A lazy table
+// (r_j < 2^59) adds the products in [0, 2 r_j) and r_j - [v P]_{r_j} in (0, r_j], below
+// (2 nin + 1) r_j < 2^64, and reduces once; otherwise every product and sum is reduced.
 template <int NI>
 __device__ __forceinline__ uint64_t conv_out(const ConvTable& T, const uint64_t* y, uint32_t nin, uint32_t v,
                                              uint32_t j) {
     const uint64_t r = T.pout[j];
+    if (T.lazy) {
+        uint64_t acc = r - mul_shoup((uint64_t)v, T.Pm[j], T.Pmq[j], r);
+#pragma unroll
+        for (int i = 0; i < NI; ++i)
+            if (i < (int)nin) acc += mul_shoup_lazy(y[i], T.M[i][j], T.Mq[i][j], r);
+        return reduce64(acc, r, T.r1[j]);
+    }
     uint64_t acc = 0;
 #pragma unroll
     for (int i = 0; i < NI; ++i)

@@ -20,19 +20,26 @@ constexpr int MAX_W = 14;            // 64-bit words of a basis product, plus tw
 //   y_i = [x_i (P/p_i)^{-1}]_{p_i} (the caller may fold a factor into this constant),
 //   v   = round(sum_i y_i / p_i)   (fraction sum in 0.64 fixed point, exact fallback near 1/2),
 //   [x]_centred mod r_j = sum_i y_i [(P/p_i) mod r_j] - v [P mod r_j].
+// lazy: every output prime lies below CONV_LAZY_BOUND, so conv_out may add the nin + 1 products of
+// [0, 2 r_j) each and reduce the sum once (below (2 nin + 1) 2^59 < 2^64 for nin <= MAX_CONV).
 struct ConvTable {
-    uint32_t nin, nout, W, pad;
+    uint32_t nin, nout, W, lazy;
     uint64_t pin[MAX_CONV];
     uint64_t om_hi[MAX_CONV], om_lo[MAX_CONV];   // floor(2^128 / p_i) = om_hi 2^64 + om_lo
     uint64_t pout[MAX_CONV];
     uint64_t M[MAX_CONV][MAX_CONV];              // (P/p_i) mod r_j
     uint64_t Mq[MAX_CONV][MAX_CONV];             // Shoup companions
     uint64_t Pm[MAX_CONV], Pmq[MAX_CONV];        // P mod r_j
+    uint64_t r1[MAX_CONV];                       // floor(2^64 / r_j)
     double Md[MAX_CONV][MAX_CONV];               // (P/p_i) mod r_j as doubles (fp64 path)
     double Pmd[MAX_CONV];                        // P mod r_j as doubles
     uint64_t Pw[MAX_W];                          // P, little-endian words
     uint64_t Phat[MAX_CONV][MAX_W];              // P / p_i
 };
+
+constexpr uint64_t CONV_LAZY_BOUND = 1ull << 59;
+static_assert((2 * MAX_CONV + 1) * (CONV_LAZY_BOUND >> 32) < (1ull << 32), "lazy conversion sums fit 64 bits");
+// The integer path draws its auxiliary primes below CONV_LAZY_BOUND, so its conversions into B are lazy.
 
 // Primes below this bound may use the fp64 transform (see kernels.hip); the exactness argument
 // needs every intermediate integer below 2^53.

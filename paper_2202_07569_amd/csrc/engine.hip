@@ -367,7 +367,10 @@ extern "C" int pir_setup(const pir_params* params, pir_ctx** out) {
     // fp64 transforms need every prime below 2^50; then the auxiliary primes are chosen below 2^50
     bool fp = params->N <= 8192;
     for (uint64_t x : q) fp = fp && x < cw::FP_PRIME_BOUND;
-    std::vector<uint64_t> B = cw::host::aux_primes(params->N, q, params->t, fp ? cw::FP_PRIME_BOUND : (1ull << 61));
+    // (on the integer path below 2^59, where the conversions into B reduce lazily, unless that takes
+    // more than MAX_LB primes; then below 2^61)
+    std::vector<uint64_t> B = cw::host::aux_primes(params->N, q, params->t, fp ? cw::FP_PRIME_BOUND : cw::CONV_LAZY_BOUND);
+    if (!fp && B.size() > (size_t)cw::MAX_LB) B = cw::host::aux_primes(params->N, q, params->t, 1ull << 61);
     if (B.size() > (size_t)cw::MAX_LB) return fail(PIR_E_UNSUPPORTED, "auxiliary basis too large");
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) return fail(PIR_E_DEVICE, "no HIP device");

@@ -142,8 +142,11 @@ static void build_conv(ConvTable& T, const std::vector<uint64_t>& in, const std:
             T.Md[i][j] = (double)T.M[i][j];
         }
     }
+    T.lazy = 1;
     for (size_t j = 0; j < out.size(); ++j) {
         T.pout[j] = out[j];
+        T.r1[j] = (uint64_t)(((u128)1 << 64) / out[j]);
+        if (out[j] >= CONV_LAZY_BOUND) T.lazy = 0;
         T.Pm[j] = mw_mod(P, out[j]);
         T.Pmq[j] = shoup(T.Pm[j], out[j]);
         T.Pmd[j] = (double)T.Pm[j];
