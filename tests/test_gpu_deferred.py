@@ -7,7 +7,7 @@ leaves per element).  The answers must be bit-identical to relinearizing every s
 and to the oracle's, for every shape the deferred path takes: k = 2 and k = 4 trees, one, two,
 three and four plaintexts per element (row pairs for s = 1, single rows with payload pairs above),
 ragged chunks, several queries per launch, the tiny, mid and wide prime sets on the fp64
-transforms, and the keyword parameters and 52-55-bit primes on the integer transforms.
+transforms, and the keyword parameters (s = 1, 2, 3) and 52-55-bit primes on the integer transforms.
 """
 import numpy as np
 import pytest
@@ -60,8 +60,11 @@ CASES = {
     "mid-k4-s3": datagen.Config("mid-k4-s3", 8192, datagen.Q_N8192, 65537, 4, 9, 40, 3, 72),
     # k = 3 (depth 2) needs the mid modulus for the answer to decrypt (tiny's 108 bits run out)
     "mid-k3-s4": datagen.Config("mid-k3-s4", 8192, datagen.Q_N8192, 65537, 3, 8, 30, 4, 73),
-    # keyword parameters: N = 16384, eight 54/55-bit primes, integer transforms, s = 2
+    # keyword parameters: N = 16384, eight 54/55-bit primes, integer transforms: s = 2 (single rows
+    # with payload pairs), s = 1 (row pairs) and s = 3 (a payload pair, then a single payload row)
     "kw-k4-s2": datagen.Config("kw-k4-s2", 16384, datagen.Q_N16384, 65537, 4, 12, 24, 2, 75),
+    "kw-k2-s1": datagen.Config("kw-k2-s1", 16384, datagen.Q_N16384, 65537, 2, 12, 20, 1, 76),
+    "kw-k2-s3": datagen.Config("kw-k2-s3", 16384, datagen.Q_N16384, 65537, 2, 12, 18, 3, 77),
 }
 
 
