@@ -887,8 +887,9 @@ __global__ __launch_bounds__(Sh::T, Sh::LOGN == 13 ? 8 : 1) void k_ntt_inv_tenso
     const uint32_t pi = row.prime(g);
     // X leaves without the transform's factor N^-1: the scale kernels, its only readers, take it
     // with their first constants (tqinv, kb1), which the fp64 transform multiplies in at its first
-    // stage (X row k holds [f_k x]_{p_k}, f = K->foldd).  The tensor products enter below 1.4 p, so
-    // the inverse transform takes a lazy schedule (rows modulo primes below 2^44 almost unreduced).
+    // stage (X row k holds [f_k x]_{p_k}, f = K->foldd, as centred doubles).  The tensor products
+    // enter below 1.4 p, so the inverse transform takes a lazy schedule (rows modulo primes below
+    // 2^44 almost unreduced).
     if constexpr (FP) {
         double v[Sh::EPT];
         row.load_f(g, tid, v);
@@ -896,9 +897,8 @@ __global__ __launch_bounds__(Sh::T, Sh::LOGN == 13 ? 8 : 1) void k_ntt_inv_tenso
         constexpr int LZQ = inv_lazy_exact<Sh>(2) ? 2 : LZB;  // would reach 11.2 p, beyond 8 p below 2^50
         if (K->pd[pi] < 0x1p44) ntt_inv_f<Sh, false, LZQ, true>(v, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
         else ntt_inv_f<Sh, false, LZB, true>(v, sm, tid, tw_row(tw, twf, pi, Sh::N), K, pi);
-        const double p = K->pd[pi];
 #pragma unroll
-        for (int u = 0; u < Sh::EPT; ++u) row.store(g, tid, u, fp_to_residue(v[u], p));
+        for (int u = 0; u < Sh::EPT; ++u) row.store(g, tid, u, (uint64_t)__double_as_longlong(v[u]));  // centred
     } else {
         uint64_t a[Sh::EPT];
         row.load(g, tid, a);
@@ -1694,8 +1694,8 @@ void launch_operand_q_rows(const Launch& lc, const uint64_t* in, uint64_t* out, 
 // ---------------------------------------------------------------------------------------------
 // Exact scale-and-round of a coefficient-form tensor product X over Q u B:
 //   r = [t X]_q (centred, exact Q -> B), y = (t X - r) / q in B, c = y (exact centred B -> Q).
-// Output: coefficient form [E][3][L][N].  PRE: X row k already holds [f_k X]_{p_k} with the first
-// constants f (tqinv for Q, kb1 for B), as the fp64 tensor transform leaves it.
+// Output: coefficient form [E][3][L][N].  PRE: X as the fp64 tensor transform leaves it: row k holds
+// [f_k X]_{p_k} with the first constants f (tqinv for Q, kb1 for B), as centred doubles.
 // ---------------------------------------------------------------------------------------------
 template <int NL, int NB, bool PRE>
 __device__ __forceinline__ bool scale_coeff(const CtxConst* K, const uint64_t* x, size_t xs, uint64_t* cq, bool exact) {
@@ -1703,7 +1703,9 @@ __device__ __forceinline__ bool scale_coeff(const CtxConst* K, const uint64_t* x
     uint64_t y[NL];
 #pragma unroll
     for (int i = 0; i < NL; ++i)
-        if (i < (int)L) y[i] = PRE ? x[i * xs] : mul_shoup(x[i * xs], K->tqinv[i], K->tqinvq[i], K->p[i]);
+        if (i < (int)L)
+            y[i] = PRE ? fp_to_residue(__longlong_as_double((long long)x[i * xs]), K->pd[i])
+                       : mul_shoup(x[i * xs], K->tqinv[i], K->tqinvq[i], K->p[i]);
     bool amb = false;
     const uint32_t v = exact ? conv_round_exact(K->qb, y) : conv_round_fast<NL>(K->qb, y, L, amb);
     uint64_t z[NB];
@@ -1712,8 +1714,9 @@ __device__ __forceinline__ bool scale_coeff(const CtxConst* K, const uint64_t* x
         if (j < (int)LB) {
             const uint64_t b = K->p[L + j];
             const uint64_t rb = conv_out<NL>(K->qb, y, L, v, j);
-            const uint64_t xb = x[(L + j) * xs];
-            z[j] = sub_mod(PRE ? xb : mul_shoup(xb, K->kb1[j], K->kb1q[j], b), mul_shoup(rb, K->kb2[j], K->kb2q[j], b), b);
+            const uint64_t xb = PRE ? fp_to_residue(__longlong_as_double((long long)x[(L + j) * xs]), K->pd[L + j])
+                                    : mul_shoup(x[(L + j) * xs], K->kb1[j], K->kb1q[j], b);
+            z[j] = sub_mod(xb, mul_shoup(rb, K->kb2[j], K->kb2q[j], b), b);
         }
     const uint32_t v2 = exact ? conv_round_exact(K->bq, z) : conv_round_fast<NB>(K->bq, z, LB, amb);
 #pragma unroll
@@ -1723,15 +1726,16 @@ __device__ __forceinline__ bool scale_coeff(const CtxConst* K, const uint64_t* x
 }
 
 // fp64 form (every prime below 2^50; X as the fp64 tensor transform leaves it, PRE above): the same
-// conversions on doubles.  y_i in [0, q_i), so S = sum y_i / q_i lies in [0, L) and v in [0, L].  The
-// rounding decisions v, v2 come from double sums whose error is below 2^-45; a sum within 2^-40 of a
-// half is reported as ambiguous and the exact integer form redoes the coefficient.  The key constant
-// kb2 is folded into the Q -> B products (fqbd, fqpd), so z_j is the input [kb1 x_j] (below b), L
-// products (each below (1/2 + 3 q_i 2^-53) b <= 0.875 b in magnitude) and v fqpd, an exact product
-// (|fqpd| < b/2): for L <= 5 the sum stays below (1 + 1.375 L) b < 2^53 (b < 2^50) and is reduced
-// once.  The outputs take -v2 [B]_{q_i}, exact as well (|v2| <= (LB + 1)/2, B mod q_i below q_i),
-// and LB products below 0.69 q_i (|z_j| <= b/2 < 2^49): for LB <= 6 below 8 q_i.  The general form
-// (EX = false) reduces the two exact products and every few sums.
+// conversions on doubles.  |y_i| <= q_i / 2 (plus 2^-52 of it), so |S| = |sum y_i / q_i| <= L/2 and
+// |v| <= (L + 1)/2.  The rounding decisions v, v2 come from double sums whose error is below 2^-45;
+// a sum within 2^-40 of a half is reported as ambiguous and the exact integer form redoes the
+// coefficient.  The key constant kb2 is folded into the Q -> B products (fqbd, fqpd), so z_j is the
+// input [kb1 x_j] (|.| <= b/2), L products (each below (1/2 + 3 |y_i| 2^-53) b <= 0.69 b in
+// magnitude) and v fqpd, an exact product (|fqpd| < b/2): for L <= 5 the sum stays below 6 b < 2^53
+// (b < 2^50) and is reduced once.  The outputs take -v2 [B]_{q_i}, exact as well
+// (|v2| <= (LB + 1)/2, B mod q_i below q_i), and LB products below 0.69 q_i (|z_j| <= b/2 < 2^49):
+// for LB <= 6 below 8 q_i.  The general form (EX = false) reduces the two exact products and every
+// few sums.
 #pragma clang fp contract(off)
 template <int NL, int NB, bool EX>
 __device__ __forceinline__ bool scale_coeff_fp(const CtxConst* K, const uint64_t* x, size_t xs, uint64_t* cq) {
@@ -1742,7 +1746,7 @@ __device__ __forceinline__ bool scale_coeff_fp(const CtxConst* K, const uint64_t
 #pragma unroll
     for (int i = 0; i < NL; ++i)
         if (i < (int)L) {
-            y[i] = u52_to_double(x[i * xs]);
+            y[i] = __longlong_as_double((long long)x[i * xs]);
             S += y[i] * K->pinv[i];
         }
     const double v = __builtin_rint(S);
@@ -1754,8 +1758,8 @@ __device__ __forceinline__ bool scale_coeff_fp(const CtxConst* K, const uint64_t
         if (j < (int)LB) {
             const uint32_t jj = L + j;
             const double b = K->pd[jj], binv = K->pinv[jj];
-            const double vf = v * K->fqpd[j];  // exact: |v| <= L <= 12, |fqpd| < 2^49
-            double acc = u52_to_double(x[jj * xs]) + (EX ? vf : fred(vf, b, binv));
+            const double vf = v * K->fqpd[j];  // exact: |v| <= 7, |fqpd| < 2^49
+            double acc = __longlong_as_double((long long)x[jj * xs]) + (EX ? vf : fred(vf, b, binv));
 #pragma unroll
             for (int i = 0; i < NL; ++i)
                 if (i < (int)L) {
@@ -1809,7 +1813,7 @@ __global__ void k_scale(const CtxConst* __restrict__ K, const uint64_t* __restri
     scale_store<NL>(K, cq, out, er, c);
 }
 
-// PRE: X as the fp64 tensor transform leaves it (rows already multiplied by their first constants).
+// PRE: X as the fp64 tensor transform leaves it (rows multiplied by their first constants, centred doubles).
 template <int NL, int NB, bool PRE>
 __global__ void k_scale_fix(const CtxConst* __restrict__ K, const uint64_t* __restrict__ X, uint64_t* __restrict__ out,
                             uint64_t* fix, uint32_t* fixcnt) {
