@@ -803,14 +803,22 @@ struct Bufs {
 // LDS; at N = 4096 two fit), so a launch takes ceil(workgroups / resident) rounds of one
 // workgroup's time, which grows with the slice (plus about one element's worth of set-up: the
 // twiddle copy, the first row, the sums written out).  The slice minimises that product; among
-// equal costs the longer slice writes fewer partial sums.
+// equal costs the longer slice writes fewer partial sums.  The workgroups of slice g run on XCD
+// g mod 8 (xcd_split), so on the integer path the rounds are those of the busiest XCD, which holds
+// ceil(slices / 8) slices on an eighth of the compute units (at the keyword parameters this took
+// the root products from 6.3 to 3.2 ms per launch: slice 32 instead of 64, whose four slices left
+// half of the XCDs idle).  The fp64 kernel counts all compute units together: its one-query
+// launches move about 4 TB/s, and there fewer, longer slices measured faster than balanced XCDs.
 static uint32_t root_slice(const pir_ctx* ctx, uint32_t E, uint32_t nq, uint32_t units) {
     const uint64_t resident = (uint64_t)std::max<uint32_t>(ctx->cus, 1) * (ctx->fp && ctx->N == 4096 ? 2 : 1);
     const uint64_t per = (uint64_t)nq * units;
+    const bool by_xcd = !ctx->fp;
+    const uint64_t slots = by_xcd ? std::max<uint64_t>(1, resident / 8) : resident;
     uint64_t best = 1, best_cost = ~0ull;
     for (uint64_t slice = 1; slice <= 64; ++slice) {
-        const uint64_t groups = ((uint64_t)std::max<uint32_t>(E, 1) + slice - 1) / slice * per;
-        const uint64_t cost = (groups + resident - 1) / resident * (slice + 1);
+        const uint64_t slices = ((uint64_t)std::max<uint32_t>(E, 1) + slice - 1) / slice;
+        const uint64_t groups = (by_xcd ? (slices + 7) / 8 : slices) * per;
+        const uint64_t cost = (groups + slots - 1) / slots * (slice + 1);
         if (cost <= best_cost) {
             best_cost = cost;
             best = slice;
