@@ -807,8 +807,10 @@ struct Bufs {
 // g mod 8 (xcd_split), so on the integer path the rounds are those of the busiest XCD, which holds
 // ceil(slices / 8) slices on an eighth of the compute units (at the keyword parameters this took
 // the root products from 6.3 to 3.2 ms per launch: slice 32 instead of 64, whose four slices left
-// half of the XCDs idle).  The fp64 kernel counts all compute units together: its one-query
-// launches move about 4 TB/s, and there fewer, longer slices measured faster than balanced XCDs.
+// half of the XCDs idle).  The fp64 kernel counts all compute units together: on the one-query
+// launches of the mid parameters (1024 elements, 11 units, about 4 TB/s) that choice (slice 45)
+// measured 41.7 ms per answer against 41.9, 46.1 and 47.4 ms for slices 23, 64 and 32, and 42.4 ms
+// for the busiest-XCD choice (16).
 static uint32_t root_slice(const pir_ctx* ctx, uint32_t E, uint32_t nq, uint32_t units) {
     const uint64_t resident = (uint64_t)std::max<uint32_t>(ctx->cus, 1) * (ctx->fp && ctx->N == 4096 ? 2 : 1);
     const uint64_t per = (uint64_t)nq * units;
