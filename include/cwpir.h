@@ -334,7 +334,10 @@ int pir_set_schedule(pir_ctx* ctx, const pir_schedule* schedule);
 int pir_autotune(pir_ctx* ctx, uint32_t batch, uint32_t k, uint32_t s, pir_schedule* records, uint32_t max_records,
                  pir_schedule* best);
 
-/* Introspection. */
+/* Introspection.  pir_ctx_aux_primes: the auxiliary basis B of the exact scale-and-round (the
+ * largest primes = 1 mod 2N below 2^50 on the fp64 path, below 2^59 on the integer path (below 2^61
+ * when 2^59 would take more than 13), until prod B > 4 t N q); returns their count and, when
+ * out_primes is not NULL, writes them there. */
 uint32_t pir_ctx_aux_primes(const pir_ctx* ctx, uint64_t* out_primes /* may be NULL */);
 uint64_t pir_ctx_device_bytes(const pir_ctx* ctx);       /* bytes the library holds on the device */
 uint64_t pir_db_pair_count(const pir_db* db);            /* distinct inner tree nodes (k >= 3)    */
